@@ -1,0 +1,263 @@
+/*
+ * ms.h -- C ABI of the MI355X multilevel elastodynamics timestep library.
+ *
+ * The library advances a tetrahedral mesh by implicit Euler timesteps,
+ * x^{t+1} = argmin_x E(x) with the incremental potential of Eq. (IP)
+ * (Sec. 3.1): E = 1/2 ||x - x~||_M^2 + h^2 (Psi + B), x~ = x^t + h v^t,
+ * v^{t+1} = (x^{t+1} - x^t) / h.  Each timestep is a Newton solve
+ * (H d = -g, Sec. 3.1) whose linear systems are solved by preconditioned
+ * conjugate gradient; the preconditioner is either 3x3 block-Jacobi or the
+ * two-level preconditioner built from the sparse material-aware basis U of
+ * Sec. 3.3-3.5 (restriction U^T r, a dense Cholesky solve with U^T H U,
+ * prolongation U e).  The paper's own three-level inexact Newton solve
+ * (Alg. 1 and 2) is available as a mode.
+ *
+ * Conventions for every call below:
+ *   - All functions return ms_status; MS_OK (0) is success.  On failure the
+ *     context keeps a message retrievable with ms_last_error().
+ *   - Unless stated otherwise, array arguments are HOST pointers that are
+ *     read (or written) during the call only; the caller keeps ownership.
+ *     Vectors of points are row-major [n][3] doubles.
+ *   - Device memory is obtained through ms_device.alloc (for instance a
+ *     PyTorch caching allocator) or hipMalloc when alloc is NULL, and all
+ *     device work is enqueued on ms_device.hip_stream.  A context owns every
+ *     device buffer it allocates and releases it in ms_destroy().
+ *   - A context may be used by one host thread at a time.
+ *   - Call order: ms_create -> ms_upload_mesh -> ms_upload_material ->
+ *     (ms_set_gravity, ms_set_dirichlet, ms_add_halfspace in any order) ->
+ *     ms_set_state -> (ms_build_basis | ms_set_basis, optional) -> ms_step*.
+ *     A call made before its prerequisites returns MS_E_ORDER.
+ */
+#ifndef MS_H
+#define MS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ms_ctx ms_ctx;
+
+typedef enum {
+  MS_OK = 0,
+  MS_E_ARG = -1,        /* invalid argument (null pointer, size, index out of range) */
+  MS_E_MESH = -2,       /* degenerate or inverted rest tetrahedron                    */
+  MS_E_ORDER = -3,      /* call made before its prerequisites                          */
+  MS_E_DEVICE = -4,     /* a HIP call failed                                           */
+  MS_E_NOMEM = -5,      /* device allocation failed                                    */
+  MS_E_NOCONV = -6,     /* Newton did not converge in max_newton iterations            */
+  MS_E_LINESEARCH = -7, /* no energy decrease within the backtracking budget          */
+  MS_E_NONFINITE = -8   /* NaN or Inf in an input or in the iterate                    */
+} ms_status;
+
+/* Device, stream and allocator the context runs on.  alloc/free may be NULL
+ * (then hipMalloc/hipFree are used).  hip_stream is a hipStream_t (NULL =
+ * the null stream). */
+typedef struct {
+  int device;
+  void* hip_stream;
+  void* (*alloc)(size_t bytes, void* user);
+  void (*free)(void* ptr, void* user);
+  void* user;
+} ms_device;
+
+typedef enum { MS_PREC_FP64 = 0, MS_PREC_MIXED = 1 } ms_precision;
+typedef enum { MS_PC_BLOCK_JACOBI = 0, MS_PC_TWO_LEVEL = 1 } ms_preconditioner;
+typedef enum { MS_MODE_PLAIN = 0, MS_MODE_PAPER = 1 } ms_mode;
+
+/* Parameters of one timestep solve.  ms_solver_defaults() fills them. */
+typedef struct {
+  int32_t mode;            /* ms_mode                                                   */
+  int32_t precision;       /* ms_precision: FP64, or FP32 Hessian/SpMV/preconditioner
+                              with FP64 gradient, residual replacement and line search */
+  int32_t preconditioner;  /* ms_preconditioner (plain mode)                            */
+  int32_t max_newton;      /* Newton iteration cap (MS_E_NOCONV beyond it)              */
+  int32_t max_pcg;         /* PCG iteration cap per Newton iteration                   */
+  double newton_tol;       /* plain mode: stop when a full step has
+                              ||d||_2 <= newton_tol * max(||x - x^t||_2, abs_floor)     */
+  double abs_floor;        /* absolute displacement floor of that test (m)              */
+  double pcg_eta_max;      /* forcing term eta = min(eta_max, sqrt(||g||/||g_0||))       */
+  double pcg_eta_min;      /* lower bound of the forcing term                           */
+  int32_t replace_every;   /* mixed precision: FP64 true-residual recomputation period  */
+  int32_t max_backtracks;  /* line-search halvings before MS_E_LINESEARCH               */
+  int32_t exact_endgame;   /* 1: drop the PSD projection once steps are small           */
+  int32_t warm_start;      /* 1: use the learned coarse warm start if one is set        */
+  /* paper mode (Alg. 1 and 2) */
+  double paper_eps;        /* termination on mean per-vertex ||d_s,v|| / h  (m/s)       */
+  double subspace_rtol;    /* relative residual of the affine and subspace PCG solves   */
+  int32_t refine_iters;    /* fixed Jacobi-PCG iterations of the full-space refinement  */
+  int32_t lag_window;      /* step sizes averaged by the Hessian-lag trigger             */
+  double lag_threshold;    /* refresh the lagged elastic Hessian below this average     */
+  int32_t lag_min_gap;     /* at most one refresh every lag_min_gap iterations          */
+} ms_solver_params;
+
+/* Statistics of the last ms_step. */
+typedef struct {
+  int32_t newton_iters;
+  int32_t pcg_iters;          /* total over the step                                    */
+  int32_t max_pcg_iters;      /* largest single solve                                   */
+  int32_t backtracks;         /* total line-search halvings                             */
+  int32_t hessian_refreshes;  /* paper mode: lagged-Hessian recomputations              */
+  int32_t warm_start_used;    /* 1 if the learned prediction was accepted               */
+  double energy;              /* E at x^{t+1}                                            */
+  double last_dnorm;          /* ||d||_2 of the last Newton step                         */
+  double disp_norm;           /* ||x^{t+1} - x^t||_2                                     */
+  double min_alpha;           /* smallest accepted line-search step                      */
+  double time_ms;             /* host wall time of the step                              */
+} ms_step_stats;
+
+/* Parameters of the basis construction (Sec. 3.4-3.5).  ms_basis_defaults()
+ * fills them. */
+typedef struct {
+  int32_t n_handles;       /* target number of partitions / handles m               */
+  double oversample;       /* K-means starts with ceil(oversample * m) seeds          */
+  double jump_penalty;     /* stiffness factor on tets at material jumps (x softest)  */
+  double prune_ratio;      /* prune when median volume > prune_ratio * own volume    */
+  int32_t prune_every;     /* Lloyd iterations between pruning rounds                */
+  int32_t prune_n;         /* clusters removed per pruning round                     */
+  int32_t max_lloyd;       /* Lloyd iteration cap                                    */
+  int32_t lattice_seeding; /* 1: seeds on a fixed lattice, no pruning (stable handle
+                              indices across meshes of the same shape)              */
+  uint64_t seed;
+  int32_t n_threads;       /* host threads (0 = hardware concurrency)                */
+} ms_basis_params;
+
+void ms_solver_defaults(ms_solver_params* p);
+void ms_basis_defaults(ms_basis_params* p);
+
+/* Create a context on dev->device.  *out receives the context.
+ * Errors: MS_E_ARG (null), MS_E_DEVICE (device cannot be selected). */
+ms_status ms_create(const ms_device* dev, ms_ctx** out);
+
+/* Upload the reference mesh (Sec. 3.1: positions at n vertices, a simplicial
+ * tet mesh).  rest_xyz [n][3], tets [T][4] vertex indices with positive
+ * orientation (det[x1-x0, x2-x0, x3-x0] > 0).  Builds the block-sparse
+ * Hessian pattern and the atomic-free assembly maps.
+ * Errors: MS_E_ARG (index out of range, n or T < 1), MS_E_MESH (a rest tet
+ * with non-positive volume), MS_E_NONFINITE. */
+ms_status ms_upload_mesh(ms_ctx* c, int64_t n_verts, const double* rest_xyz, int64_t n_tets,
+                         const int32_t* tets);
+
+/* Per-tet Young's modulus E (Pa, > 0), Poisson ratio nu (in (-1, 0.5)) and
+ * density rho (kg/m^3, > 0), each [T].  The elastic energy is the stable
+ * Neo-Hookean density with mu = E/(2(1+nu)), lam' = E nu/((1+nu)(1-2nu)) + mu;
+ * masses are lumped, m_v = sum rho V / 4.  Errors: MS_E_ARG, MS_E_ORDER. */
+ms_status ms_upload_material(ms_ctx* c, const double* E, const double* nu, const double* rho);
+
+/* Gravity g[3] (m/s^2), entering E as -h^2 sum_v m_v g . x_v. */
+ms_status ms_set_gravity(ms_ctx* c, const double g[3]);
+
+/* Dirichlet conditions (Sec. 3.4.1): vertices verts[n] are set to
+ * target_xyz [n][3] at the start of every following step and their DOFs are
+ * eliminated.  May be called between steps (moving targets) with the same
+ * or a different vertex set (a different set invalidates a built basis:
+ * build it again).  n = 0 clears them.  Errors: MS_E_ARG, MS_E_ORDER. */
+ms_status ms_set_dirichlet(ms_ctx* c, int64_t n, const int32_t* verts, const double* target_xyz);
+
+/* A rigid half-space {y : normal . y >= offset} in contact with every
+ * vertex through the IPC log barrier b(d) = -(d - dhat)^2 ln(d/dhat) on
+ * d = normal . x - offset (Eq. IP, term B), scaled by kappa (N/m).  The line
+ * search keeps every vertex strictly inside the half-space.  normal need not
+ * be unit length (it is normalised).  At most one half-space. */
+ms_status ms_add_halfspace(ms_ctx* c, const double normal[3], double offset, double dhat, double kappa);
+
+/* Set positions x [n][3] and velocities v [n][3].  With a half-space every
+ * vertex must lie strictly inside it.  Errors: MS_E_NONFINITE, MS_E_ARG. */
+ms_status ms_set_state(ms_ctx* c, const double* x, const double* v);
+ms_status ms_get_state(const ms_ctx* c, double* x, double* v);
+
+/* Build the sparse geometry- and material-aware basis (Sec. 3.4-3.5) on the
+ * host: stiffness-weighted heat-geodesic K-means partitioning with jump
+ * penalty and pruning, local stiffness-weighted biharmonic solves on each
+ * partition's face-neighbour subdomain, clipping, partition of unity, and
+ * the Dirichlet-compatible variant when Dirichlet vertices exist.  Uploads
+ * the basis for the two-level preconditioner and paper mode.
+ * Errors: MS_E_ORDER (no mesh/material), MS_E_ARG. */
+ms_status ms_build_basis(ms_ctx* c, const ms_basis_params* p);
+
+/* Install an externally computed basis: m handles with origins [m][3]; for
+ * each vertex v the handles vhandle[vptr[v] .. vptr[v+1]) with weights vphi
+ * (the phi_i(x_v) of Eq. LBS).  nnz = vptr[n]. */
+ms_status ms_set_basis(ms_ctx* c, int32_t m, const double* origins, const int64_t* vptr,
+                       const int32_t* vhandle, const double* vphi);
+
+/* Query the installed basis: *m, *nnz; then, if the arrays are non-null,
+ * origins [m][3], vptr [n+1], vhandle [nnz], vphi [nnz], and part [T] (the
+ * partition of every tet, or -1 for a basis set by ms_set_basis). */
+ms_status ms_get_basis_size(const ms_ctx* c, int32_t* m, int64_t* nnz);
+ms_status ms_get_basis(const ms_ctx* c, double* origins, int64_t* vptr, int32_t* vhandle, double* vphi,
+                       int32_t* part);
+
+/* Advance one timestep of size dt (s) with parameters p (NULL = defaults);
+ * stats may be NULL.  Transactional: on any error x and v are unchanged.
+ * Errors: MS_E_ORDER, MS_E_NOCONV, MS_E_LINESEARCH, MS_E_NONFINITE,
+ * MS_E_DEVICE. */
+ms_status ms_step(ms_ctx* c, double dt, const ms_solver_params* p, ms_step_stats* stats);
+
+/* Coarse coordinates of the current state: q = (U^T M U)^{-1} U^T M (x - x_rest),
+ * [12 m] doubles (the handles of Eq. LBS).  Requires a basis. */
+ms_status ms_get_coarse(ms_ctx* c, double* q);
+
+/* ---- learned coarse warm start ------------------------------------------
+ * A 3-layer MLP in -> width -> width -> out with SiLU activations, BF16
+ * weights and FP32 accumulation, predicting the next coarse state from the
+ * last two (in = 2 * 12 m, out = 12 m).  Weights are row-major [out][in]
+ * FP32 on the host (rounded to BF16 on upload); mean/std standardise the
+ * input, out_scale rescales the output; the prediction is a residual over
+ * the constant-velocity extrapolation 2 q^t - q^{t-1}. */
+typedef struct {
+  int32_t in_dim, width, out_dim;
+  const float *W0, *b0, *W1, *b1, *W2, *b2;
+  const float *in_mean, *in_std, *out_scale;
+} ms_mlp_desc;
+ms_status ms_set_warmstart(ms_ctx* c, const ms_mlp_desc* d);
+
+/* ---- kernel-level entry points (parity checks and measurements) ---------
+ * ms_eval: at positions x [n][3] (host), with x~ = x^t + dt v^t from the
+ * current state, return the energy parts e4 = {K, h^2 Psi, h^2 G, h^2 B},
+ * the gradient grad [n][3] (Dirichlet DOFs NOT eliminated) and, if hess
+ * is non-null, the PSD-projected Hessian as BSR3 values [nnzb][3][3] in the
+ * pattern returned by ms_get_pattern.  prec selects the Hessian precision. */
+ms_status ms_get_pattern(const ms_ctx* c, int64_t* nnzb, int32_t* row_ptr, int32_t* col);
+ms_status ms_eval(ms_ctx* c, const double* x, double dt, int32_t prec, double* e4, double* grad,
+                  double* hess);
+
+/* Apply the preconditioner built for the Hessian of the last ms_eval
+ * (kind = ms_preconditioner) to r [n][3]; z [n][3].  Dirichlet DOFs of z
+ * are zero. */
+ms_status ms_apply_preconditioner(ms_ctx* c, int32_t kind, int32_t prec, const double* r, double* z);
+
+/* Coarse operator U^T H U (12m x 12m, row-major) of the last ms_eval. */
+ms_status ms_get_coarse_matrix(ms_ctx* c, double* A);
+
+/* ---- standalone sliced-BSR3 matrix for SpMV measurements ----------------
+ * A block-sparse matrix with 3x3 blocks given in BSR form (host row_ptr
+ * [n+1], col [nnzb], vals [nnzb][3][3] doubles) is converted into the
+ * library's device layout (64-row slices, component-major planes) in FP64
+ * (dtype 0) or FP32 (dtype 1).  ms_mat_spmv computes y = A x for DEVICE
+ * vectors x, y of 3n elements of that dtype on the matrix's stream. */
+typedef struct ms_mat ms_mat;
+ms_status ms_mat_create(const ms_device* dev, int64_t n, const int32_t* row_ptr, const int32_t* col,
+                        const double* vals, int32_t dtype, ms_mat** out);
+ms_status ms_mat_spmv(ms_mat* A, const void* x_dev, void* y_dev);
+/* Algorithmic bytes of one product (values, indices, x, y counted once). */
+double ms_mat_bytes(const ms_mat* A);
+void ms_mat_destroy(ms_mat* A);
+
+/* ---- batched scenes ------------------------------------------------------
+ * Advance several independent contexts (same device and stream) by one
+ * timestep each; the solver runs them as one block-diagonal system with
+ * per-scene reductions, masks and line searches. per_scene may be NULL.
+ * Results equal running ms_step on each context alone. */
+ms_status ms_batch_step(ms_ctx* const* scenes, int32_t n_scenes, double dt, const ms_solver_params* p,
+                        ms_step_stats* per_scene);
+
+const char* ms_last_error(const ms_ctx* c);
+void ms_destroy(ms_ctx* c);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MS_H */

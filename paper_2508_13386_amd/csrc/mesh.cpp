@@ -1,0 +1,157 @@
+// Host-side precompute for an uploaded tet mesh: rest shape matrices,
+// volumes, vertex-tet incidence, the block-sparse Hessian pattern in the
+// sliced BSR3 layout, and the gather lists that let the assembly kernels sum
+// element blocks into Hessian slots and element gradients into vertices
+// without atomics and in a fixed order (so results are bitwise reproducible).
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+#include "ms_internal.h"
+
+namespace ms {
+
+// Local pair index of the 10 stored element blocks (a <= b).
+static inline int pair_index(int a, int b) {
+  // (0,0)=0 (0,1)=1 (0,2)=2 (0,3)=3 (1,1)=4 (1,2)=5 (1,3)=6 (2,2)=7 (2,3)=8 (3,3)=9
+  static const int tbl[4][4] = {{0, 1, 2, 3}, {1, 4, 5, 6}, {2, 5, 7, 8}, {3, 6, 8, 9}};
+  return tbl[a][b];
+}
+
+ms_status build_mesh(ms_ctx* c) {
+  const int64_t n = c->n, T = c->T;
+  c->h_vol.assign(T, 0.0);
+  c->h_Dminv.assign(9 * T, 0.0);
+  for (int64_t t = 0; t < T; ++t) {
+    const int32_t* v = &c->h_tets[4 * t];
+    double Dm[3][3];
+    for (int col = 0; col < 3; ++col)
+      for (int i = 0; i < 3; ++i) Dm[i][col] = c->h_rest[3 * v[col + 1] + i] - c->h_rest[3 * v[0] + i];
+    double det = Dm[0][0] * (Dm[1][1] * Dm[2][2] - Dm[1][2] * Dm[2][1]) -
+                 Dm[0][1] * (Dm[1][0] * Dm[2][2] - Dm[1][2] * Dm[2][0]) +
+                 Dm[0][2] * (Dm[1][0] * Dm[2][1] - Dm[1][1] * Dm[2][0]);
+    if (!(det > 0.0) || !std::isfinite(det))
+      return fail(c, MS_E_MESH, "rest tet " + std::to_string(t) + " has non-positive volume");
+    double inv = 1.0 / det;
+    double* m = &c->h_Dminv[9 * t];
+    m[0] = (Dm[1][1] * Dm[2][2] - Dm[1][2] * Dm[2][1]) * inv;
+    m[1] = (Dm[0][2] * Dm[2][1] - Dm[0][1] * Dm[2][2]) * inv;
+    m[2] = (Dm[0][1] * Dm[1][2] - Dm[0][2] * Dm[1][1]) * inv;
+    m[3] = (Dm[1][2] * Dm[2][0] - Dm[1][0] * Dm[2][2]) * inv;
+    m[4] = (Dm[0][0] * Dm[2][2] - Dm[0][2] * Dm[2][0]) * inv;
+    m[5] = (Dm[0][2] * Dm[1][0] - Dm[0][0] * Dm[1][2]) * inv;
+    m[6] = (Dm[1][0] * Dm[2][1] - Dm[1][1] * Dm[2][0]) * inv;
+    m[7] = (Dm[0][1] * Dm[2][0] - Dm[0][0] * Dm[2][1]) * inv;
+    m[8] = (Dm[0][0] * Dm[1][1] - Dm[0][1] * Dm[1][0]) * inv;
+    c->h_vol[t] = det / 6.0;
+  }
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  for (int64_t v = 0; v < n; ++v)
+    for (int i = 0; i < 3; ++i) {
+      lo[i] = std::min(lo[i], c->h_rest[3 * v + i]);
+      hi[i] = std::max(hi[i], c->h_rest[3 * v + i]);
+    }
+  c->bbox_diag = std::sqrt((hi[0] - lo[0]) * (hi[0] - lo[0]) + (hi[1] - lo[1]) * (hi[1] - lo[1]) +
+                           (hi[2] - lo[2]) * (hi[2] - lo[2]));
+  // vertex -> (tet, local) incidence, ordered by tet index
+  std::vector<int32_t> vt_ptr(n + 1, 0), vt_code(4 * T);
+  for (int64_t t = 0; t < T; ++t)
+    for (int a = 0; a < 4; ++a) vt_ptr[c->h_tets[4 * t + a] + 1]++;
+  for (int64_t v = 0; v < n; ++v) vt_ptr[v + 1] += vt_ptr[v];
+  {
+    std::vector<int32_t> fill(vt_ptr.begin(), vt_ptr.end() - 1);
+    for (int64_t t = 0; t < T; ++t)
+      for (int a = 0; a < 4; ++a) vt_code[fill[c->h_tets[4 * t + a]]++] = int32_t(4 * t + a);
+  }
+  ms_status s;
+  if ((s = upload(c, &c->d_rest, c->h_rest.data(), 3 * n))) return s;
+  if ((s = upload(c, &c->d_tets, c->h_tets.data(), 4 * T))) return s;
+  if ((s = upload(c, &c->d_Dminv, c->h_Dminv.data(), 9 * T))) return s;
+  if ((s = upload(c, &c->d_vol, c->h_vol.data(), T))) return s;
+  if ((s = upload(c, &c->d_vt_ptr, vt_ptr.data(), n + 1))) return s;
+  if ((s = upload(c, &c->d_vt_code, vt_code.data(), 4 * T))) return s;
+  return build_pattern(c);
+}
+
+ms_status build_pattern(ms_ctx* c) {
+  const int64_t n = c->n, T = c->T;
+  Pattern& P = c->pat;
+  P.n = n;
+  // adjacency (including self), sorted per row
+  std::vector<std::vector<int32_t>> adj(n);
+  for (int64_t v = 0; v < n; ++v) adj[v].push_back(int32_t(v));
+  for (int64_t t = 0; t < T; ++t)
+    for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < 4; ++b)
+        if (a != b) adj[c->h_tets[4 * t + a]].push_back(c->h_tets[4 * t + b]);
+  P.h_row_ptr.assign(n + 1, 0);
+  for (int64_t v = 0; v < n; ++v) {
+    auto& a = adj[v];
+    std::sort(a.begin(), a.end());
+    a.erase(std::unique(a.begin(), a.end()), a.end());
+    P.h_row_ptr[v + 1] = P.h_row_ptr[v] + int32_t(a.size());
+  }
+  P.nnzb = P.h_row_ptr[n];
+  P.h_col.resize(P.nnzb);
+  for (int64_t v = 0; v < n; ++v) std::copy(adj[v].begin(), adj[v].end(), P.h_col.begin() + P.h_row_ptr[v]);
+  // slices of 64 rows
+  P.nslices = (n + kSlice - 1) / kSlice;
+  P.h_slice_base.assign(P.nslices + 1, 0);
+  for (int64_t s = 0; s < P.nslices; ++s) {
+    int32_t w = 0;
+    for (int64_t r = s * kSlice; r < std::min<int64_t>(n, (s + 1) * kSlice); ++r)
+      w = std::max(w, P.h_row_ptr[r + 1] - P.h_row_ptr[r]);
+    P.h_slice_base[s + 1] = P.h_slice_base[s] + w * kSlice;
+  }
+  P.nslots = P.h_slice_base[P.nslices];
+  std::vector<int32_t> scol(P.nslots, -1), diag_slot(n);
+  P.h_slot_of_bsr.resize(P.nnzb);
+  for (int64_t r = 0; r < n; ++r) {
+    int64_t s = r / kSlice, lane = r % kSlice;
+    for (int32_t k = 0; k < P.h_row_ptr[r + 1] - P.h_row_ptr[r]; ++k) {
+      int64_t slot = P.h_slice_base[s] + int64_t(k) * kSlice + lane;
+      int32_t col = P.h_col[P.h_row_ptr[r] + k];
+      scol[slot] = col;
+      P.h_slot_of_bsr[P.h_row_ptr[r] + k] = slot;
+      if (col == r) diag_slot[r] = int32_t(slot);
+    }
+  }
+  // gather lists: every tet contributes block (a,b) to row tets[a], column tets[b]
+  auto find_slot = [&](int32_t i, int32_t j) -> int64_t {
+    const int32_t* b = &P.h_col[P.h_row_ptr[i]];
+    const int32_t* e = &P.h_col[P.h_row_ptr[i + 1]];
+    int64_t k = std::lower_bound(b, e, j) - b;
+    return P.h_slice_base[i / kSlice] + k * kSlice + (i % kSlice);
+  };
+  std::vector<int32_t> gcnt(P.nslots + 1, 0);
+  std::vector<int64_t> tslot(16 * T);
+  for (int64_t t = 0; t < T; ++t)
+    for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < 4; ++b) {
+        int64_t sl = find_slot(c->h_tets[4 * t + a], c->h_tets[4 * t + b]);
+        tslot[16 * t + 4 * a + b] = sl;
+        gcnt[sl + 1]++;
+      }
+  for (int64_t s = 0; s < P.nslots; ++s) gcnt[s + 1] += gcnt[s];
+  std::vector<int32_t> gcode(16 * T);
+  {
+    std::vector<int32_t> fill(gcnt.begin(), gcnt.end() - 1);
+    for (int64_t t = 0; t < T; ++t)
+      for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b) {
+          int64_t sl = tslot[16 * t + 4 * a + b];
+          int pr = pair_index(std::min(a, b), std::max(a, b));
+          int tr = a > b ? 1 : 0;
+          gcode[fill[sl]++] = int32_t((t * 10 + pr) * 2 + tr);
+        }
+  }
+  ms_status s;
+  if ((s = upload(c, &P.d_slice_base, P.h_slice_base.data(), P.nslices + 1))) return s;
+  if ((s = upload(c, &P.d_col, scol.data(), P.nslots))) return s;
+  if ((s = upload(c, &P.d_diag_slot, diag_slot.data(), n))) return s;
+  if ((s = upload(c, &c->d_gptr, gcnt.data(), P.nslots + 1))) return s;
+  if ((s = upload(c, &c->d_gcode, gcode.data(), 16 * T))) return s;
+  return MS_OK;
+}
+
+}  // namespace ms

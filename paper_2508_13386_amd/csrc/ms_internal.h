@@ -1,0 +1,244 @@
+// Internal state of an ms_ctx and declarations shared by the library's
+// translation units.  Device layouts:
+//   * positions / vectors: [n][3] doubles (or floats in the FP32 parts);
+//   * Hessian: sliced BSR3 ("SBSR3"): rows are grouped in slices of
+//     kSlice = 64 consecutive vertices; slice s holds width_s block columns;
+//     block k of row (64 s + lane) stores its 9 components at
+//       vals[9 * base_s + (9 k + c) * 64 + lane],  base_s = 64 * sum_{s'<s} width_s',
+//     and its column at col[base_s + 64 k + lane] (-1 for padding).  A wave
+//     reading component c of block k of a slice reads 64 consecutive values.
+//   * per-tet element blocks: 10 blocks (a <= b of the 4 local vertices) of
+//     3x3, [T][10][9], written by the element kernel and gathered without
+//     atomics into the slots above.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/ms.h"
+
+namespace ms {
+
+constexpr int kSlice = 64;
+
+struct Buf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+// Sliced BSR3 pattern on the device plus host copies needed by queries.
+struct Pattern {
+  int64_t n = 0, nnzb = 0, nslots = 0, nslices = 0;
+  int32_t* d_slice_base = nullptr;   // [nslices+1] block-slot base of each slice (multiple of 64)
+  int32_t* d_col = nullptr;          // [nslots]
+  int32_t* d_diag_slot = nullptr;    // [n] slot of the diagonal block of each row
+  std::vector<int32_t> h_row_ptr, h_col;  // canonical BSR (sorted columns)
+  std::vector<int64_t> h_slot_of_bsr;     // [nnzb] slot of every canonical block
+  std::vector<int32_t> h_slice_base;
+};
+
+struct Basis {
+  int32_t m = 0;
+  int64_t nnz = 0;
+  std::vector<double> origins;    // [m][3]
+  std::vector<int64_t> vptr;      // [n+1]
+  std::vector<int32_t> vhandle;   // [nnz]
+  std::vector<double> vphi;       // [nnz]
+  std::vector<int32_t> part;      // [T] or empty
+  // device: per-vertex rows and per-handle columns (transpose) of U
+  int32_t* d_vptr = nullptr;      // [n+1]
+  int32_t* d_vh = nullptr;        // [nnz]
+  double* d_vw = nullptr;         // [nnz][4] = phi * [1, x - o_i]
+  float* d_vw32 = nullptr;
+  int32_t* d_hptr = nullptr;      // [m+1]
+  int32_t* d_hv = nullptr;        // [nnz] vertex of each (handle, vertex) pair
+  int32_t* d_hk = nullptr;        // [nnz] index into the per-vertex arrays
+  // Galerkin pair lists: for each coarse block (i <= j) the list of
+  // (Hessian slot, k_v, k_w) contributions; built on first use
+  int32_t npairs = 0;
+  int32_t* d_pair_ij = nullptr;   // [npairs][2]
+  int32_t* d_pair_ptr = nullptr;  // [npairs+1]
+  int32_t* d_pair_ent = nullptr;  // [L][3]
+  int64_t pair_L = 0;
+};
+
+}  // namespace ms
+
+struct Mlp;
+
+struct ms_ctx {
+  ms_device dev{};
+  hipStream_t stream = nullptr;
+  std::vector<void*> allocs;  // every live device allocation of this context
+  std::string err;
+  int stage = 0;  // 1 mesh, 2 material, 3 state
+  // sizes
+  int64_t n = 0, T = 0;
+  // host mesh
+  std::vector<double> h_rest;
+  std::vector<int32_t> h_tets;
+  std::vector<double> h_vol, h_mu, h_lam, h_mass, h_Dminv;
+  std::vector<double> h_E;
+  double bbox_diag = 1.0;
+  // device mesh
+  double* d_rest = nullptr;
+  int32_t* d_tets = nullptr;
+  double* d_Dminv = nullptr;  // [T][9]
+  double* d_vol = nullptr;
+  double* d_mu = nullptr;
+  double* d_lam = nullptr;
+  double* d_mass = nullptr;
+  int32_t* d_vt_ptr = nullptr;   // [n+1] vertex -> incident (tet, local) codes
+  int32_t* d_vt_code = nullptr;  // [4T]  t*4 + a
+  ms::Pattern pat;
+  int32_t* d_gptr = nullptr;     // [nslots+1] gather ranges per slot
+  int32_t* d_gcode = nullptr;    // [16T] (t*10 + pair)*2 + transpose
+  // physics
+  double gravity[3] = {0, 0, 0};
+  bool has_hs = false;
+  double hs_n[3] = {0, 0, 1}, hs_off = 0, hs_dhat = 1e-3, hs_kappa = 0;
+  // Dirichlet
+  std::vector<int32_t> h_dbc;
+  std::vector<double> h_dbc_tgt;
+  uint8_t* d_pinned = nullptr;
+  int32_t* d_dbc = nullptr;
+  double* d_dbc_tgt = nullptr;
+  int64_t dbc_cap = 0;
+  // state
+  double* d_x = nullptr;
+  double* d_v = nullptr;
+  double* d_xt = nullptr;
+  double* d_xtilde = nullptr;
+  double* d_xtrial = nullptr;
+  // assembly workspace
+  double* d_He = nullptr;     // [T][10][9] FP64
+  float* d_He32 = nullptr;    // [T][10][9] FP32
+  double* d_ge = nullptr;     // [T][12]
+  double* d_g = nullptr;      // [n][3]
+  double* d_vals = nullptr;   // sliced values FP64 [9*nslots]
+  float* d_vals32 = nullptr;  // sliced values FP32
+  double* d_Dinv = nullptr;   // [n][9] inverse diagonal blocks
+  float* d_Dinv32 = nullptr;
+  // PCG workspace
+  double *d_d = nullptr, *d_r = nullptr, *d_u = nullptr, *d_w = nullptr, *d_p = nullptr, *d_s = nullptr;
+  float *f_r = nullptr, *f_u = nullptr, *f_w = nullptr, *f_p = nullptr, *f_s = nullptr;
+  double* d_scal = nullptr;   // device scalars of the solvers
+  double* h_scal = nullptr;   // pinned host mirror
+  double* d_part = nullptr;   // reduction partials
+  unsigned* d_counter = nullptr;
+  int nblk_vert = 0;          // blocks of the per-vertex kernels
+  // graphs of fixed-size PCG chunks (per precision x preconditioner)
+  hipGraphExec_t cg_graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  int cg_chunk = 16;
+  bool use_graphs = true;
+  bool own_stream = false;
+  // basis / two-level preconditioner
+  ms::Basis basis;
+  bool has_basis = false;
+  int32_t r = 0;              // 12 m
+  double* d_c = nullptr;      // coarse rhs [r]
+  double* d_e = nullptr;      // coarse solution [r]
+  double* d_Ac = nullptr;     // coarse matrix [r][r] (row-major), then its Cholesky factor
+  double* d_Ainv = nullptr;   // explicit inverse of the coarse matrix [r][r]
+  float* d_Ac32 = nullptr;    // FP32 Galerkin accumulation
+  double* d_cpart = nullptr;  // coarse restriction partials
+  int coarse_valid = 0;
+  // learned warm start
+  Mlp* mlp = nullptr;
+  std::vector<double> q_prev, q_cur;  // last two coarse states
+  int q_hist = 0;
+  // last eval
+  int eval_prec = 0;
+  bool eval_valid = false;
+};
+
+struct ms_mat {
+  ms_ctx ctx;  // reuses the allocator / stream plumbing of a context
+  int dtype = 0;
+  double bytes = 0.0;
+};
+
+namespace ms {
+
+// error helpers ------------------------------------------------------------
+ms_status fail(ms_ctx* c, ms_status s, const std::string& msg);
+ms_status hip_fail(ms_ctx* c, hipError_t e, const char* what);
+#define MS_HIP(call)                                    \
+  do {                                                  \
+    hipError_t e_ = (call);                             \
+    if (e_ != hipSuccess) return ms::hip_fail(c, e_, #call); \
+  } while (0)
+
+void* dalloc(ms_ctx* c, size_t bytes);
+void dfree(ms_ctx* c, void* p);
+template <class T>
+ms_status alloc_n(ms_ctx* c, T** p, size_t n) {
+  if (*p) dfree(c, *p);
+  *p = static_cast<T*>(dalloc(c, n * sizeof(T) + 256));
+  if (!*p) return fail(c, MS_E_NOMEM, "device allocation failed");
+  return MS_OK;
+}
+template <class T>
+ms_status upload(ms_ctx* c, T** p, const T* h, size_t n) {
+  ms_status s = alloc_n(c, p, n);
+  if (s) return s;
+  if (n) {
+    hipError_t e = hipMemcpyAsync(*p, h, n * sizeof(T), hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "hipMemcpyAsync H2D");
+    e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+  }
+  return MS_OK;
+}
+
+// host precompute (mesh.cpp) ------------------------------------------------
+ms_status build_mesh(ms_ctx* c);
+ms_status build_pattern(ms_ctx* c);
+
+// kernel launchers (kernels_*.hip) -------------------------------------------
+enum Scal {  // indices into ctx->d_scal
+  S_GAMMA = 0, S_DELTA, S_RHO, S_ALPHA, S_BETA, S_GAMMA_OLD, S_ALPHA_OLD, S_ITER, S_DONE, S_TOL2,
+  S_RHO0, S_MAXIT, S_E0, S_E1, S_E2, S_E3, S_CCD, S_DOT0, S_DOT1, S_DOT2, S_G0SQ, S_COUNT = 32
+};
+
+void launch_predict(ms_ctx* c, double dt);
+void launch_apply_dbc(ms_ctx* c, int64_t nd);
+void launch_element(ms_ctx* c, const double* x, double h2, int prec, bool hess, bool project);
+void launch_gather_grad(ms_ctx* c, const double* x, double h2, double* g);
+void launch_gather_hess(ms_ctx* c, const double* x, double h2, int prec);
+void launch_block_jacobi(ms_ctx* c, int prec);
+void launch_energy(ms_ctx* c, const double* x, const double* d, double alpha, double h2);
+void launch_ccd(ms_ctx* c, const double* x, const double* d);
+void launch_dots(ms_ctx* c, const double* a, const double* b, const double* a2, const double* b2,
+                 const double* a3, const double* b3);
+void launch_axpy(ms_ctx* c, double* y, const double* x, double alpha, int64_t len);
+void launch_velocity(ms_ctx* c, double inv_h);
+void launch_cg_init(ms_ctx* c, int prec, double eta_max, double eta_min, bool first, int max_it);
+void launch_coarse_correction(ms_ctx* c, int prec);
+void launch_cg_iteration(ms_ctx* c, int prec, int pc);
+void launch_precond(ms_ctx* c, int pc, int prec, const double* r, double* z);
+void launch_spmv(ms_ctx* c, int prec, const double* x, double* y);
+ms_status launch_galerkin(ms_ctx* c, int prec);
+ms_status coarse_factor(ms_ctx* c);
+void launch_extract_bsr(ms_ctx* c, const int64_t* slot_of_bsr_dev, int64_t nnzb, double* out, int prec);
+void launch_fill(ms_ctx* c, double* p, double v, int64_t len);
+
+// solver (api.hip, solver.hip)
+ms_status sync(ms_ctx* c);
+ms_status read_scal(ms_ctx* c);
+ms_status pcg_solve(ms_ctx* c, int prec, int pc, double eta_max, double eta_min, bool first, int max_it, int* iters,
+                    int* code);
+ms_status assemble(ms_ctx* c, const double* x, double h2, int prec, bool project, bool need_pc, int pc);
+ms_status energy(ms_ctx* c, const double* x, const double* d, double alpha, double h2, double parts[4]);
+ms_status plain_step(ms_ctx* c, double dt, const ms_solver_params& P, ms_step_stats* st);
+ms_status paper_step(ms_ctx* c, double dt, const ms_solver_params& P, ms_step_stats* st);
+void release_all(ms_ctx* c);
+ms_status line_search(ms_ctx* c, double h2, double gd, int max_bt, double* alpha_out, int* nbt);
+ms_status warm_start(ms_ctx* c, double dt, int32_t* used);
+ms_status record_coarse(ms_ctx* c);
+ms_status mat_build(struct ::ms_mat* A, int64_t n, const int32_t* row_ptr, const int32_t* col, const double* vals);
+void mat_spmv(struct ::ms_mat* A, const void* x, void* y);
+
+}  // namespace ms

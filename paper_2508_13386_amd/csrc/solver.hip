@@ -1,0 +1,142 @@
+// Plain Newton-PCG timestep (Sec. 3.1).
+//
+// Per Newton iteration: element kernel + atomic-free gathers assemble g
+// (FP64) and H (FP64 or FP32) at x; PCG (block-Jacobi or two-level) solves
+// H d = -g to the forcing tolerance eta = min(eta_max, sqrt(||g|| / ||g_0||));
+// the step is truncated by the half-space CCD bound and backtracked on the
+// FP64 energy until the Armijo condition holds (skipped when the predicted
+// decrease is below the round-off level of E).  The iteration stops after a
+// full step with ||d|| <= newton_tol * max(||x - x^t||, abs_floor).
+//
+// Near the minimiser the element Hessians are used without the PSD
+// projection (the exact Hessian), which restores quadratic convergence;
+// if PCG then detects a loss of positive definiteness the iteration is
+// redone with the projection.  A failed step restores x (transactional).
+#include <chrono>
+#include <cmath>
+
+#include "ms_internal.h"
+
+namespace ms {
+
+static double now_ms() {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+static ms_status restore(ms_ctx* c, ms_status s) {
+  (void)hipMemcpyAsync(c->d_x, c->d_xt, 3 * c->n * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
+  (void)hipStreamSynchronize(c->stream);
+  return s;
+}
+
+// Backtracking line search along d from x; returns the accepted alpha.
+ms_status line_search(ms_ctx* c, double h2, double gd, int max_bt, double* alpha_out, int* nbt) {
+  double alpha = 1.0;
+  ms_status s;
+  if (c->has_hs) {
+    launch_ccd(c, c->d_x, c->d_d);
+    if ((s = read_scal(c))) return s;
+    alpha = std::fmin(1.0, c->h_scal[S_CCD]);
+  }
+  double e0[4];
+  if ((s = energy(c, c->d_x, nullptr, 0.0, h2, e0))) return s;
+  const double E0 = e0[0] + e0[1] + e0[2] + e0[3];
+  const double scale = std::fabs(e0[0]) + std::fabs(e0[1]) + std::fabs(e0[2]) + std::fabs(e0[3]);
+  if (!std::isfinite(E0)) return fail(c, MS_E_NONFINITE, "non-finite energy");
+  int k = 0;
+  if (-gd > 1e-12 * scale) {
+    while (true) {
+      double e1[4];
+      if ((s = energy(c, c->d_x, c->d_d, alpha, h2, e1))) return s;
+      const double E1 = e1[0] + e1[1] + e1[2] + e1[3];
+      if (std::isfinite(E1) && E1 <= E0 + 1e-4 * alpha * gd) break;
+      alpha *= 0.5;
+      if (++k > max_bt) return fail(c, MS_E_LINESEARCH, "no energy decrease within the backtracking budget");
+    }
+  }
+  *alpha_out = alpha;
+  *nbt = k;
+  return MS_OK;
+}
+
+ms_status plain_step(ms_ctx* c, double dt, const ms_solver_params& P, ms_step_stats* st) {
+  const double t0 = now_ms();
+  const double h2 = dt * dt;
+  const int prec = P.precision == MS_PREC_MIXED ? MS_PREC_MIXED : MS_PREC_FP64;
+  const int pc = P.preconditioner == MS_PC_TWO_LEVEL ? MS_PC_TWO_LEVEL : MS_PC_BLOCK_JACOBI;
+  if (pc == MS_PC_TWO_LEVEL && !c->has_basis) return fail(c, MS_E_ORDER, "two-level preconditioner needs a basis");
+  launch_predict(c, dt);
+  launch_apply_dbc(c, int64_t(c->h_dbc.size()));
+  ms_step_stats S{};
+  S.min_alpha = 1.0;
+  ms_status s;
+  if (P.warm_start && c->mlp) {
+    if ((s = warm_start(c, dt, &S.warm_start_used))) return restore(c, s);
+  }
+  bool endgame = false, converged = false, first = true;
+  double dnorm = 0.0, disp = 0.0;
+  int it = 0;
+  for (; it < P.max_newton; ++it) {
+    const bool project = !(P.exact_endgame && endgame);
+    if ((s = assemble(c, c->d_x, h2, prec, project, true, pc))) return restore(c, s);
+    int iters = 0, code = 0;
+    if ((s = pcg_solve(c, prec, pc, P.pcg_eta_max, P.pcg_eta_min, first, P.max_pcg, &iters, &code)))
+      return restore(c, s);
+    first = false;
+    S.pcg_iters += iters;
+    S.max_pcg_iters = std::max(S.max_pcg_iters, iters);
+    if (!std::isfinite(c->h_scal[S_RHO0])) return restore(c, fail(c, MS_E_NONFINITE, "non-finite gradient"));
+    if (code == 3 && !project) {  // indefinite exact Hessian: redo with the projection
+      endgame = false;
+      continue;
+    }
+    launch_dots(c, c->d_g, c->d_d, c->d_d, c->d_d, nullptr, nullptr);
+    if ((s = read_scal(c))) return restore(c, s);
+    const double gd = c->h_scal[S_DOT0];
+    dnorm = std::sqrt(c->h_scal[S_DOT1]);
+    if (!std::isfinite(gd) || !std::isfinite(dnorm)) return restore(c, fail(c, MS_E_NONFINITE, "non-finite step"));
+    if (dnorm == 0.0) {
+      converged = true;
+      break;
+    }
+    if (!(gd < 0.0)) {
+      if (!project) {
+        endgame = false;
+        continue;
+      }
+      return restore(c, fail(c, MS_E_LINESEARCH, "search direction is not a descent direction"));
+    }
+    double alpha = 1.0;
+    int nbt = 0;
+    if ((s = line_search(c, h2, gd, P.max_backtracks, &alpha, &nbt))) return restore(c, s);
+    launch_axpy(c, c->d_x, c->d_d, alpha, 3 * c->n);
+    S.backtracks += nbt;
+    S.min_alpha = std::min(S.min_alpha, alpha);
+    launch_dots(c, nullptr, nullptr, nullptr, nullptr, c->d_x, c->d_xt);
+    if ((s = read_scal(c))) return restore(c, s);
+    disp = std::sqrt(c->h_scal[S_DOT2]);
+    const double ref = std::max(disp, P.abs_floor);
+    if (alpha == 1.0 && dnorm <= P.newton_tol * ref) {
+      converged = true;
+      ++it;
+      break;
+    }
+    if (dnorm <= 1e-3 * ref) endgame = true;
+  }
+  if (!converged) return restore(c, fail(c, MS_E_NOCONV, "Newton did not converge"));
+  launch_velocity(c, 1.0 / dt);
+  double ef[4];
+  if ((s = energy(c, c->d_x, nullptr, 0.0, h2, ef))) return restore(c, s);
+  if (c->has_basis && c->mlp) {
+    if ((s = record_coarse(c))) return s;
+  }
+  S.newton_iters = it;
+  S.energy = ef[0] + ef[1] + ef[2] + ef[3];
+  S.last_dnorm = dnorm;
+  S.disp_norm = disp;
+  S.time_ms = now_ms() - t0;
+  if (st) *st = S;
+  return MS_OK;
+}
+
+}  // namespace ms

@@ -1,0 +1,380 @@
+"""ctypes binding of libms (the C ABI declared in include/ms.h).
+
+Argument marshalling only: every computation runs in the HIP library.  The
+functions keep the C names.  Device memory comes from PyTorch's caching
+allocator through the ms_device callbacks, and work runs on a dedicated
+torch.cuda.Stream.  Loading fails loudly when the library is not built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libms.so")
+
+MS_OK, MS_E_ARG, MS_E_MESH, MS_E_ORDER, MS_E_DEVICE, MS_E_NOMEM, MS_E_NOCONV, MS_E_LINESEARCH, MS_E_NONFINITE = \
+    0, -1, -2, -3, -4, -5, -6, -7, -8
+PREC_FP64, PREC_MIXED = 0, 1
+PC_BLOCK_JACOBI, PC_TWO_LEVEL = 0, 1
+MODE_PLAIN, MODE_PAPER = 0, 1
+
+_ALLOC = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+_FREE = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class ms_device(C.Structure):
+    _fields_ = [("device", C.c_int), ("hip_stream", C.c_void_p), ("alloc", _ALLOC), ("free", _FREE),
+                ("user", C.c_void_p)]
+
+
+class ms_solver_params(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("precision", C.c_int32), ("preconditioner", C.c_int32),
+                ("max_newton", C.c_int32), ("max_pcg", C.c_int32), ("newton_tol", C.c_double),
+                ("abs_floor", C.c_double), ("pcg_eta_max", C.c_double), ("pcg_eta_min", C.c_double),
+                ("replace_every", C.c_int32), ("max_backtracks", C.c_int32), ("exact_endgame", C.c_int32),
+                ("warm_start", C.c_int32), ("paper_eps", C.c_double), ("subspace_rtol", C.c_double),
+                ("refine_iters", C.c_int32), ("lag_window", C.c_int32), ("lag_threshold", C.c_double),
+                ("lag_min_gap", C.c_int32)]
+
+
+class ms_step_stats(C.Structure):
+    _fields_ = [("newton_iters", C.c_int32), ("pcg_iters", C.c_int32), ("max_pcg_iters", C.c_int32),
+                ("backtracks", C.c_int32), ("hessian_refreshes", C.c_int32), ("warm_start_used", C.c_int32),
+                ("energy", C.c_double), ("last_dnorm", C.c_double), ("disp_norm", C.c_double),
+                ("min_alpha", C.c_double), ("time_ms", C.c_double)]
+
+    def asdict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ms_basis_params(C.Structure):
+    _fields_ = [("n_handles", C.c_int32), ("oversample", C.c_double), ("jump_penalty", C.c_double),
+                ("prune_ratio", C.c_double), ("prune_every", C.c_int32), ("prune_n", C.c_int32),
+                ("max_lloyd", C.c_int32), ("lattice_seeding", C.c_int32), ("seed", C.c_uint64),
+                ("n_threads", C.c_int32)]
+
+
+_FP = C.POINTER(C.c_float)
+
+
+class ms_mlp_desc(C.Structure):
+    _fields_ = [("in_dim", C.c_int32), ("width", C.c_int32), ("out_dim", C.c_int32),
+                ("W0", _FP), ("b0", _FP), ("W1", _FP), ("b1", _FP), ("W2", _FP), ("b2", _FP),
+                ("in_mean", _FP), ("in_std", _FP), ("out_scale", _FP)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libms.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2508_13386_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, d, dp, ip = C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_void_p, C.c_void_p
+        sig = {
+            "ms_create": [C.POINTER(ms_device), C.POINTER(C.c_void_p)],
+            "ms_upload_mesh": [vp, i64, dp, i64, ip],
+            "ms_upload_material": [vp, dp, dp, dp],
+            "ms_set_gravity": [vp, dp],
+            "ms_set_dirichlet": [vp, i64, ip, dp],
+            "ms_add_halfspace": [vp, dp, d, d, d],
+            "ms_set_state": [vp, dp, dp],
+            "ms_get_state": [vp, dp, dp],
+            "ms_build_basis": [vp, C.POINTER(ms_basis_params)],
+            "ms_set_basis": [vp, i32, dp, ip, ip, dp],
+            "ms_get_basis_size": [vp, C.POINTER(i32), C.POINTER(i64)],
+            "ms_get_basis": [vp, dp, ip, ip, dp, ip],
+            "ms_step": [vp, d, C.POINTER(ms_solver_params), C.POINTER(ms_step_stats)],
+            "ms_get_coarse": [vp, dp],
+            "ms_set_warmstart": [vp, C.POINTER(ms_mlp_desc)],
+            "ms_get_pattern": [vp, C.POINTER(i64), ip, ip],
+            "ms_eval": [vp, dp, d, i32, dp, dp, dp],
+            "ms_apply_preconditioner": [vp, i32, i32, dp, dp],
+            "ms_get_coarse_matrix": [vp, dp],
+            "ms_mat_create": [C.POINTER(ms_device), i64, ip, ip, dp, i32, C.POINTER(C.c_void_p)],
+            "ms_mat_spmv": [vp, vp, vp],
+            "ms_batch_step": [C.POINTER(C.c_void_p), i32, d, C.POINTER(ms_solver_params), C.POINTER(ms_step_stats)],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = C.c_int
+        L.ms_mat_bytes.argtypes = [vp]
+        L.ms_mat_bytes.restype = C.c_double
+        L.ms_mat_destroy.argtypes = [vp]
+        L.ms_mat_destroy.restype = None
+        L.ms_destroy.argtypes = [vp]
+        L.ms_destroy.restype = None
+        L.ms_last_error.argtypes = [vp]
+        L.ms_last_error.restype = C.c_char_p
+        for f in ("ms_solver_defaults",):
+            getattr(L, f).argtypes = [C.POINTER(ms_solver_params)]
+            getattr(L, f).restype = None
+        L.ms_basis_defaults.argtypes = [C.POINTER(ms_basis_params)]
+        L.ms_basis_defaults.restype = None
+        _lib = L
+    return _lib
+
+
+class MSError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"ms status {code}: {msg}")
+        self.code = code
+
+
+def _ptr(a):
+    return a.ctypes.data_as(C.c_void_p) if a is not None else None
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def solver_defaults(**kw) -> ms_solver_params:
+    p = ms_solver_params()
+    lib().ms_solver_defaults(C.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise AttributeError(k)
+        setattr(p, k, v)
+    return p
+
+
+def basis_defaults(**kw) -> ms_basis_params:
+    p = ms_basis_params()
+    lib().ms_basis_defaults(C.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise AttributeError(k)
+        setattr(p, k, v)
+    return p
+
+
+class TorchDevice:
+    """ms_device backed by torch's caching allocator and a torch stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self.torch = torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible to torch")
+        self.index = device
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=device)
+        self._live = {}
+
+        def _alloc(nbytes, user):
+            t = torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=f"cuda:{device}")
+            p = t.data_ptr()
+            self._live[p] = t
+            return p
+
+        def _free(p, user):
+            self._live.pop(p, None)
+
+        self._alloc_cb = _ALLOC(_alloc)
+        self._free_cb = _FREE(_free)
+        self.desc = ms_device(device, C.c_void_p(self.stream.cuda_stream), self._alloc_cb, self._free_cb, None)
+
+
+class Context:
+    """One simulation context (ms_ctx) with Python-friendly argument marshalling."""
+
+    def __init__(self, dev: TorchDevice):
+        self.dev = dev
+        self.L = lib()
+        h = C.c_void_p()
+        self._check(self.L.ms_create(C.byref(dev.desc), C.byref(h)), ctx=None)
+        self.h = h
+        self.n = 0
+        self.T = 0
+
+    def _check(self, code, ctx="self"):
+        if code != MS_OK:
+            msg = ""
+            if ctx is not None and getattr(self, "h", None):
+                msg = (self.L.ms_last_error(self.h) or b"").decode()
+            raise MSError(code, msg)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.ms_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- uploads --------------------------------------------------------------
+    def ms_upload_mesh(self, rest, tets):
+        rest, tets = _f64(rest), _i32(tets)
+        self.n, self.T = len(rest), len(tets)
+        self._check(self.L.ms_upload_mesh(self.h, self.n, _ptr(rest), self.T, _ptr(tets)))
+
+    def ms_upload_material(self, E, nu, rho):
+        E, nu, rho = _f64(E), _f64(nu), _f64(rho)
+        self._check(self.L.ms_upload_material(self.h, _ptr(E), _ptr(nu), _ptr(rho)))
+
+    def ms_set_gravity(self, g):
+        g = _f64(g)
+        self._check(self.L.ms_set_gravity(self.h, _ptr(g)))
+
+    def ms_set_dirichlet(self, verts, targets):
+        verts, targets = _i32(verts), _f64(targets).reshape(-1, 3)
+        self._check(self.L.ms_set_dirichlet(self.h, len(verts), _ptr(verts), _ptr(targets)))
+
+    def ms_add_halfspace(self, normal, offset, dhat, kappa):
+        nrm = _f64(normal)
+        self._check(self.L.ms_add_halfspace(self.h, _ptr(nrm), float(offset), float(dhat), float(kappa)))
+
+    def ms_set_state(self, x, v):
+        x, v = _f64(x), _f64(v)
+        self._check(self.L.ms_set_state(self.h, _ptr(x), _ptr(v)))
+
+    def ms_get_state(self):
+        x = np.empty((self.n, 3))
+        v = np.empty((self.n, 3))
+        self._check(self.L.ms_get_state(self.h, _ptr(x), _ptr(v)))
+        return x, v
+
+    # -- basis ----------------------------------------------------------------
+    def ms_build_basis(self, params=None, **kw):
+        p = params or basis_defaults(**kw)
+        self._check(self.L.ms_build_basis(self.h, C.byref(p)))
+
+    def ms_set_basis(self, origins, vptr, vhandle, vphi):
+        o, vp, vh, w = _f64(origins), np.ascontiguousarray(vptr, dtype=np.int64), _i32(vhandle), _f64(vphi)
+        self._check(self.L.ms_set_basis(self.h, len(o), _ptr(o), _ptr(vp), _ptr(vh), _ptr(w)))
+
+    def ms_get_basis(self):
+        m = C.c_int32()
+        nnz = C.c_int64()
+        self._check(self.L.ms_get_basis_size(self.h, C.byref(m), C.byref(nnz)))
+        o = np.empty((m.value, 3))
+        vp = np.empty(self.n + 1, dtype=np.int64)
+        vh = np.empty(nnz.value, dtype=np.int32)
+        w = np.empty(nnz.value)
+        part = np.empty(self.T, dtype=np.int32)
+        self._check(self.L.ms_get_basis(self.h, _ptr(o), _ptr(vp), _ptr(vh), _ptr(w), _ptr(part)))
+        return dict(origins=o, vptr=vp, vhandle=vh, vphi=w, part=part, m=m.value)
+
+    # -- stepping ---------------------------------------------------------------
+    def ms_step(self, dt, params=None, **kw):
+        p = params or solver_defaults(**kw)
+        st = ms_step_stats()
+        self._check(self.L.ms_step(self.h, float(dt), C.byref(p), C.byref(st)))
+        return st.asdict()
+
+    def ms_get_coarse(self, r):
+        q = np.empty(r)
+        self._check(self.L.ms_get_coarse(self.h, _ptr(q)))
+        return q
+
+    def ms_set_warmstart(self, desc: ms_mlp_desc):
+        self._check(self.L.ms_set_warmstart(self.h, C.byref(desc)))
+
+    # -- kernel-level queries ---------------------------------------------------
+    def ms_get_pattern(self):
+        nnzb = C.c_int64()
+        self._check(self.L.ms_get_pattern(self.h, C.byref(nnzb), None, None))
+        rp = np.empty(self.n + 1, dtype=np.int32)
+        col = np.empty(nnzb.value, dtype=np.int32)
+        self._check(self.L.ms_get_pattern(self.h, C.byref(nnzb), _ptr(rp), _ptr(col)))
+        return rp, col
+
+    def ms_eval(self, x, dt, prec=PREC_FP64, hess=True):
+        x = _f64(x)
+        e4 = np.empty(4)
+        g = np.empty((self.n, 3))
+        H = None
+        if hess:
+            nnzb = C.c_int64()
+            self._check(self.L.ms_get_pattern(self.h, C.byref(nnzb), None, None))
+            H = np.empty((nnzb.value, 3, 3))
+        self._check(self.L.ms_eval(self.h, _ptr(x), float(dt), int(prec), _ptr(e4), _ptr(g), _ptr(H)))
+        return e4, g, H
+
+    def ms_apply_preconditioner(self, kind, r, prec=PREC_FP64):
+        r = _f64(r)
+        z = np.empty((self.n, 3))
+        self._check(self.L.ms_apply_preconditioner(self.h, int(kind), int(prec), _ptr(r), _ptr(z)))
+        return z
+
+    def ms_get_coarse_matrix(self, r):
+        A = np.empty((r, r))
+        self._check(self.L.ms_get_coarse_matrix(self.h, _ptr(A)))
+        return A
+
+
+def ms_batch_step(contexts, dt, params=None, **kw):
+    L = lib()
+    p = params or solver_defaults(**kw)
+    arr = (C.c_void_p * len(contexts))(*[c.h for c in contexts])
+    stats = (ms_step_stats * len(contexts))()
+    code = L.ms_batch_step(arr, len(contexts), float(dt), C.byref(p), stats)
+    if code != MS_OK:
+        msg = (L.ms_last_error(contexts[0].h) or b"").decode()
+        raise MSError(code, msg)
+    return [s.asdict() for s in stats]
+
+
+class Matrix:
+    """Standalone sliced-BSR3 matrix (ms_mat) for SpMV measurements."""
+
+    def __init__(self, dev: TorchDevice, row_ptr, col, vals, dtype=0):
+        self.L = lib()
+        rp, cl, vv = _i32(row_ptr), _i32(col), _f64(vals).reshape(-1, 9)
+        h = C.c_void_p()
+        code = self.L.ms_mat_create(C.byref(dev.desc), len(rp) - 1, _ptr(rp), _ptr(cl), _ptr(vv), int(dtype),
+                                    C.byref(h))
+        if code != MS_OK:
+            raise MSError(code, "ms_mat_create")
+        self.h = h
+        self.n = len(rp) - 1
+        self.dtype = dtype
+
+    def spmv(self, x_ptr: int, y_ptr: int):
+        code = self.L.ms_mat_spmv(self.h, C.c_void_p(x_ptr), C.c_void_p(y_ptr))
+        if code != MS_OK:
+            raise MSError(code, "ms_mat_spmv")
+
+    @property
+    def bytes(self):
+        return self.L.ms_mat_bytes(self.h)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.ms_mat_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def context_from_scene(dev: TorchDevice, s, step: int = 1):
+    """Create a context and upload a scene dict from the `scenes` generators."""
+    c = Context(dev)
+    c.ms_upload_mesh(s["rest"], s["tets"])
+    c.ms_upload_material(s["E"], s["nu"], s["rho"])
+    c.ms_set_gravity(s["gravity"])
+    if len(s["dirichlet"]):
+        c.ms_set_dirichlet(s["dirichlet"], s["dbc_targets"](step))
+    if s["halfspace"] is not None:
+        hs = s["halfspace"]
+        c.ms_add_halfspace(hs["normal"], hs["offset"], hs["dhat"], hs["kappa"])
+    c.ms_set_state(s["x0"], s["v0"])
+    return c
