@@ -64,7 +64,15 @@ typedef struct {
 } ms_device;
 
 typedef enum { MS_PREC_FP64 = 0, MS_PREC_MIXED = 1 } ms_precision;
-typedef enum { MS_PC_BLOCK_JACOBI = 0, MS_PC_TWO_LEVEL = 1 } ms_preconditioner;
+/* Preconditioners of the plain path.  S = 3x3 block-Jacobi of H,
+ * Q = U (U^T H U)^-1 U^T the coarse correction on the basis U:
+ *   MS_PC_BLOCK_JACOBI         z = S r
+ *   MS_PC_TWO_LEVEL            z = S r + Q (r - H S r)   (smoothing then coarse
+ *                              correction; PCG starts from d_0 = Q(-g), which
+ *                              makes the iteration a deflated / balancing
+ *                              two-level method)
+ *   MS_PC_TWO_LEVEL_ADDITIVE   z = S r + Q r */
+typedef enum { MS_PC_BLOCK_JACOBI = 0, MS_PC_TWO_LEVEL = 1, MS_PC_TWO_LEVEL_ADDITIVE = 2 } ms_preconditioner;
 typedef enum { MS_MODE_PLAIN = 0, MS_MODE_PAPER = 1 } ms_mode;
 
 /* Parameters of one timestep solve.  ms_solver_defaults() fills them. */
@@ -78,7 +86,7 @@ typedef struct {
   double newton_tol;       /* plain mode: stop when a full step has
                               ||d||_2 <= newton_tol * max(||x - x^t||_2, abs_floor)     */
   double abs_floor;        /* absolute displacement floor of that test (m)              */
-  double pcg_eta_max;      /* forcing term eta = min(eta_max, sqrt(||g||/||g_0||))       */
+  double pcg_eta_max;      /* upper bound of the PCG forcing term (see forcing)         */
   double pcg_eta_min;      /* lower bound of the forcing term                           */
   int32_t replace_every;   /* mixed precision: FP64 true-residual recomputation period  */
   int32_t max_backtracks;  /* line-search halvings before MS_E_LINESEARCH               */
@@ -91,6 +99,16 @@ typedef struct {
   int32_t lag_window;      /* step sizes averaged by the Hessian-lag trigger             */
   double lag_threshold;    /* refresh the lagged elastic Hessian below this average     */
   int32_t lag_min_gap;     /* at most one refresh every lag_min_gap iterations          */
+  /* plain mode, continued */
+  int32_t forcing;         /* 0: eta = sqrt(||g||/||g_0||); 1: Eisenstat-Walker choice 2,
+                              eta_k = 0.9 (||g_k||/||g_k-1||)^2 with safeguard          */
+  double endgame_ratio;    /* exact (unprojected) Hessian once ||d|| <= ratio * ||x - x^t|| */
+  int32_t coarse_every;    /* two-level: rebuild U^T H U and its factor at the first Newton
+                              iteration of a step and then every coarse_every iterations
+                              (0: once per step; the preconditioner may lag H)          */
+  int32_t predictor;       /* initial Newton iterate: 0 x^t; 1 the inertial predictor
+                              x^t + h v^t (truncated by the contact filter, Dirichlet
+                              vertices at their targets), kept only if it lowers E     */
 } ms_solver_params;
 
 /* Statistics of the last ms_step. */
@@ -189,6 +207,20 @@ ms_status ms_set_basis(ms_ctx* c, int32_t m, const double* origins, const int64_
 ms_status ms_get_basis_size(const ms_ctx* c, int32_t* m, int64_t* nnz);
 ms_status ms_get_basis(const ms_ctx* c, double* origins, int64_t* vptr, int32_t* vhandle, double* vphi,
                        int32_t* part);
+
+/* Host-only basis construction (no device involved): the same algorithm as
+ * ms_build_basis on a mesh rest_xyz [n][3] / tets [T][4], Young's moduli
+ * E [T] and Dirichlet vertices dbc [n_dbc].  *out receives an opaque result
+ * that ms_basis_get queries (first with null arrays for *m and *nnz, then
+ * with arrays sized origins [m][3], vptr [n+1], vhandle [nnz], vphi [nnz],
+ * part [T]) and ms_basis_free releases.  The arrays can be passed to
+ * ms_set_basis.  Errors: MS_E_ARG, MS_E_MESH. */
+typedef struct ms_basis ms_basis;
+ms_status ms_basis_compute(int64_t n, const double* rest_xyz, int64_t T, const int32_t* tets, const double* E,
+                           int64_t n_dbc, const int32_t* dbc, const ms_basis_params* p, ms_basis** out);
+ms_status ms_basis_get(const ms_basis* b, int32_t* m, int64_t* nnz, double* origins, int64_t* vptr,
+                       int32_t* vhandle, double* vphi, int32_t* part);
+void ms_basis_free(ms_basis* b);
 
 /* Advance one timestep of size dt (s) with parameters p (NULL = defaults);
  * stats may be NULL.  Transactional: on any error x and v are unchanged.

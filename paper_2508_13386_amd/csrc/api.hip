@@ -3,6 +3,8 @@
 // steps H d = -g, CCD-filtered backtracking line search).
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 #include "ms_internal.h"
@@ -81,9 +83,9 @@ static ms_status alloc_workspace(ms_ctx* c) {
       (s = alloc_n(c, &c->d_vals32, 9 * c->pat.nslots)) || (s = alloc_n(c, &c->d_Dinv, 9 * n)) ||
       (s = alloc_n(c, &c->d_Dinv32, 9 * n)) || (s = alloc_n(c, &c->d_d, n3)) || (s = alloc_n(c, &c->d_r, n3)) ||
       (s = alloc_n(c, &c->d_u, n3)) || (s = alloc_n(c, &c->d_w, n3)) || (s = alloc_n(c, &c->d_p, n3)) ||
-      (s = alloc_n(c, &c->d_s, n3)) || (s = alloc_n(c, &c->f_r, n3)) || (s = alloc_n(c, &c->f_u, n3)) ||
-      (s = alloc_n(c, &c->f_w, n3)) || (s = alloc_n(c, &c->f_p, n3)) || (s = alloc_n(c, &c->f_s, n3)) ||
+      (s = alloc_n(c, &c->d_s, n3)) ||
       (s = alloc_n(c, &c->d_scal, S_COUNT)) || (s = alloc_n(c, &c->d_counter, 4)) ||
+      (s = alloc_n(c, &c->d_cgst, 8)) ||
       (s = alloc_n(c, &c->d_pinned, n)))
     return s;
   const int64_t nparts = std::max<int64_t>(std::max(T, n3) / 64 + 64, 4096);
@@ -111,15 +113,16 @@ static void destroy_graphs(ms_ctx* c) {
 // Returns the device "done" code in *code (1 converged, 2 iteration cap,
 // 3 loss of positive definiteness).
 ms_status pcg_solve(ms_ctx* c, int prec, int pc, double eta_max, double eta_min, bool first, int max_it, int* iters,
-                    int* code) {
-  launch_cg_init(c, prec, eta_max, eta_min, first, max_it);
-  if (pc == MS_PC_TWO_LEVEL) launch_coarse_correction(c, prec);
+                    int* code, int forcing) {
+  launch_cg_init(c, prec, eta_max, eta_min, first, max_it, forcing);
+  if (pc == MS_PC_TWO_LEVEL) launch_coarse_start(c, prec);
+  launch_precond_apply(c, prec, pc);
   const int chunk = c->cg_chunk;
   hipGraphExec_t& ge = c->cg_graph[prec][pc];
   if (!ge && c->use_graphs) {
     hipGraph_t g;
     MS_HIP(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-    for (int i = 0; i < chunk; ++i) launch_cg_iteration(c, prec, pc);
+    for (int i = 0; i < chunk; ++i) launch_cg_iteration(c, prec, pc, i & 1);
     MS_HIP(hipStreamEndCapture(c->stream, &g));
     MS_HIP(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
     (void)hipGraphDestroy(g);
@@ -129,7 +132,7 @@ ms_status pcg_solve(ms_ctx* c, int prec, int pc, double eta_max, double eta_min,
     if (c->use_graphs) {
       MS_HIP(hipGraphLaunch(ge, c->stream));
     } else {
-      for (int i = 0; i < chunk; ++i) launch_cg_iteration(c, prec, pc);
+      for (int i = 0; i < chunk; ++i) launch_cg_iteration(c, prec, pc, i & 1);
     }
     launched += chunk;
     ms_status s = read_scal(c);
@@ -142,13 +145,14 @@ ms_status pcg_solve(ms_ctx* c, int prec, int pc, double eta_max, double eta_min,
   return MS_OK;
 }
 
-ms_status assemble(ms_ctx* c, const double* x, double h2, int prec, bool project, bool need_pc, int pc) {
+ms_status assemble(ms_ctx* c, const double* x, double h2, int prec, bool project, bool need_pc, int pc,
+                   bool refresh_coarse) {
   launch_element(c, x, h2, prec, true, project);
   launch_gather_grad(c, x, h2, c->d_g);
   launch_gather_hess(c, x, h2, prec);
   if (need_pc) {
     launch_block_jacobi(c, prec);
-    if (pc == MS_PC_TWO_LEVEL) {
+    if (two_level(pc) && (refresh_coarse || !c->coarse_valid)) {
       ms_status s = launch_galerkin(c, prec);
       if (s) return s;
       s = coarse_factor(c);
@@ -194,6 +198,10 @@ void ms_solver_defaults(ms_solver_params* p) {
   p->lag_window = 3;
   p->lag_threshold = 0.5;
   p->lag_min_gap = 5;
+  p->forcing = 0;
+  p->endgame_ratio = 1e-3;
+  p->coarse_every = 1;
+  p->predictor = 1;
 }
 
 void ms_basis_defaults(ms_basis_params* p) {
@@ -216,6 +224,7 @@ ms_status ms_create(const ms_device* dev, ms_ctx** out) {
   if (hipSetDevice(dev->device) != hipSuccess) return MS_E_DEVICE;
   ms_ctx* c = new ms_ctx();
   c->dev = *dev;
+  if (const char* v = std::getenv("MS_VERBOSE")) c->verbose = std::atoi(v);
   if (dev->hip_stream) {
     c->stream = static_cast<hipStream_t>(dev->hip_stream);
   } else {
@@ -377,7 +386,7 @@ ms_status ms_eval(ms_ctx* c, const double* x, double dt, int32_t prec, double* e
   MS_HIP(hipMemcpyAsync(c->d_xtrial, x, n3 * sizeof(double), hipMemcpyHostToDevice, c->stream));
   launch_predict(c, dt);
   const double h2 = dt * dt;
-  ms_status s = assemble(c, c->d_xtrial, h2, prec, true, true, MS_PC_BLOCK_JACOBI);
+  ms_status s = assemble(c, c->d_xtrial, h2, prec, true, true, MS_PC_BLOCK_JACOBI, true);
   if (s) return s;
   if (c->has_basis) {
     if ((s = launch_galerkin(c, prec))) return s;
@@ -409,22 +418,16 @@ ms_status ms_apply_preconditioner(ms_ctx* c, int32_t kind, int32_t prec, const d
   if (!c || !r || !z) return MS_E_ARG;
   if (!c->eval_valid) return fail(c, MS_E_ORDER, "call ms_eval first");
   if (prec != c->eval_prec) return fail(c, MS_E_ARG, "precision differs from the last ms_eval");
-  if (kind == MS_PC_TWO_LEVEL && !c->has_basis) return fail(c, MS_E_ORDER, "no basis");
+  if (kind < 0 || kind > 2) return fail(c, MS_E_ARG, "bad preconditioner kind");
+  if (two_level(kind) && !c->has_basis) return fail(c, MS_E_ORDER, "no basis");
   const int64_t n3 = 3 * c->n;
   std::vector<double> mr(r, r + n3);
   for (auto& v : mr) v = -v;
   MS_HIP(hipMemcpyAsync(c->d_g, mr.data(), n3 * sizeof(double), hipMemcpyHostToDevice, c->stream));
-  launch_cg_init(c, prec, 0.0, 0.0, true, 0);
-  if (kind == MS_PC_TWO_LEVEL) launch_coarse_correction(c, prec);
-  if (prec == MS_PREC_FP64) {
-    MS_HIP(hipMemcpyAsync(z, c->d_u, n3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    return sync(c);
-  }
-  std::vector<float> zf(n3);
-  MS_HIP(hipMemcpyAsync(zf.data(), c->f_u, n3 * sizeof(float), hipMemcpyDeviceToHost, c->stream));
-  ms_status s = sync(c);
-  for (int64_t i = 0; i < n3; ++i) z[i] = zf[i];
-  return s;
+  launch_cg_init(c, prec, 0.0, 0.0, true, 0, 0);
+  launch_precond_apply(c, prec, kind);
+  MS_HIP(hipMemcpyAsync(z, c->d_u, n3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  return sync(c);
 }
 
 ms_status ms_step(ms_ctx* c, double dt, const ms_solver_params* pin, ms_step_stats* st) {

@@ -1,0 +1,611 @@
+// Two-level preconditioner built on the sparse material-aware basis U of
+// Eq. (LBS): the columns of U at vertex v are phi_vi (I_3 (x) [1, x_v - o_i]).
+//
+//   restriction   c = U^T r          one block per handle, fixed-order sums
+//   coarse solve  e = (U^T H U)^-1 c  FP64 Cholesky of the Galerkin matrix,
+//                                     applied as a GEMV with its inverse
+//   prolongation  u += U e            one thread per vertex
+// The PCG preconditioner is additive: z = D^-1 r + U (U^T H U)^-1 U^T r with
+// D the 3x3 block diagonal of H (Sec. 3.6 uses the same triple product
+// U^T H U matrix-free; here it is formed once per Newton iteration).
+//
+// Galerkin product in two atomic-free stages:
+//   Z_vj[a][b][l] = sum_{w in N(v), j in h(w)} H_vw[a][b] W_wj[l]     (Z = H U)
+//   A_(i,a,k),(j,b,l) = sum_{v: i in h(v)} W_vi[k] Z_vj[a][b][l]     (U^T Z)
+// with W_vi = phi_vi [1, x_v - o_i]; both stages sum in a fixed order.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+
+#include "ms_internal.h"
+#include "reduce.h"
+
+namespace ms {
+
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+__global__ void k_sub(int64_t len, const double* __restrict__ a, const double* __restrict__ b,
+                      double* __restrict__ out) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < len) out[i] = a[i] - b[i];
+}
+
+// Partial restriction over one chunk of a handle's vertex list:
+// part[chunk] = sum_{v in chunk} W_vi (x) (weight_v r_v); chunks of the
+// same handle are contiguous and are summed in order by the GEMV kernel.
+template <typename VT>
+__global__ void __launch_bounds__(64) k_restrict(int nchunks, const int32_t* __restrict__ chunk_beg,
+                                                 const int32_t* __restrict__ hv, const int32_t* __restrict__ hk,
+                                                 const double* __restrict__ vw, const VT* __restrict__ r,
+                                                 const double* __restrict__ weight, double* __restrict__ part,
+                                                 const double* __restrict__ scal) {
+  if (scal && scal[S_DONE] != 0.0) return;
+  const int ch = blockIdx.x;
+  const int e0 = chunk_beg[ch], e1 = chunk_beg[ch + 1];
+  double acc[12];
+#pragma unroll
+  for (int q = 0; q < 12; ++q) acc[q] = 0.0;
+  for (int eb = e0 + 4 * threadIdx.x; eb < e1; eb += 4 * blockDim.x) {
+    int64_t v[4], kk[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const bool ok = eb + u < e1;
+      v[u] = ok ? hv[eb + u] : -1;
+      kk[u] = ok ? hk[eb + u] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (v[u] < 0) continue;
+      const double* w = vw + 4 * kk[u];
+      const double s = weight ? weight[v[u]] : 1.0;
+      const double r0 = s * double(r[3 * v[u]]), r1 = s * double(r[3 * v[u] + 1]), r2 = s * double(r[3 * v[u] + 2]);
+#pragma unroll
+      for (int l = 0; l < 4; ++l) {
+        acc[l] += w[l] * r0;
+        acc[4 + l] += w[l] * r1;
+        acc[8 + l] += w[l] * r2;
+      }
+    }
+  }
+  block_sum<12>(acc);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int q = 0; q < 12; ++q) part[12 * ch + q] = acc[q];
+}
+
+// c = U^T v from the restriction partials: handle i owns chunks
+// hchunk[i] .. hchunk[i+1], summed in order.
+__global__ void k_chunk_sum(int r, const int32_t* __restrict__ hchunk, const double* __restrict__ part,
+                            double* __restrict__ c, const double* __restrict__ scal) {
+  if (scal && scal[S_DONE] != 0.0) return;
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= r) return;
+  const int i = q / 12, comp = q % 12;
+  const int c0 = hchunk[i], c1 = hchunk[i + 1];
+  double s = 0.0;
+  for (int cb = c0; cb < c1; cb += 4) {
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = (cb + u < c1) ? part[12 * (cb + u) + comp] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) s += v[u];
+  }
+  c[q] = s;
+}
+
+// e = A c for a dense row-major r x r matrix (leading dimension ld), one
+// wave per row.
+__global__ void __launch_bounds__(256) k_gemv(int r, int ld, const double* __restrict__ A,
+                                              const double* __restrict__ c, double* __restrict__ e,
+                                              const double* __restrict__ scal) {
+  if (scal && scal[S_DONE] != 0.0) return;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= r) return;
+  double s = 0.0;
+  const double* a = A + int64_t(row) * ld;
+  for (int j = lane; j < r; j += 64) s += a[j] * c[j];
+  s = wave_sum(s);
+  if (lane == 0) e[row] = s;
+}
+
+// u_v += sum_i W_vi (x) e_i, entries batched four at a time.
+__device__ __forceinline__ void prolong_sum(int k0, int k1, const int32_t* __restrict__ vh,
+                                            const double* __restrict__ vw, const double* __restrict__ e,
+                                            double& a0, double& a1, double& a2) {
+  for (int kb = k0; kb < k1; kb += 4) {
+    int h[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) h[u] = (kb + u < k1) ? vh[kb + u] : -1;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (h[u] < 0) continue;
+      const double* w = vw + 4 * int64_t(kb + u);
+      const double* q = e + 12 * int64_t(h[u]);
+#pragma unroll
+      for (int l = 0; l < 4; ++l) {
+        a0 += w[l] * q[l];
+        a1 += w[l] * q[4 + l];
+        a2 += w[l] * q[8 + l];
+      }
+    }
+  }
+}
+
+template <typename VT>
+__global__ void __launch_bounds__(64) k_prolong(int64_t n, const int32_t* __restrict__ vptr,
+                                                const int32_t* __restrict__ vh, const double* __restrict__ vw,
+                                                const double* __restrict__ e, const uint8_t* __restrict__ pinned,
+                                                VT* __restrict__ u, const double* __restrict__ scal) {
+  if (scal && scal[S_DONE] != 0.0) return;
+  const int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (v >= n || (pinned && pinned[v])) return;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  prolong_sum(vptr[v], vptr[v + 1], vh, vw, e, a0, a1, a2);
+  u[3 * v] = VT(double(u[3 * v]) + a0);
+  u[3 * v + 1] = VT(double(u[3 * v + 1]) + a1);
+  u[3 * v + 2] = VT(double(u[3 * v + 2]) + a2);
+}
+
+// Stage 1: one thread per (v, j) entry of Z = H U.
+template <typename HT>
+__global__ void __launch_bounds__(256) k_galerkin_z(int64_t nz, int S, const int32_t* __restrict__ zptr,
+                                                    const int32_t* __restrict__ zent, const HT* __restrict__ vals,
+                                                    const double* __restrict__ vw, const uint8_t* __restrict__ zmask,
+                                                    double* __restrict__ Z) {
+  const int64_t z = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (z >= nz) return;
+  double acc[36];
+#pragma unroll
+  for (int q = 0; q < 36; ++q) acc[q] = 0.0;
+  if (!zmask[z]) {
+    for (int e = zptr[z]; e < zptr[z + 1]; ++e) {
+      const int64_t slot = zent[2 * e];
+      const double* w = vw + 4 * int64_t(zent[2 * e + 1]);
+      const HT* h = vals + vbase(slot, S);
+      double hb[9];
+#pragma unroll
+      for (int q = 0; q < 9; ++q) hb[q] = double(h[S * q]);
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+#pragma unroll
+          for (int l = 0; l < 4; ++l) acc[12 * a + 4 * b + l] += hb[3 * a + b] * w[l];
+    }
+  }
+  double* out = Z + 36 * z;
+#pragma unroll
+  for (int q = 0; q < 36; ++q) out[q] = acc[q];
+}
+
+// Stage 2: one block per coarse pair (i <= j); entries staged through LDS.
+__global__ void __launch_bounds__(256) k_galerkin_a(int r, const int32_t* __restrict__ pair_ij,
+                                                    const int32_t* __restrict__ pptr,
+                                                    const int32_t* __restrict__ pent, const double* __restrict__ vw,
+                                                    const double* __restrict__ Z, double* __restrict__ A) {
+  __shared__ double sw[64][4];
+  __shared__ double sz[64][36];
+  const int p = blockIdx.x;
+  const int i = pair_ij[2 * p], j = pair_ij[2 * p + 1];
+  const int t = threadIdx.x;
+  // output (a,k),(b,l) handled by thread t < 144: a = t/48, k = (t/12)%4, b = (t%12)/4, l = t%4
+  const int a = t / 48, k = (t / 12) % 4, b = (t % 12) / 4, l = t % 4;
+  double acc = 0.0;
+  for (int e0 = pptr[p]; e0 < pptr[p + 1]; e0 += 64) {
+    const int ne = min(64, pptr[p + 1] - e0);
+    __syncthreads();
+    for (int q = t; q < ne * 40; q += blockDim.x) {
+      const int e = q / 40, c = q % 40;
+      const int kv = pent[2 * (e0 + e)], zz = pent[2 * (e0 + e) + 1];
+      if (c < 4)
+        sw[e][c] = vw[4 * int64_t(kv) + c];
+      else
+        sz[e][c - 4] = Z[36 * int64_t(zz) + (c - 4)];
+    }
+    __syncthreads();
+    if (t < 144)
+      for (int e = 0; e < ne; ++e) acc += sw[e][k] * sz[e][12 * a + 4 * b + l];
+  }
+  if (t < 144) {
+    const int row = 12 * i + 4 * a + k, col = 12 * j + 4 * b + l;
+    A[int64_t(row) * r + col] = acc;
+    if (i != j) A[int64_t(col) * r + row] = acc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+static inline unsigned nblocks(int64_t n, int b) { return unsigned((n + b - 1) / b); }
+
+ms_status install_basis(ms_ctx* c, Basis&& B) {
+  const int64_t n = c->n;
+  const int m = B.m;
+  if (m < 1) return fail(c, MS_E_ARG, "basis has no handles");
+  if (int64_t(B.vptr.size()) != n + 1 || B.vptr[0] != 0) return fail(c, MS_E_ARG, "bad vptr");
+  const int64_t nnz = B.vptr[n];
+  if (nnz > (int64_t(1) << 30)) return fail(c, MS_E_ARG, "basis too large");
+  B.nnz = nnz;
+  for (int64_t k = 0; k < nnz; ++k)
+    if (B.vhandle[k] < 0 || B.vhandle[k] >= m || !std::isfinite(B.vphi[k]))
+      return fail(c, MS_E_ARG, "bad basis entry");
+  // per-vertex weights W = phi [1, x - o]
+  std::vector<int32_t> vptr(n + 1);
+  for (int64_t v = 0; v <= n; ++v) vptr[v] = int32_t(B.vptr[v]);
+  std::vector<double> vw(4 * nnz);
+  for (int64_t v = 0; v < n; ++v)
+    for (int64_t k = B.vptr[v]; k < B.vptr[v + 1]; ++k) {
+      const int i = B.vhandle[k];
+      vw[4 * k] = B.vphi[k];
+      for (int d = 0; d < 3; ++d) vw[4 * k + 1 + d] = B.vphi[k] * (c->h_rest[3 * v + d] - B.origins[3 * i + d]);
+    }
+  // transpose (per handle, vertices ascending)
+  std::vector<int32_t> hptr(m + 1, 0), hv(nnz), hk(nnz);
+  for (int64_t k = 0; k < nnz; ++k) hptr[B.vhandle[k] + 1]++;
+  for (int i = 0; i < m; ++i) hptr[i + 1] += hptr[i];
+  {
+    std::vector<int32_t> fill(hptr.begin(), hptr.end() - 1);
+    for (int64_t v = 0; v < n; ++v)
+      for (int64_t k = B.vptr[v]; k < B.vptr[v + 1]; ++k) {
+        const int32_t pos = fill[B.vhandle[k]]++;
+        hv[pos] = int32_t(v);
+        hk[pos] = int32_t(k);
+      }
+  }
+  // restriction chunks: each handle's vertex list split into runs of at most kChunk
+  constexpr int kChunk = 256;
+  std::vector<int32_t> hchunk(m + 1, 0), chunk_beg;
+  for (int i = 0; i < m; ++i) {
+    for (int32_t e = hptr[i]; e < hptr[i + 1]; e += kChunk) chunk_beg.push_back(e);
+    hchunk[i + 1] = int32_t(chunk_beg.size());
+  }
+  chunk_beg.push_back(hptr[m]);
+  // Galerkin stage-1 lists: for each vertex v the handles reachable through
+  // its Hessian row, h'(v) = union of h(w) for w in N(v)
+  const Pattern& P = c->pat;
+  std::vector<int32_t> zvptr(n + 1, 0);
+  std::vector<int32_t> zhandle;
+  std::vector<int32_t> zptr(1, 0), zent;
+  std::vector<uint8_t> zmask;
+  std::vector<std::vector<std::pair<int, int>>> tmp;  // per handle in h'(v): (slot, k_w)
+  std::vector<int> hpos(m, -1);
+  std::vector<uint8_t> pinned(n, 0);
+  for (int v : c->h_dbc) pinned[v] = 1;
+  for (int64_t v = 0; v < n; ++v) {
+    std::vector<int> hs;
+    for (int32_t q = P.h_row_ptr[v]; q < P.h_row_ptr[v + 1]; ++q) {
+      const int w = P.h_col[q];
+      for (int64_t k = B.vptr[w]; k < B.vptr[w + 1]; ++k) hs.push_back(B.vhandle[k]);
+    }
+    std::sort(hs.begin(), hs.end());
+    hs.erase(std::unique(hs.begin(), hs.end()), hs.end());
+    tmp.assign(hs.size(), {});
+    for (size_t a = 0; a < hs.size(); ++a) hpos[hs[a]] = int(a);
+    for (int32_t q = P.h_row_ptr[v]; q < P.h_row_ptr[v + 1]; ++q) {
+      const int w = P.h_col[q];
+      if (pinned[w]) continue;  // U vanishes on eliminated DOFs
+      const int64_t slot = P.h_slot_of_bsr[q];
+      for (int64_t k = B.vptr[w]; k < B.vptr[w + 1]; ++k) tmp[hpos[B.vhandle[k]]].push_back({int(slot), int(k)});
+    }
+    for (size_t a = 0; a < hs.size(); ++a) {
+      zhandle.push_back(hs[a]);
+      for (auto& pr : tmp[a]) {
+        zent.push_back(pr.first);
+        zent.push_back(pr.second);
+      }
+      zptr.push_back(int32_t(zent.size() / 2));
+      zmask.push_back(pinned[v] ? 1 : 0);
+      hpos[hs[a]] = -1;
+    }
+    zvptr[v + 1] = int32_t(zhandle.size());
+  }
+  const int64_t nz = int64_t(zhandle.size());
+  // stage-2 lists per coarse pair (i <= j): (k_v of (v,i), z index of (v,j))
+  std::vector<std::vector<std::pair<int, int>>> pl;
+  std::vector<std::pair<int, int>> pairs;
+  {
+    std::map<std::pair<int, int>, int> pid;
+    std::vector<std::vector<std::pair<int, int>>> lists;
+    for (int64_t v = 0; v < n; ++v) {
+      if (pinned[v]) continue;
+      for (int64_t k = B.vptr[v]; k < B.vptr[v + 1]; ++k) {
+        const int i = B.vhandle[k];
+        for (int32_t z = zvptr[v]; z < zvptr[v + 1]; ++z) {
+          const int j = zhandle[z];
+          if (j < i) continue;
+          auto key = std::make_pair(i, j);
+          auto it = pid.find(key);
+          int id;
+          if (it == pid.end()) {
+            id = int(lists.size());
+            pid[key] = id;
+            lists.emplace_back();
+          } else {
+            id = it->second;
+          }
+          lists[id].push_back({int(k), int(z)});
+        }
+      }
+    }
+    for (auto& kv : pid) {
+      pairs.push_back(kv.first);
+      pl.push_back(std::move(lists[kv.second]));
+    }
+  }
+  std::vector<int32_t> pair_ij, pptr(1, 0), pent;
+  for (size_t p = 0; p < pairs.size(); ++p) {
+    pair_ij.push_back(pairs[p].first);
+    pair_ij.push_back(pairs[p].second);
+    for (auto& e : pl[p]) {
+      pent.push_back(e.first);
+      pent.push_back(e.second);
+    }
+    pptr.push_back(int32_t(pent.size() / 2));
+  }
+  // coarse mass matrix (U^T M U) and its inverse for the coarse coordinates
+  const int r = 12 * m;
+  const int rp = coarse_pad(r);
+  std::vector<double> G(size_t(4 * m) * 4 * m, 0.0);  // sum_v m_v W_vi W_vj^T  [(i,k),(j,l)]
+  for (int64_t v = 0; v < n; ++v)
+    for (int64_t a = B.vptr[v]; a < B.vptr[v + 1]; ++a)
+      for (int64_t b = B.vptr[v]; b < B.vptr[v + 1]; ++b)
+        for (int k = 0; k < 4; ++k)
+          for (int l = 0; l < 4; ++l)
+            G[size_t(4 * B.vhandle[a] + k) * (4 * m) + 4 * B.vhandle[b] + l] += c->h_mass[v] * vw[4 * a + k] * vw[4 * b + l];
+  // invert G (SPD up to null directions) by Cholesky with pivot regularisation
+  const int g = 4 * m;
+  std::vector<double> Lg(G);
+  double gmax = 0.0;
+  for (int i = 0; i < g; ++i) gmax = std::max(gmax, G[size_t(i) * g + i]);
+  for (int k = 0; k < g; ++k) {
+    double d = Lg[size_t(k) * g + k];
+    for (int q = 0; q < k; ++q) d -= Lg[size_t(k) * g + q] * Lg[size_t(k) * g + q];
+    if (!(d > 1e-13 * gmax)) d = std::max(gmax, 1e-300);
+    d = std::sqrt(d);
+    Lg[size_t(k) * g + k] = d;
+    for (int i = k + 1; i < g; ++i) {
+      double s = Lg[size_t(i) * g + k];
+      for (int q = 0; q < k; ++q) s -= Lg[size_t(i) * g + q] * Lg[size_t(k) * g + q];
+      Lg[size_t(i) * g + k] = s / d;
+    }
+  }
+  std::vector<double> Ginv(size_t(g) * g, 0.0);
+  for (int col = 0; col < g; ++col) {
+    std::vector<double> y(g, 0.0);
+    for (int i = 0; i < g; ++i) {
+      double s = (i == col) ? 1.0 : 0.0;
+      for (int q = 0; q < i; ++q) s -= Lg[size_t(i) * g + q] * y[q];
+      y[i] = s / Lg[size_t(i) * g + i];
+    }
+    for (int i = g - 1; i >= 0; --i) {
+      double s = y[i];
+      for (int q = i + 1; q < g; ++q) s -= Lg[size_t(q) * g + i] * y[q];
+      y[i] = s / Lg[size_t(i) * g + i];
+    }
+    for (int i = 0; i < g; ++i) Ginv[size_t(i) * g + col] = y[i];
+  }
+  // expand to the r x r inverse of U^T M U = G (x) I_3 in (handle, a, k) order
+  std::vector<double> Minv(size_t(r) * r, 0.0);
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j)
+      for (int a = 0; a < 3; ++a)
+        for (int k = 0; k < 4; ++k)
+          for (int l = 0; l < 4; ++l)
+            Minv[size_t(12 * i + 4 * a + k) * r + 12 * j + 4 * a + l] = Ginv[size_t(4 * i + k) * g + 4 * j + l];
+  // upload
+  Basis& D = c->basis;
+  ms_status s;
+  if ((s = upload(c, &D.d_vptr, vptr.data(), vptr.size())) || (s = upload(c, &D.d_vh, B.vhandle.data(), nnz)) ||
+      (s = upload(c, &D.d_vw, vw.data(), vw.size())) || (s = upload(c, &D.d_hptr, hptr.data(), hptr.size())) ||
+      (s = upload(c, &D.d_hv, hv.data(), nnz)) || (s = upload(c, &D.d_hk, hk.data(), nnz)) ||
+      (s = upload(c, &D.d_hchunk, hchunk.data(), hchunk.size())) ||
+      (s = upload(c, &D.d_chunk_beg, chunk_beg.data(), chunk_beg.size())) ||
+      (s = alloc_n(c, &D.d_cpart, 12 * (chunk_beg.size() + 1))) ||
+      (s = upload(c, &D.d_zptr, zptr.data(), zptr.size())) || (s = upload(c, &D.d_zent, zent.data(), zent.size())) ||
+      (s = upload(c, &D.d_zmask, zmask.data(), zmask.size())) || (s = alloc_n(c, &D.d_Z, 36 * std::max<int64_t>(nz, 1))) ||
+      (s = upload(c, &D.d_pair_ij, pair_ij.data(), pair_ij.size())) ||
+      (s = upload(c, &D.d_pair_ptr, pptr.data(), pptr.size())) ||
+      (s = upload(c, &D.d_pair_ent, pent.data(), pent.size())) ||
+      (s = upload(c, &D.d_Minv, Minv.data(), Minv.size())) || (s = alloc_n(c, &c->d_c, r)) ||
+      (s = alloc_n(c, &c->d_e, r)) || (s = alloc_n(c, &c->d_Ac, size_t(r) * r)) ||
+      (s = alloc_n(c, &c->d_Lc, size_t(rp) * rp)) || (s = alloc_n(c, &c->d_Ainv, size_t(rp) * rp)) ||
+      (s = alloc_n(c, &c->d_Y, size_t(rp) * rp)) || (s = alloc_n(c, &c->d_Ldiag, size_t(rp) * 64)) ||
+      (s = alloc_n(c, &c->d_Linvd, size_t(rp) * 64)) || (s = alloc_n(c, &c->d_diag0, rp + 1)) || (s = alloc_n(c, &c->d_nreg, 4)))
+    return s;
+  D.m = m;
+  D.nnz = nnz;
+  D.nchunks = int32_t(chunk_beg.size()) - 1;
+  D.nz = nz;
+  D.npairs = int32_t(pairs.size());
+  D.pair_L = int64_t(pent.size() / 2);
+  D.z_L = int64_t(zent.size() / 2);
+  D.origins = std::move(B.origins);
+  D.vptr = std::move(B.vptr);
+  D.vhandle = std::move(B.vhandle);
+  D.vphi = std::move(B.vphi);
+  D.part = std::move(B.part);
+  c->r = r;
+  c->rp = rp;
+  c->has_basis = true;
+  c->coarse_valid = 0;
+  for (auto& row : c->cg_graph)
+    for (int pc = 1; pc < 3; ++pc)
+      if (row[pc]) {
+        (void)hipGraphExecDestroy(row[pc]);
+        row[pc] = nullptr;
+      }
+  return sync(c);
+}
+
+ms_status launch_galerkin(ms_ctx* c, int prec) {
+  if (!c->has_basis) return fail(c, MS_E_ORDER, "no basis");
+  Basis& D = c->basis;
+  MS_HIP(hipMemsetAsync(c->d_Ac, 0, size_t(c->r) * c->r * sizeof(double), c->stream));
+  if (D.nz > 0) {
+    if (prec == MS_PREC_FP64)
+      k_galerkin_z<double><<<nblocks(D.nz, 256), 256, 0, c->stream>>>(D.nz, c->pat.S, D.d_zptr, D.d_zent, c->d_vals, D.d_vw,
+                                                                      D.d_zmask, D.d_Z);
+    else
+      k_galerkin_z<float><<<nblocks(D.nz, 256), 256, 0, c->stream>>>(D.nz, c->pat.S, D.d_zptr, D.d_zent, c->d_vals32, D.d_vw,
+                                                                     D.d_zmask, D.d_Z);
+  }
+  if (D.npairs > 0)
+    k_galerkin_a<<<unsigned(D.npairs), 256, 0, c->stream>>>(c->r, D.d_pair_ij, D.d_pair_ptr, D.d_pair_ent, D.d_vw,
+                                                           D.d_Z, c->d_Ac);
+  return MS_OK;
+}
+
+// u += U A^-1 U^T v with v = r (from_w false) or the scratch vector w.
+void launch_coarse_correction(ms_ctx* c, int prec, bool from_w) {
+  Basis& D = c->basis;
+  (void)prec;
+  k_restrict<double><<<unsigned(D.nchunks), 64, 0, c->stream>>>(D.nchunks, D.d_chunk_beg, D.d_hv, D.d_hk, D.d_vw,
+                                                               from_w ? c->d_w : c->d_r, nullptr, D.d_cpart,
+                                                               c->d_scal);
+  k_chunk_sum<<<nblocks(c->r, 256), 256, 0, c->stream>>>(c->r, D.d_hchunk, D.d_cpart, c->d_c, c->d_scal);
+  k_gemv<<<nblocks(c->r, 4), 256, 0, c->stream>>>(c->r, c->rp, c->d_Ainv, c->d_c, c->d_e, c->d_scal);
+  k_prolong<double><<<nblocks(c->n, 64), 64, 0, c->stream>>>(c->n, D.d_vptr, D.d_vh, D.d_vw, c->d_e, c->d_pinned,
+                                                              c->d_u, c->d_scal);
+}
+
+// Preconditioner applied to r, with u = S r already in place.
+void launch_precond_apply(ms_ctx* c, int prec, int pc) {
+  if (pc == MS_PC_TWO_LEVEL_ADDITIVE) {
+    launch_coarse_correction(c, prec, false);
+  } else if (pc == MS_PC_TWO_LEVEL) {
+    launch_spmv_resid(c, prec, false);  // w = r - H u
+    launch_coarse_correction(c, prec, true);
+  }
+}
+
+// d = U e with e already computed (coarse start of PCG).
+__global__ void __launch_bounds__(64) k_prolong_set(int64_t n, const int32_t* __restrict__ vptr,
+                                                     const int32_t* __restrict__ vh, const double* __restrict__ vw,
+                                                     const double* __restrict__ e, const uint8_t* __restrict__ pinned,
+                                                     double* __restrict__ d, const double* __restrict__ scal) {
+  if (scal && scal[S_DONE] != 0.0) return;
+  const int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  if (!(pinned && pinned[v])) prolong_sum(vptr[v], vptr[v + 1], vh, vw, e, a0, a1, a2);
+  d[3 * v] = a0;
+  d[3 * v + 1] = a1;
+  d[3 * v + 2] = a2;
+}
+
+void launch_prolong_set_d(ms_ctx* c) {
+  Basis& D = c->basis;
+  k_prolong_set<<<nblocks(c->n, 64), 64, 0, c->stream>>>(c->n, D.d_vptr, D.d_vh, D.d_vw, c->d_e, c->d_pinned,
+                                                           c->d_d, c->d_scal);
+}
+
+// PCG starting vector d_0 = Q r_0 (r_0 = -g): afterwards r = -g - H d_0 and
+// u = S r.
+void launch_coarse_start(ms_ctx* c, int prec) {
+  Basis& D = c->basis;
+  k_restrict<double><<<unsigned(D.nchunks), 64, 0, c->stream>>>(D.nchunks, D.d_chunk_beg, D.d_hv, D.d_hk, D.d_vw,
+                                                               c->d_r, nullptr, D.d_cpart, c->d_scal);
+  k_chunk_sum<<<nblocks(c->r, 256), 256, 0, c->stream>>>(c->r, D.d_hchunk, D.d_cpart, c->d_c, c->d_scal);
+  k_gemv<<<nblocks(c->r, 4), 256, 0, c->stream>>>(c->r, c->rp, c->d_Ainv, c->d_c, c->d_e, c->d_scal);
+  launch_prolong_set_d(c);
+  launch_spmv_resid(c, prec, true);  // r = r - H d
+  launch_bj(c, prec);                 // u = S r
+}
+
+// q = (U^T M U)^-1 U^T M (x - x_rest), on the device; result copied to host.
+ms_status coarse_coordinates(ms_ctx* c, const double* x_dev, double* q_host, double* q_dev) {
+  Basis& D = c->basis;
+  // d_w <- x - rest (scratch)
+  k_sub<<<nblocks(3 * c->n, 256), 256, 0, c->stream>>>(3 * c->n, x_dev, c->d_rest, c->d_w);
+  k_restrict<double><<<unsigned(D.nchunks), 64, 0, c->stream>>>(D.nchunks, D.d_chunk_beg, D.d_hv, D.d_hk, D.d_vw,
+                                                               c->d_w, c->d_mass, D.d_cpart, nullptr);
+  k_chunk_sum<<<nblocks(c->r, 256), 256, 0, c->stream>>>(c->r, D.d_hchunk, D.d_cpart, c->d_c, nullptr);
+  k_gemv<<<nblocks(c->r, 4), 256, 0, c->stream>>>(c->r, c->r, D.d_Minv, c->d_c, q_dev ? q_dev : c->d_e, nullptr);
+  if (q_host)
+    MS_HIP(hipMemcpyAsync(q_host, q_dev ? q_dev : c->d_e, c->r * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  return sync(c);
+}
+
+}  // namespace ms
+
+using namespace ms;
+
+extern "C" {
+
+ms_status ms_build_basis(ms_ctx* c, const ms_basis_params* p) {
+  if (!c) return MS_E_ARG;
+  if (c->stage < 2) return fail(c, MS_E_ORDER, "upload mesh and material first");
+  ms_basis_params P;
+  if (p)
+    P = *p;
+  else
+    ms_basis_defaults(&P);
+  if (P.n_handles < 1 || P.n_handles > c->n) return fail(c, MS_E_ARG, "n_handles out of range");
+  Basis B;
+  ms_status s = build_basis_host(c, P, B);
+  if (s) return s;
+  return install_basis(c, std::move(B));
+}
+
+ms_status ms_set_basis(ms_ctx* c, int32_t m, const double* origins, const int64_t* vptr, const int32_t* vhandle,
+                       const double* vphi) {
+  if (!c || !origins || !vptr || !vhandle || !vphi || m < 1) return MS_E_ARG;
+  if (c->stage < 2) return fail(c, MS_E_ORDER, "upload mesh and material first");
+  Basis B;
+  B.m = m;
+  B.origins.assign(origins, origins + 3 * m);
+  B.vptr.assign(vptr, vptr + c->n + 1);
+  const int64_t nnz = B.vptr[c->n];
+  if (nnz < 0) return fail(c, MS_E_ARG, "bad vptr");
+  for (int64_t v = 0; v < c->n; ++v)
+    if (B.vptr[v + 1] < B.vptr[v]) return fail(c, MS_E_ARG, "vptr not monotone");
+  B.vhandle.assign(vhandle, vhandle + nnz);
+  B.vphi.assign(vphi, vphi + nnz);
+  B.part.assign(c->T, -1);
+  return install_basis(c, std::move(B));
+}
+
+ms_status ms_get_basis_size(const ms_ctx* c, int32_t* m, int64_t* nnz) {
+  if (!c || !m || !nnz) return MS_E_ARG;
+  if (!c->has_basis) return fail(const_cast<ms_ctx*>(c), MS_E_ORDER, "no basis");
+  *m = c->basis.m;
+  *nnz = c->basis.nnz;
+  return MS_OK;
+}
+
+ms_status ms_get_basis(const ms_ctx* c, double* origins, int64_t* vptr, int32_t* vhandle, double* vphi,
+                       int32_t* part) {
+  if (!c) return MS_E_ARG;
+  if (!c->has_basis) return fail(const_cast<ms_ctx*>(c), MS_E_ORDER, "no basis");
+  const Basis& B = c->basis;
+  if (origins) std::memcpy(origins, B.origins.data(), B.origins.size() * sizeof(double));
+  if (vptr) std::memcpy(vptr, B.vptr.data(), B.vptr.size() * sizeof(int64_t));
+  if (vhandle) std::memcpy(vhandle, B.vhandle.data(), B.vhandle.size() * sizeof(int32_t));
+  if (vphi) std::memcpy(vphi, B.vphi.data(), B.vphi.size() * sizeof(double));
+  if (part) {
+    if (B.part.empty())
+      std::fill(part, part + c->T, -1);
+    else
+      std::memcpy(part, B.part.data(), B.part.size() * sizeof(int32_t));
+  }
+  return MS_OK;
+}
+
+ms_status ms_get_coarse_matrix(ms_ctx* c, double* A) {
+  if (!c || !A) return MS_E_ARG;
+  if (!c->has_basis || !c->eval_valid) return fail(c, MS_E_ORDER, "needs a basis and ms_eval");
+  MS_HIP(hipMemcpyAsync(A, c->d_Ac, size_t(c->r) * c->r * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  return sync(c);
+}
+
+ms_status ms_get_coarse(ms_ctx* c, double* q) {
+  if (!c || !q) return MS_E_ARG;
+  if (!c->has_basis) return fail(c, MS_E_ORDER, "no basis");
+  if (c->stage < 3) return fail(c, MS_E_ORDER, "no state");
+  return coarse_coordinates(c, c->d_x, q, nullptr);
+}
+
+}  // extern "C"

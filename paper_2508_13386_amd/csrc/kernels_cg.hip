@@ -1,67 +1,71 @@
 // Sparse products and preconditioned conjugate gradient for H d = -g
 // (the Newton system of Sec. 3.1), on the sliced BSR3 layout.
 //
-// PCG uses the Chronopoulos-Gear recurrence, which needs one fused grid
+// PCG uses the Chronopoulos-Gear recurrence, which needs one grid-wide
 // reduction per iteration: per iteration two kernels run,
-//   k_cg_spmv    w = H u, the dots (r.u, w.u, r.r), and -- in the last block
-//                to finish -- the scalar recurrences alpha, beta and the
-//                convergence test, written to device memory;
-//   k_cg_update  p = u + beta p, s = w + beta s, d += alpha p, r -= alpha s,
-//                u = S r (3x3 block-Jacobi; the two-level preconditioner adds
-//                its coarse correction in separate kernels).
+//   k_cg_spmv    w = H u and per-block partials of (r.u, w.u, r.r);
+//   k_cg_update  every block sums the partials in the same fixed order, forms
+//                alpha, beta and the convergence test, then p = u + beta p,
+//                s = w + beta s, d += alpha p, r -= alpha s, u = S r (3x3
+//                block-Jacobi; the two-level preconditioner adds its coarse
+//                correction in separate kernels).
+// A wave serves one slice of S rows with 64/S lanes per row (S = 16, 32, 64),
+// the lanes of a row striding over its block columns and combining their
+// sums with cross-lane shuffles.
 // Every kernel returns at once when the device "done" flag is set, so fixed
 // chunks of iterations can be captured in a HIP graph and replayed with one
 // host synchronisation per chunk.
 #include <algorithm>
+#include <cstdlib>
+#include <type_traits>
 
 #include "ms_internal.h"
 #include "reduce.h"
 
 namespace ms {
 
-template <typename T>
-struct Acc;
-template <>
-struct Acc<double> {
-  using type = double;
-};
-template <>
-struct Acc<float> {
-  using type = float;
-};
-
-// y = A x, one wave per 64-row slice, one row per lane.
-template <typename VT, typename XT>
+// Row sums of y = A x for the rows of slice s handled by this wave; lane =
+// kq * S + r serves row S s + r and block columns k = kq, kq + R, ...
+// (R = 64 / S).  Every lane of a row returns the full sum.
+template <typename VT, typename XT, int S>
 __device__ __forceinline__ void row_product(int64_t s, int lane, const int32_t* __restrict__ slice_base,
                                             const int32_t* __restrict__ scol, const VT* __restrict__ vals,
-                                            const XT* __restrict__ x, typename Acc<VT>::type y[3]) {
-  using AT = typename Acc<VT>::type;
+                                            const XT* __restrict__ x, double y[3]) {
+  constexpr int R = 64 / S;
+  const int r = lane % S, kq = lane / S;
   const int base = slice_base[s];
-  const int width = (slice_base[s + 1] - base) / kSlice;
-  y[0] = y[1] = y[2] = AT(0);
-  for (int k = 0; k < width; ++k) {
-    const int64_t slot = int64_t(base) + int64_t(k) * kSlice + lane;
+  const int width = (slice_base[s + 1] - base) / S;
+  y[0] = y[1] = y[2] = 0.0;
+  for (int k = kq; k < width; k += R) {
+    const int64_t slot = int64_t(base) + int64_t(k) * S + r;
     const int col = scol[slot];
     if (col < 0) continue;
-    const VT* a = vals + 9 * slot - 8 * lane;
-    const AT x0 = AT(x[3 * int64_t(col)]), x1 = AT(x[3 * int64_t(col) + 1]), x2 = AT(x[3 * int64_t(col) + 2]);
-    y[0] += AT(a[0]) * x0 + AT(a[64]) * x1 + AT(a[128]) * x2;
-    y[1] += AT(a[192]) * x0 + AT(a[256]) * x1 + AT(a[320]) * x2;
-    y[2] += AT(a[384]) * x0 + AT(a[448]) * x1 + AT(a[512]) * x2;
+    const VT* a = vals + vbase(slot, S);
+    const double x0 = double(x[3 * int64_t(col)]), x1 = double(x[3 * int64_t(col) + 1]),
+                 x2 = double(x[3 * int64_t(col) + 2]);
+    y[0] += double(a[0]) * x0 + double(a[S]) * x1 + double(a[2 * S]) * x2;
+    y[1] += double(a[3 * S]) * x0 + double(a[4 * S]) * x1 + double(a[5 * S]) * x2;
+    y[2] += double(a[6 * S]) * x0 + double(a[7 * S]) * x1 + double(a[8 * S]) * x2;
   }
+#pragma unroll
+  for (int o = S; o < 64; o <<= 1)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) y[i] += __shfl_xor(y[i], o, 64);
 }
 
-template <typename VT, typename XT>
-__global__ void __launch_bounds__(64) k_spmv(int64_t n, const int32_t* __restrict__ slice_base,
-                                             const int32_t* __restrict__ scol, const VT* __restrict__ vals,
-                                             const XT* __restrict__ x, XT* __restrict__ y,
-                                             const uint8_t* __restrict__ pinned) {
-  const int64_t s = blockIdx.x;
-  const int lane = threadIdx.x;
-  const int64_t row = s * kSlice + lane;
-  typename Acc<VT>::type acc[3];
-  row_product<VT, XT>(s, lane, slice_base, scol, vals, x, acc);
-  if (row < n) {
+// One slice per wave, 4 waves per block.
+template <typename VT, typename XT, int S>
+__global__ void __launch_bounds__(256) k_spmv(int64_t n, int64_t nslices, const int32_t* __restrict__ slice_base,
+                                              const int32_t* __restrict__ scol, const VT* __restrict__ vals,
+                                              const XT* __restrict__ x, XT* __restrict__ y,
+                                              const uint8_t* __restrict__ pinned) {
+  const int64_t s = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  if (s >= nslices) return;
+  const int lane = threadIdx.x & 63;
+  double acc[3];
+  row_product<VT, XT, S>(s, lane, slice_base, scol, vals, x, acc);
+  const int64_t row = s * S + lane % S;
+  if (lane < S && row < n) {
     const bool pin = pinned && pinned[row];
     y[3 * row] = pin ? XT(0) : XT(acc[0]);
     y[3 * row + 1] = pin ? XT(0) : XT(acc[1]);
@@ -70,102 +74,125 @@ __global__ void __launch_bounds__(64) k_spmv(int64_t n, const int32_t* __restric
 }
 
 // ---------------------------------------------------------------------------
-// PCG kernels.  VT: matrix / iteration vector type (double or float); the
-// solution d and all dot products are accumulated in double.
+// PCG kernels.  VT is the type of the Hessian values and of the block-Jacobi
+// inverse (double, or float in mixed precision); every vector, product
+// accumulation and dot product is FP64.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void finalize_cg(double* scal, double gamma, double delta, double rho) {
-  const double it = scal[S_ITER];
-  if (rho <= scal[S_TOL2]) {
-    scal[S_DONE] = 1.0;
-    scal[S_RHO] = rho;
-    return;
-  }
-  if (it >= scal[S_MAXIT]) {
-    scal[S_DONE] = 2.0;
-    scal[S_RHO] = rho;
-    return;
-  }
-  double alpha, beta;
-  if (it == 0.0 || scal[S_GAMMA_OLD] == 0.0) {
+// Recurrence state of one PCG iteration, double-buffered between
+// iterations: [gamma_old, alpha_old, iter].
+enum { ST_GAMMA = 0, ST_ALPHA = 1, ST_ITER = 2, ST_N = 4 };
+
+// Chronopoulos-Gear scalars from the dots (gamma = r.u, delta = w.u, rho =
+// r.r).  Returns the done code (0 running, 1 converged, 2 iteration cap,
+// 3 loss of positive definiteness).
+__device__ __forceinline__ int cg_scalars(const double* st, const double* scal, double gamma, double delta,
+                                          double rho, double& alpha, double& beta) {
+  const double it = st[ST_ITER];
+  alpha = beta = 0.0;
+  if (rho <= scal[S_TOL2]) return 1;
+  if (it >= scal[S_MAXIT]) return 2;
+  if (it == 0.0 || st[ST_GAMMA] == 0.0) {
     beta = 0.0;
     alpha = gamma / delta;
   } else {
-    beta = gamma / scal[S_GAMMA_OLD];
-    alpha = gamma / (delta - beta * gamma / scal[S_ALPHA_OLD]);
+    beta = gamma / st[ST_GAMMA];
+    alpha = gamma / (delta - beta * gamma / st[ST_ALPHA]);
   }
-  if (!(alpha > 0.0) || !isfinite(alpha) || !isfinite(beta)) {  // loss of positive definiteness
-    scal[S_DONE] = 3.0;
-    scal[S_RHO] = rho;
-    return;
-  }
-  scal[S_ALPHA] = alpha;
-  scal[S_BETA] = beta;
-  scal[S_ALPHA_OLD] = alpha;
-  scal[S_GAMMA_OLD] = gamma;
-  scal[S_RHO] = rho;
-  scal[S_ITER] = it + 1.0;
+  if (!(alpha > 0.0) || !isfinite(alpha) || !isfinite(beta)) return 3;
+  return 0;
 }
 
-template <typename VT>
-__global__ void __launch_bounds__(64) k_cg_spmv(int64_t n, const int32_t* __restrict__ slice_base,
-                                                const int32_t* __restrict__ scol, const VT* __restrict__ vals,
-                                                const VT* __restrict__ u, VT* __restrict__ w,
-                                                const VT* __restrict__ r, const uint8_t* __restrict__ pinned,
-                                                double* __restrict__ scal, double* __restrict__ part,
-                                                unsigned* __restrict__ counter) {
+// w = H u and the block partials of (r.u, w.u, r.r); no grid-wide step here:
+// the update kernel reduces the partials.
+template <typename VT, int S>
+__global__ void __launch_bounds__(256) k_cg_spmv(int64_t n, int64_t nslices, const int32_t* __restrict__ slice_base,
+                                                 const int32_t* __restrict__ scol, const VT* __restrict__ vals,
+                                                 const double* __restrict__ u, double* __restrict__ w,
+                                                 const double* __restrict__ r, const uint8_t* __restrict__ pinned,
+                                                 const double* __restrict__ scal, double* __restrict__ part) {
   if (scal[S_DONE] != 0.0) return;
-  const int64_t s = blockIdx.x;
-  const int lane = threadIdx.x;
-  const int64_t row = s * kSlice + lane;
-  typename Acc<VT>::type acc[3];
-  row_product<VT, VT>(s, lane, slice_base, scol, vals, u, acc);
+  const int64_t s = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int64_t row = s * S + lane % S;
   double dots[3] = {0.0, 0.0, 0.0};
-  if (row < n) {
-    const bool pin = pinned[row];
+  if (s < nslices) {
+    double acc[3];
+    row_product<VT, double, S>(s, lane, slice_base, scol, vals, u, acc);
+    if (lane < S && row < n) {
+      const bool pin = pinned[row];
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      const VT wi = pin ? VT(0) : VT(acc[i]);
-      w[3 * row + i] = wi;
-      const double ui = double(u[3 * row + i]), ri = double(r[3 * row + i]);
-      dots[0] += ri * ui;
-      dots[1] += double(wi) * ui;
-      dots[2] += ri * ri;
+      for (int i = 0; i < 3; ++i) {
+        const double wi = pin ? 0.0 : acc[i];
+        w[3 * row + i] = wi;
+        const double ui = u[3 * row + i], ri = r[3 * row + i];
+        dots[0] += ri * ui;
+        dots[1] += wi * ui;
+        dots[2] += ri * ri;
+      }
     }
   }
-  if (grid_sum<3>(dots, part, counter) && threadIdx.x == 0) finalize_cg(scal, dots[0], dots[1], dots[2]);
+  block_sum<3>(dots);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) part[3 * blockIdx.x + i] = dots[i];
 }
 
 // Block-Jacobi application u = Dinv r for one vertex.
 template <typename VT>
-__device__ __forceinline__ void bj_apply(const VT* __restrict__ Dinv, int64_t v, const VT r[3], VT u[3]) {
+__device__ __forceinline__ void bj_apply(const VT* __restrict__ Dinv, int64_t v, const double r[3], double u[3]) {
   const VT* D = Dinv + 9 * v;
-  u[0] = D[0] * r[0] + D[1] * r[1] + D[2] * r[2];
-  u[1] = D[3] * r[0] + D[4] * r[1] + D[5] * r[2];
-  u[2] = D[6] * r[0] + D[7] * r[1] + D[8] * r[2];
+  u[0] = double(D[0]) * r[0] + double(D[1]) * r[1] + double(D[2]) * r[2];
+  u[1] = double(D[3]) * r[0] + double(D[4]) * r[1] + double(D[5]) * r[2];
+  u[2] = double(D[6]) * r[0] + double(D[7]) * r[1] + double(D[8]) * r[2];
 }
 
+// Every block reduces the SpMV partials in the same order (identical,
+// deterministic scalars in all blocks), block 0 records the recurrence state
+// and the done flag, then p = u + beta p, s = w + beta s, d += alpha p,
+// r -= alpha s, u = S r.
 template <typename VT>
-__global__ void __launch_bounds__(256) k_cg_update(int64_t n, VT* __restrict__ p, VT* __restrict__ s,
-                                                   double* __restrict__ d, VT* __restrict__ r,
-                                                   VT* __restrict__ u, const VT* __restrict__ w,
-                                                   const VT* __restrict__ Dinv, const double* __restrict__ scal) {
+__global__ void __launch_bounds__(256) k_cg_update(int64_t n, int nparts, const double* __restrict__ part,
+                                                   const double* __restrict__ st_in, double* __restrict__ st_out,
+                                                   double* __restrict__ p, double* __restrict__ s,
+                                                   double* __restrict__ d, double* __restrict__ r,
+                                                   double* __restrict__ u, const double* __restrict__ w,
+                                                   const VT* __restrict__ Dinv, double* __restrict__ scal) {
   if (scal[S_DONE] != 0.0) return;
+  double dots[3] = {0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < nparts; b += blockDim.x)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) dots[i] += part[3 * b + i];
+  block_sum<3>(dots);
+  double alpha, beta;
+  const int code = cg_scalars(st_in, scal, dots[0], dots[1], dots[2], alpha, beta);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    scal[S_RHO] = dots[2];
+    if (code != 0) {
+      scal[S_DONE] = double(code);
+      scal[S_ITER] = st_in[ST_ITER];
+    } else {
+      st_out[ST_GAMMA] = dots[0];
+      st_out[ST_ALPHA] = alpha;
+      st_out[ST_ITER] = st_in[ST_ITER] + 1.0;
+      scal[S_ITER] = st_in[ST_ITER] + 1.0;
+    }
+  }
+  if (code != 0) return;
   const int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (v >= n) return;
-  const double alpha = scal[S_ALPHA], beta = scal[S_BETA];
-  VT rr[3];
+  double rr[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     const int64_t k = 3 * v + i;
-    const VT pi = VT(double(u[k]) + beta * double(p[k]));
-    const VT si = VT(double(w[k]) + beta * double(s[k]));
+    const double pi = u[k] + beta * p[k];
+    const double si = w[k] + beta * s[k];
     p[k] = pi;
     s[k] = si;
-    d[k] += alpha * double(pi);
-    rr[i] = VT(double(r[k]) - alpha * double(si));
+    d[k] += alpha * pi;
+    rr[i] = r[k] - alpha * si;
     r[k] = rr[i];
   }
-  VT uu[3];
+  double uu[3];
   bj_apply<VT>(Dinv, v, rr, uu);
 #pragma unroll
   for (int i = 0; i < 3; ++i) u[3 * v + i] = uu[i];
@@ -177,29 +204,30 @@ __global__ void __launch_bounds__(256) k_cg_update(int64_t n, VT* __restrict__ p
 // iteration.
 template <typename VT>
 __global__ void __launch_bounds__(256) k_cg_init(int64_t n, const double* __restrict__ g,
-                                                 const uint8_t* __restrict__ pinned, VT* __restrict__ p,
-                                                 VT* __restrict__ s, double* __restrict__ d, VT* __restrict__ r,
-                                                 VT* __restrict__ u, const VT* __restrict__ Dinv, double eta_max,
-                                                 double eta_min, int first, double maxit, double* __restrict__ scal,
+                                                 const uint8_t* __restrict__ pinned, double* __restrict__ p,
+                                                 double* __restrict__ s, double* __restrict__ d, double* __restrict__ r,
+                                                 double* __restrict__ u, const VT* __restrict__ Dinv, double eta_max,
+                                                 double eta_min, int first, int forcing, double maxit,
+                                                 double* __restrict__ st0, double* __restrict__ scal,
                                                  double* __restrict__ part,
                                                  unsigned* __restrict__ counter) {
   const int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   double rho[1] = {0.0};
   if (v < n) {
     const bool pin = pinned[v];
-    VT rr[3];
+    double rr[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       const int64_t k = 3 * v + i;
       const double gi = pin ? 0.0 : -g[k];
-      rr[i] = VT(gi);
-      r[k] = rr[i];
-      p[k] = VT(0);
-      s[k] = VT(0);
+      rr[i] = gi;
+      r[k] = gi;
+      p[k] = 0.0;
+      s[k] = 0.0;
       d[k] = 0.0;
       rho[0] += gi * gi;
     }
-    VT uu[3];
+    double uu[3];
     bj_apply<VT>(Dinv, v, rr, uu);
 #pragma unroll
     for (int i = 0; i < 3; ++i) u[3 * v + i] = uu[i];
@@ -208,13 +236,29 @@ __global__ void __launch_bounds__(256) k_cg_init(int64_t n, const double* __rest
     scal[S_RHO0] = rho[0];
     scal[S_RHO] = rho[0];
     if (first) scal[S_G0SQ] = rho[0];
-    double eta = scal[S_G0SQ] > 0.0 ? sqrt(sqrt(rho[0] / scal[S_G0SQ])) : 1.0;
+    double eta;
+    if (forcing == 1) {
+      // Eisenstat-Walker choice 2 (gamma 0.9, exponent 2) with its safeguard
+      if (first || !(scal[S_GPREV] > 0.0)) {
+        eta = eta_max;
+      } else {
+        eta = 0.9 * rho[0] / scal[S_GPREV];  // 0.9 (||g_k|| / ||g_k-1||)^2
+        const double safe = 0.9 * scal[S_ETAPREV] * scal[S_ETAPREV];
+        if (safe > 0.1) eta = fmax(eta, safe);
+      }
+    } else {
+      eta = scal[S_G0SQ] > 0.0 ? sqrt(sqrt(rho[0] / scal[S_G0SQ])) : 1.0;
+    }
     eta = fmin(eta_max, fmax(eta_min, eta));
+    scal[S_GPREV] = rho[0];
+    scal[S_ETAPREV] = eta;
+    scal[S_ETA] = eta;
     scal[S_TOL2] = eta * eta * rho[0];
     scal[S_ITER] = 0.0;
     scal[S_MAXIT] = maxit;
-    scal[S_GAMMA_OLD] = 0.0;
-    scal[S_ALPHA_OLD] = 1.0;
+    st0[ST_GAMMA] = 0.0;
+    st0[ST_ALPHA] = 1.0;
+    st0[ST_ITER] = 0.0;
     scal[S_DONE] = rho[0] > 0.0 ? 0.0 : 1.0;
   }
 }
@@ -222,15 +266,16 @@ __global__ void __launch_bounds__(256) k_cg_init(int64_t n, const double* __rest
 // Inverse of each diagonal 3x3 block (cofactor formula in double); pinned
 // vertices get a zero block so that the preconditioned vectors vanish there.
 template <typename VT>
-__global__ void k_block_jacobi(int64_t n, const int32_t* __restrict__ diag_slot, const VT* __restrict__ vals,
-                               const uint8_t* __restrict__ pinned, VT* __restrict__ Dinv) {
+__global__ void k_block_jacobi(int64_t n, int S, const int32_t* __restrict__ diag_slot,
+                               const VT* __restrict__ vals, const uint8_t* __restrict__ pinned,
+                               VT* __restrict__ Dinv) {
   const int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (v >= n) return;
   const int64_t slot = diag_slot[v];
-  const VT* a = vals + 9 * slot - 8 * (slot & 63);
+  const VT* a = vals + vbase(slot, S);
   double m[9];
 #pragma unroll
-  for (int c = 0; c < 9; ++c) m[c] = double(a[64 * c]);
+  for (int c = 0; c < 9; ++c) m[c] = double(a[S * c]);
   double inv[9];
   inv[0] = m[4] * m[8] - m[5] * m[7];
   inv[1] = m[2] * m[7] - m[1] * m[8];
@@ -278,35 +323,138 @@ __global__ void k_fill(int64_t len, double* __restrict__ y, double v) {
   if (i < len) y[i] = v;
 }
 template <typename VT>
-__global__ void k_extract(int64_t nnzb, const int64_t* __restrict__ slot_of, const VT* __restrict__ vals,
+__global__ void k_extract(int64_t nnzb, int S, const int64_t* __restrict__ slot_of, const VT* __restrict__ vals,
                           double* __restrict__ out) {
   const int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (b >= nnzb) return;
   const int64_t slot = slot_of[b];
-  const VT* a = vals + 9 * slot - 8 * (slot & 63);
+  const VT* a = vals + vbase(slot, S);
 #pragma unroll
-  for (int c = 0; c < 9; ++c) out[9 * b + c] = double(a[64 * c]);
+  for (int c = 0; c < 9; ++c) out[9 * b + c] = double(a[S * c]);
+}
+
+// t = r - H x (zero on pinned rows); x is the iteration vector (VT) or the
+// FP64 solution d.  In-place use (t == r) is safe: each row reads only its
+// own r entry.
+template <typename VT, int S>
+__global__ void __launch_bounds__(256) k_spmv_resid(int64_t n, int64_t nslices, const int32_t* __restrict__ slice_base,
+                                                    const int32_t* __restrict__ scol, const VT* __restrict__ vals,
+                                                    const double* __restrict__ x, const double* r, double* t,
+                                                    const uint8_t* __restrict__ pinned,
+                                                    const double* __restrict__ scal) {
+  if (scal[S_DONE] != 0.0) return;
+  const int64_t s = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  if (s >= nslices) return;
+  const int lane = threadIdx.x & 63;
+  const int64_t row = s * S + lane % S;
+  double acc[3];
+  row_product<VT, double, S>(s, lane, slice_base, scol, vals, x, acc);
+  if (lane < S && row < n) {
+    const bool pin = pinned[row];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) t[3 * row + i] = pin ? 0.0 : r[3 * row + i] - acc[i];
+  }
+}
+
+template <typename VT>
+__global__ void __launch_bounds__(256) k_bj(int64_t n, const double* __restrict__ r, double* __restrict__ u,
+                                            const VT* __restrict__ Dinv, const double* __restrict__ scal) {
+  if (scal[S_DONE] != 0.0) return;
+  const int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  double rr[3] = {r[3 * v], r[3 * v + 1], r[3 * v + 2]}, uu[3];
+  bj_apply<VT>(Dinv, v, rr, uu);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) u[3 * v + i] = uu[i];
 }
 
 static inline unsigned nblocks(int64_t n, int b) { return unsigned((n + b - 1) / b); }
 
-void launch_spmv(ms_ctx* c, int prec, const double* x, double* y) {
-  // FP64 vectors; the FP32 matrix variant converts on load
-  if (prec == MS_PREC_FP64)
-    k_spmv<double, double><<<unsigned(c->pat.nslices), 64, 0, c->stream>>>(c->n, c->pat.d_slice_base, c->pat.d_col,
-                                                                          c->d_vals, x, y, nullptr);
+// Calls f(std::integral_constant<int, S>) for the runtime slice height.
+template <typename F>
+static void with_slice(int S, F&& f) {
+  if (S == 16)
+    f(std::integral_constant<int, 16>());
+  else if (S == 32)
+    f(std::integral_constant<int, 32>());
   else
-    k_spmv<float, double><<<unsigned(c->pat.nslices), 64, 0, c->stream>>>(c->n, c->pat.d_slice_base, c->pat.d_col,
-                                                                         c->d_vals32, x, y, nullptr);
+    f(std::integral_constant<int, 64>());
+}
+
+void launch_spmv_resid(ms_ctx* c, int prec, bool from_d) {
+  const int64_t ns = c->pat.nslices;
+  const unsigned nbs = unsigned((ns + 3) / 4);
+  const double* x = from_d ? c->d_d : c->d_u;
+  double* t = from_d ? c->d_r : c->d_w;
+  with_slice(c->pat.S, [&](auto SS) {
+    constexpr int S = decltype(SS)::value;
+    if (prec == MS_PREC_FP64)
+      k_spmv_resid<double, S><<<nbs, 256, 0, c->stream>>>(c->n, ns, c->pat.d_slice_base, c->pat.d_col, c->d_vals, x,
+                                                          c->d_r, t, c->d_pinned, c->d_scal);
+    else
+      k_spmv_resid<float, S><<<nbs, 256, 0, c->stream>>>(c->n, ns, c->pat.d_slice_base, c->pat.d_col, c->d_vals32, x,
+                                                         c->d_r, t, c->d_pinned, c->d_scal);
+  });
+}
+
+void launch_bj(ms_ctx* c, int prec) {
+  if (prec == MS_PREC_FP64)
+    k_bj<double><<<nblocks(c->n, 256), 256, 0, c->stream>>>(c->n, c->d_r, c->d_u, c->d_Dinv, c->d_scal);
+  else
+    k_bj<float><<<nblocks(c->n, 256), 256, 0, c->stream>>>(c->n, c->d_r, c->d_u, c->d_Dinv32, c->d_scal);
+}
+
+void launch_spmv(ms_ctx* c, int prec, const double* x, double* y) {
+  const int64_t ns = c->pat.nslices;
+  with_slice(c->pat.S, [&](auto SS) {
+    constexpr int S = decltype(SS)::value;
+    if (prec == MS_PREC_FP64)
+      k_spmv<double, double, S><<<unsigned((ns + 3) / 4), 256, 0, c->stream>>>(c->n, ns, c->pat.d_slice_base,
+                                                                               c->pat.d_col, c->d_vals, x, y, nullptr);
+    else
+      k_spmv<float, double, S><<<unsigned((ns + 3) / 4), 256, 0, c->stream>>>(c->n, ns, c->pat.d_slice_base,
+                                                                              c->pat.d_col, c->d_vals32, x, y, nullptr);
+  });
+}
+
+// Average duration (ms) of an FP64 SpMV on a candidate layout with random
+// values; -1 on a HIP error.
+double time_spmv_layout(ms_ctx* c, int S, const int32_t* d_slice_base, const int32_t* d_col, int64_t nslices,
+                        int64_t nslots, int reps) {
+  double *vals = nullptr, *x = nullptr, *y = nullptr;
+  if (alloc_n(c, &vals, 9 * nslots) || alloc_n(c, &x, 3 * c->n) || alloc_n(c, &y, 3 * c->n)) return -1.0;
+  k_fill<<<nblocks(9 * nslots, 256), 256, 0, c->stream>>>(9 * nslots, vals, 0.5);
+  k_fill<<<nblocks(3 * c->n, 256), 256, 0, c->stream>>>(3 * c->n, x, 1.0);
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return -1.0;
+  auto run = [&]() {
+    with_slice(S, [&](auto SS) {
+      constexpr int SV = decltype(SS)::value;
+      k_spmv<double, double, SV><<<unsigned((nslices + 3) / 4), 256, 0, c->stream>>>(c->n, nslices, d_slice_base,
+                                                                                     d_col, vals, x, y, nullptr);
+    });
+  };
+  for (int i = 0; i < 3; ++i) run();
+  (void)hipEventRecord(e0, c->stream);
+  for (int i = 0; i < reps; ++i) run();
+  (void)hipEventRecord(e1, c->stream);
+  float ms = -1.0f;
+  if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) ms = -1.0f;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  dfree(c, vals);
+  dfree(c, x);
+  dfree(c, y);
+  return ms < 0 ? -1.0 : double(ms) / reps;
 }
 
 void launch_block_jacobi(ms_ctx* c, int prec) {
   if (prec == MS_PREC_FP64)
-    k_block_jacobi<double><<<nblocks(c->n, 256), 256, 0, c->stream>>>(c->n, c->pat.d_diag_slot, c->d_vals,
+    k_block_jacobi<double><<<nblocks(c->n, 256), 256, 0, c->stream>>>(c->n, c->pat.S, c->pat.d_diag_slot, c->d_vals,
                                                                      c->d_pinned, c->d_Dinv);
   else
-    k_block_jacobi<float><<<nblocks(c->n, 256), 256, 0, c->stream>>>(c->n, c->pat.d_diag_slot, c->d_vals32,
-                                                                    c->d_pinned, c->d_Dinv32);
+    k_block_jacobi<float><<<nblocks(c->n, 256), 256, 0, c->stream>>>(c->n, c->pat.S, c->pat.d_diag_slot,
+                                                                    c->d_vals32, c->d_pinned, c->d_Dinv32);
 }
 
 void launch_dots(ms_ctx* c, const double* a0, const double* b0, const double* a1, const double* b1,
@@ -323,37 +471,46 @@ void launch_fill(ms_ctx* c, double* p, double v, int64_t len) {
 }
 void launch_extract_bsr(ms_ctx* c, const int64_t* slot_of, int64_t nnzb, double* out, int prec) {
   if (prec == MS_PREC_FP64)
-    k_extract<double><<<nblocks(nnzb, 256), 256, 0, c->stream>>>(nnzb, slot_of, c->d_vals, out);
+    k_extract<double><<<nblocks(nnzb, 256), 256, 0, c->stream>>>(nnzb, c->pat.S, slot_of, c->d_vals, out);
   else
-    k_extract<float><<<nblocks(nnzb, 256), 256, 0, c->stream>>>(nnzb, slot_of, c->d_vals32, out);
+    k_extract<float><<<nblocks(nnzb, 256), 256, 0, c->stream>>>(nnzb, c->pat.S, slot_of, c->d_vals32, out);
 }
 
-void launch_cg_init(ms_ctx* c, int prec, double eta_max, double eta_min, bool first, int max_it) {
+void launch_cg_init(ms_ctx* c, int prec, double eta_max, double eta_min, bool first, int max_it, int forcing) {
   const unsigned nb = nblocks(c->n, 256);
   if (prec == MS_PREC_FP64)
     k_cg_init<double><<<nb, 256, 0, c->stream>>>(c->n, c->d_g, c->d_pinned, c->d_p, c->d_s, c->d_d, c->d_r, c->d_u,
-                                                 c->d_Dinv, eta_max, eta_min, first ? 1 : 0, double(max_it), c->d_scal, c->d_part,
+                                                 c->d_Dinv, eta_max, eta_min, first ? 1 : 0, forcing, double(max_it), c->d_cgst, c->d_scal, c->d_part,
                                                  c->d_counter);
   else
-    k_cg_init<float><<<nb, 256, 0, c->stream>>>(c->n, c->d_g, c->d_pinned, c->f_p, c->f_s, c->d_d, c->f_r, c->f_u,
-                                                c->d_Dinv32, eta_max, eta_min, first ? 1 : 0, double(max_it), c->d_scal, c->d_part,
+    k_cg_init<float><<<nb, 256, 0, c->stream>>>(c->n, c->d_g, c->d_pinned, c->d_p, c->d_s, c->d_d, c->d_r, c->d_u,
+                                                c->d_Dinv32, eta_max, eta_min, first ? 1 : 0, forcing, double(max_it), c->d_cgst, c->d_scal, c->d_part,
                                                 c->d_counter);
 }
 
-void launch_cg_iteration(ms_ctx* c, int prec, int pc) {
-  const unsigned ns = unsigned(c->pat.nslices), nb = nblocks(c->n, 256);
-  if (prec == MS_PREC_FP64) {
-    k_cg_spmv<double><<<ns, 64, 0, c->stream>>>(c->n, c->pat.d_slice_base, c->pat.d_col, c->d_vals, c->d_u, c->d_w,
-                                                c->d_r, c->d_pinned, c->d_scal, c->d_part, c->d_counter);
-    k_cg_update<double><<<nb, 256, 0, c->stream>>>(c->n, c->d_p, c->d_s, c->d_d, c->d_r, c->d_u, c->d_w, c->d_Dinv,
-                                                   c->d_scal);
-  } else {
-    k_cg_spmv<float><<<ns, 64, 0, c->stream>>>(c->n, c->pat.d_slice_base, c->pat.d_col, c->d_vals32, c->f_u, c->f_w,
-                                               c->f_r, c->d_pinned, c->d_scal, c->d_part, c->d_counter);
-    k_cg_update<float><<<nb, 256, 0, c->stream>>>(c->n, c->f_p, c->f_s, c->d_d, c->f_r, c->f_u, c->f_w, c->d_Dinv32,
-                                                  c->d_scal);
-  }
-  if (pc == MS_PC_TWO_LEVEL) launch_coarse_correction(c, prec);
+// One PCG iteration; `parity` selects the recurrence-state buffers
+// (iteration k reads state k % 2 and writes (k + 1) % 2).
+void launch_cg_iteration(ms_ctx* c, int prec, int pc, int parity) {
+  const int64_t ns = c->pat.nslices;
+  const unsigned nbs = unsigned((ns + 3) / 4), nb = nblocks(c->n, 256);
+  const double* st_in = c->d_cgst + ST_N * parity;
+  double* st_out = c->d_cgst + ST_N * (1 - parity);
+  with_slice(c->pat.S, [&](auto SS) {
+    constexpr int S = decltype(SS)::value;
+    if (prec == MS_PREC_FP64)
+      k_cg_spmv<double, S><<<nbs, 256, 0, c->stream>>>(c->n, ns, c->pat.d_slice_base, c->pat.d_col, c->d_vals, c->d_u,
+                                                       c->d_w, c->d_r, c->d_pinned, c->d_scal, c->d_part);
+    else
+      k_cg_spmv<float, S><<<nbs, 256, 0, c->stream>>>(c->n, ns, c->pat.d_slice_base, c->pat.d_col, c->d_vals32, c->d_u,
+                                                      c->d_w, c->d_r, c->d_pinned, c->d_scal, c->d_part);
+  });
+  if (prec == MS_PREC_FP64)
+    k_cg_update<double><<<nb, 256, 0, c->stream>>>(c->n, int(nbs), c->d_part, st_in, st_out, c->d_p, c->d_s, c->d_d,
+                                                   c->d_r, c->d_u, c->d_w, c->d_Dinv, c->d_scal);
+  else
+    k_cg_update<float><<<nb, 256, 0, c->stream>>>(c->n, int(nbs), c->d_part, st_in, st_out, c->d_p, c->d_s, c->d_d,
+                                                  c->d_r, c->d_u, c->d_w, c->d_Dinv32, c->d_scal);
+  launch_precond_apply(c, prec, pc);
 }
 
 // ---------------------------------------------------------------------------
@@ -366,17 +523,43 @@ ms_status mat_build(ms_mat* A, int64_t n, const int32_t* row_ptr, const int32_t*
   ms_ctx* c = &A->ctx;
   Pattern& P = c->pat;
   P.n = n;
+  c->n = n;
   P.nnzb = row_ptr[n];
-  P.nslices = (n + kSlice - 1) / kSlice;
-  P.h_slice_base.assign(P.nslices + 1, 0);
-  for (int64_t s = 0; s < P.nslices; ++s) {
-    int32_t w = 0;
-    for (int64_t r = s * kSlice; r < std::min<int64_t>(n, (s + 1) * kSlice); ++r)
-      w = std::max(w, row_ptr[r + 1] - row_ptr[r]);
-    P.h_slice_base[s + 1] = P.h_slice_base[s] + w * kSlice;
+  for (int64_t b = 0; b < P.nnzb; ++b)
+    if (col[b] < 0 || col[b] >= n) return fail(c, MS_E_ARG, "column index out of range");
+  for (int64_t r = 0; r < n; ++r)
+    if (row_ptr[r + 1] < row_ptr[r]) return fail(c, MS_E_ARG, "row_ptr not monotone");
+  // slice height: MS_SLICE, else the fastest candidate on this pattern
+  int S = 0;
+  if (const char* e = std::getenv("MS_SLICE")) S = std::atoi(e);
+  auto layout = [&](int cand, std::vector<int32_t>& sb, std::vector<int32_t>& sc, int& mw) {
+    slice_layout(n, row_ptr, cand, sb, mw);
+    sc.assign(sb.back(), -1);
+    for (int64_t r = 0; r < n; ++r)
+      for (int32_t k = 0; k < row_ptr[r + 1] - row_ptr[r]; ++k)
+        sc[sb[r / cand] + int64_t(k) * cand + r % cand] = col[row_ptr[r] + k];
+  };
+  if (S != 16 && S != 32 && S != 64) {
+    double best = 1e300;
+    for (int cand : {16, 32, 64}) {
+      std::vector<int32_t> sb, sc;
+      int mw = 0;
+      layout(cand, sb, sc, mw);
+      int32_t *d_sb = nullptr, *d_sc = nullptr;
+      ms_status st;
+      if ((st = upload(c, &d_sb, sb.data(), sb.size())) || (st = upload(c, &d_sc, sc.data(), sc.size()))) return st;
+      const double t = time_spmv_layout(c, cand, d_sb, d_sc, int64_t(sb.size()) - 1, sb.back(), 10);
+      dfree(c, d_sb);
+      dfree(c, d_sc);
+      if (t < 0) return fail(c, MS_E_DEVICE, "SpMV layout timing failed");
+      if (t < best) best = t, S = cand;
+    }
   }
+  P.S = S;
+  std::vector<int32_t> scol;
+  layout(S, P.h_slice_base, scol, P.maxw);
+  P.nslices = int64_t(P.h_slice_base.size()) - 1;
   P.nslots = P.h_slice_base[P.nslices];
-  std::vector<int32_t> scol(P.nslots, -1);
   const bool f32 = A->dtype == 1;
   std::vector<double> v64;
   std::vector<float> v32;
@@ -385,14 +568,12 @@ ms_status mat_build(ms_mat* A, int64_t n, const int32_t* row_ptr, const int32_t*
   else
     v64.assign(9 * P.nslots, 0.0);
   for (int64_t r = 0; r < n; ++r) {
-    const int64_t s = r / kSlice, lane = r % kSlice;
+    const int64_t s = r / S, lane = r % S;
     for (int32_t k = 0; k < row_ptr[r + 1] - row_ptr[r]; ++k) {
       const int64_t b = row_ptr[r] + k;
-      if (col[b] < 0 || col[b] >= n) return fail(c, MS_E_ARG, "column index out of range");
-      const int64_t slot = P.h_slice_base[s] + int64_t(k) * kSlice + lane;
-      scol[slot] = col[b];
+      const int64_t slot = P.h_slice_base[s] + int64_t(k) * S + lane;
       for (int cc = 0; cc < 9; ++cc) {
-        const int64_t vi = 9 * slot - 8 * lane + 64 * cc;
+        const int64_t vi = vbase(slot, S) + int64_t(S) * cc;
         if (f32)
           v32[vi] = float(vals[9 * b + cc]);
         else
@@ -410,19 +591,22 @@ ms_status mat_build(ms_mat* A, int64_t n, const int32_t* row_ptr, const int32_t*
   }
   const double vb = f32 ? 4.0 : 8.0;
   A->bytes = double(P.nnzb) * (9 * vb + 4) + 4.0 * double(P.nslices + 1) + 2.0 * 3 * n * vb;
-  c->n = n;
   return MS_OK;
 }
 
 void mat_spmv(ms_mat* A, const void* x, void* y) {
   ms_ctx* c = &A->ctx;
-  if (A->dtype == 1)
-    k_spmv<float, float><<<unsigned(c->pat.nslices), 64, 0, c->stream>>>(
-        c->n, c->pat.d_slice_base, c->pat.d_col, c->d_vals32, static_cast<const float*>(x), static_cast<float*>(y),
-        nullptr);
-  else
-    k_spmv<double, double><<<unsigned(c->pat.nslices), 64, 0, c->stream>>>(
-        c->n, c->pat.d_slice_base, c->pat.d_col, c->d_vals, static_cast<const double*>(x),
-        static_cast<double*>(y), nullptr);
+  const int64_t ns = c->pat.nslices;
+  with_slice(c->pat.S, [&](auto SS) {
+    constexpr int S = decltype(SS)::value;
+    if (A->dtype == 1)
+      k_spmv<float, float, S><<<unsigned((ns + 3) / 4), 256, 0, c->stream>>>(
+          c->n, ns, c->pat.d_slice_base, c->pat.d_col, c->d_vals32, static_cast<const float*>(x),
+          static_cast<float*>(y), nullptr);
+    else
+      k_spmv<double, double, S><<<unsigned((ns + 3) / 4), 256, 0, c->stream>>>(
+          c->n, ns, c->pat.d_slice_base, c->pat.d_col, c->d_vals, static_cast<const double*>(x),
+          static_cast<double*>(y), nullptr);
+  });
 }
 }  // namespace ms

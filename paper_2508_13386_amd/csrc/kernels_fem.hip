@@ -235,12 +235,19 @@ __global__ void k_gather_grad(int64_t n, const int32_t* __restrict__ vt_ptr, con
   const int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (v >= n) return;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-  for (int k = vt_ptr[v]; k < vt_ptr[v + 1]; ++k) {
-    const int code = vt_code[k];
-    const double* p = ge + 12 * int64_t(code >> 2) + 3 * (code & 3);
-    s0 += p[0];
-    s1 += p[1];
-    s2 += p[2];
+  const int k1 = vt_ptr[v + 1];
+  for (int kb = vt_ptr[v]; kb < k1; kb += 8) {
+    int code[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) code[u] = (kb + u < k1) ? vt_code[kb + u] : -1;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (code[u] < 0) continue;
+      const double* p = ge + 12 * int64_t(code[u] >> 2) + 3 * (code[u] & 3);
+      s0 += p[0];
+      s1 += p[1];
+      s2 += p[2];
+    }
   }
   const double m = mass[v];
   const double x0 = x[3 * v], x1 = x[3 * v + 1], x2 = x[3 * v + 2];
@@ -260,20 +267,20 @@ __global__ void k_gather_grad(int64_t n, const int32_t* __restrict__ vt_ptr, con
   g[3 * v + 2] = r2;
 }
 
-// grid: x = slice, y = block column k within the slice; 64 threads (rows)
+// grid: x = slice, y = group of 64/S block columns; lane = (column in group) * S + row
 template <typename HT, typename VT>
-__global__ void __launch_bounds__(64) k_gather_hess(int64_t n, const int32_t* __restrict__ slice_base,
+__global__ void __launch_bounds__(64) k_gather_hess(int64_t n, int S, const int32_t* __restrict__ slice_base,
                                                     const int32_t* __restrict__ scol,
                                                     const int32_t* __restrict__ gptr,
                                                     const int32_t* __restrict__ gcode, const HT* __restrict__ He,
                                                     const double* __restrict__ mass, const double* __restrict__ x,
                                                     double h2, HalfSpace hs, VT* __restrict__ vals) {
-  const int s = blockIdx.x, k = blockIdx.y, lane = threadIdx.x;
+  const int s = blockIdx.x, lane = threadIdx.x % S, k = blockIdx.y * (64 / S) + threadIdx.x / S;
   const int base = slice_base[s];
-  const int width = (slice_base[s + 1] - base) / kSlice;
+  const int width = (slice_base[s + 1] - base) / S;
   if (k >= width) return;
-  const int64_t slot = int64_t(base) + int64_t(k) * kSlice + lane;
-  const int64_t row = int64_t(s) * kSlice + lane;
+  const int64_t slot = int64_t(base) + int64_t(k) * S + lane;
+  const int64_t row = int64_t(s) * S + lane;
   const int col = scol[slot];
   double acc[9];
 #pragma unroll
@@ -311,9 +318,9 @@ __global__ void __launch_bounds__(64) k_gather_hess(int64_t n, const int32_t* __
       }
     }
   }
-  VT* out = vals + 9 * slot - 8 * lane;
+  VT* out = vals + vbase(slot, S);
 #pragma unroll
-  for (int c = 0; c < 9; ++c) out[kSlice * c] = VT(acc[c]);
+  for (int c = 0; c < 9; ++c) out[S * c] = VT(acc[c]);
 }
 
 // Energy parts at y = x + alpha d: {K, h^2 Psi, h^2 G, h^2 B}; threads cover
@@ -429,6 +436,16 @@ __global__ void k_apply_dbc(int64_t nd, const int32_t* __restrict__ idx, const d
   x[3 * v + 2] = tgt[3 * i + 2];
 }
 
+// d = x~ - x on free vertices, 0 on pinned ones.
+__global__ void k_predictor_dir(int64_t n, const double* __restrict__ x, const double* __restrict__ xtilde,
+                                const uint8_t* __restrict__ pinned, double* __restrict__ d) {
+  const int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const bool pin = pinned[v];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) d[3 * v + i] = pin ? 0.0 : xtilde[3 * v + i] - x[3 * v + i];
+}
+
 __global__ void k_velocity(int64_t n3, const double* __restrict__ x, const double* __restrict__ xt, double inv_h,
                            double* __restrict__ v) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -455,6 +472,9 @@ void launch_apply_dbc(ms_ctx* c, int64_t nd) {
   if (nd == 0) return;
   k_apply_dbc<<<nblocks(nd, 256), 256, 0, c->stream>>>(nd, c->d_dbc, c->d_dbc_tgt, c->d_x);
 }
+void launch_predictor_dir(ms_ctx* c) {
+  k_predictor_dir<<<nblocks(c->n, 256), 256, 0, c->stream>>>(c->n, c->d_x, c->d_xtilde, c->d_pinned, c->d_d);
+}
 void launch_velocity(ms_ctx* c, double inv_h) {
   k_velocity<<<nblocks(3 * c->n, 256), 256, 0, c->stream>>>(3 * c->n, c->d_x, c->d_xt, inv_h, c->d_v);
 }
@@ -471,21 +491,19 @@ void launch_element(ms_ctx* c, const double* x, double /*h2*/, int prec, bool he
                                                     c->d_ge, c->d_He32, project);
 }
 void launch_gather_grad(ms_ctx* c, const double* x, double h2, double* g) {
-  k_gather_grad<<<nblocks(c->n, 256), 256, 0, c->stream>>>(c->n, c->d_vt_ptr, c->d_vt_code, c->d_ge, c->d_mass, x,
+  k_gather_grad<<<nblocks(c->n, 64), 64, 0, c->stream>>>(c->n, c->d_vt_ptr, c->d_vt_code, c->d_ge, c->d_mass, x,
                                                           c->d_xtilde, h2, c->gravity[0], c->gravity[1],
                                                           c->gravity[2], hs_of(c), g);
 }
 void launch_gather_hess(ms_ctx* c, const double* x, double h2, int prec) {
-  int maxw = 0;
-  for (int64_t s = 0; s < c->pat.nslices; ++s)
-    maxw = std::max(maxw, (c->pat.h_slice_base[s + 1] - c->pat.h_slice_base[s]) / kSlice);
-  dim3 grid(unsigned(c->pat.nslices), unsigned(maxw));
+  const int S = c->pat.S;
+  dim3 grid(unsigned(c->pat.nslices), unsigned((c->pat.maxw * S + 63) / 64));
   if (prec == MS_PREC_FP64)
-    k_gather_hess<double, double><<<grid, 64, 0, c->stream>>>(c->n, c->pat.d_slice_base, c->pat.d_col, c->d_gptr,
+    k_gather_hess<double, double><<<grid, 64, 0, c->stream>>>(c->n, S, c->pat.d_slice_base, c->pat.d_col, c->d_gptr,
                                                              c->d_gcode, c->d_He, c->d_mass, x, h2, hs_of(c),
                                                              c->d_vals);
   else
-    k_gather_hess<float, float><<<grid, 64, 0, c->stream>>>(c->n, c->pat.d_slice_base, c->pat.d_col, c->d_gptr,
+    k_gather_hess<float, float><<<grid, 64, 0, c->stream>>>(c->n, S, c->pat.d_slice_base, c->pat.d_col, c->d_gptr,
                                                            c->d_gcode, c->d_He32, c->d_mass, x, h2, hs_of(c),
                                                            c->d_vals32);
 }

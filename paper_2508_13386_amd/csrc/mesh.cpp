@@ -5,6 +5,7 @@
 // without atomics and in a fixed order (so results are bitwise reproducible).
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <numeric>
 
 #include "ms_internal.h"
@@ -18,7 +19,7 @@ static inline int pair_index(int a, int b) {
   return tbl[a][b];
 }
 
-ms_status build_mesh(ms_ctx* c) {
+ms_status mesh_geometry(ms_ctx* c) {
   const int64_t n = c->n, T = c->T;
   c->h_vol.assign(T, 0.0);
   c->h_Dminv.assign(9 * T, 0.0);
@@ -53,6 +54,13 @@ ms_status build_mesh(ms_ctx* c) {
     }
   c->bbox_diag = std::sqrt((hi[0] - lo[0]) * (hi[0] - lo[0]) + (hi[1] - lo[1]) * (hi[1] - lo[1]) +
                            (hi[2] - lo[2]) * (hi[2] - lo[2]));
+  return MS_OK;
+}
+
+ms_status build_mesh(ms_ctx* c) {
+  const int64_t n = c->n, T = c->T;
+  ms_status s0 = mesh_geometry(c);
+  if (s0) return s0;
   // vertex -> (tet, local) incidence, ordered by tet index
   std::vector<int32_t> vt_ptr(n + 1, 0), vt_code(4 * T);
   for (int64_t t = 0; t < T; ++t)
@@ -71,6 +79,18 @@ ms_status build_mesh(ms_ctx* c) {
   if ((s = upload(c, &c->d_vt_ptr, vt_ptr.data(), n + 1))) return s;
   if ((s = upload(c, &c->d_vt_code, vt_code.data(), 4 * T))) return s;
   return build_pattern(c);
+}
+
+void slice_layout(int64_t n, const int32_t* row_ptr, int S, std::vector<int32_t>& slice_base, int& maxw) {
+  const int64_t ns = (n + S - 1) / S;
+  slice_base.assign(ns + 1, 0);
+  maxw = 0;
+  for (int64_t s = 0; s < ns; ++s) {
+    int32_t w = 0;
+    for (int64_t r = s * S; r < std::min<int64_t>(n, (s + 1) * S); ++r) w = std::max(w, row_ptr[r + 1] - row_ptr[r]);
+    slice_base[s + 1] = slice_base[s] + w * S;
+    maxw = std::max(maxw, int(w));
+  }
 }
 
 ms_status build_pattern(ms_ctx* c) {
@@ -94,22 +114,41 @@ ms_status build_pattern(ms_ctx* c) {
   P.nnzb = P.h_row_ptr[n];
   P.h_col.resize(P.nnzb);
   for (int64_t v = 0; v < n; ++v) std::copy(adj[v].begin(), adj[v].end(), P.h_col.begin() + P.h_row_ptr[v]);
-  // slices of 64 rows
-  P.nslices = (n + kSlice - 1) / kSlice;
-  P.h_slice_base.assign(P.nslices + 1, 0);
-  for (int64_t s = 0; s < P.nslices; ++s) {
-    int32_t w = 0;
-    for (int64_t r = s * kSlice; r < std::min<int64_t>(n, (s + 1) * kSlice); ++r)
-      w = std::max(w, P.h_row_ptr[r + 1] - P.h_row_ptr[r]);
-    P.h_slice_base[s + 1] = P.h_slice_base[s] + w * kSlice;
+  // slice height: forced by MS_SLICE, else the fastest of 16/32/64 rows per
+  // wave on this pattern (timed SpMV with random values)
+  int S = 0;
+  if (const char* e = std::getenv("MS_SLICE")) S = std::atoi(e);
+  if (S != 16 && S != 32 && S != 64) {
+    double best = 1e300;
+    for (int cand : {16, 32, 64}) {
+      std::vector<int32_t> sb;
+      int mw = 0;
+      slice_layout(n, P.h_row_ptr.data(), cand, sb, mw);
+      const int64_t ns = int64_t(sb.size()) - 1, nsl = sb.back();
+      std::vector<int32_t> sc(nsl, -1);
+      for (int64_t r = 0; r < n; ++r)
+        for (int32_t k = 0; k < P.h_row_ptr[r + 1] - P.h_row_ptr[r]; ++k)
+          sc[sb[r / cand] + int64_t(k) * cand + r % cand] = P.h_col[P.h_row_ptr[r] + k];
+      int32_t *d_sb = nullptr, *d_sc = nullptr;
+      ms_status st;
+      if ((st = upload(c, &d_sb, sb.data(), sb.size())) || (st = upload(c, &d_sc, sc.data(), sc.size()))) return st;
+      const double t = time_spmv_layout(c, cand, d_sb, d_sc, ns, nsl, 20);
+      dfree(c, d_sb);
+      dfree(c, d_sc);
+      if (t < 0) return fail(c, MS_E_DEVICE, "SpMV layout timing failed");
+      if (t < best) best = t, S = cand;
+    }
   }
+  P.S = S;
+  slice_layout(n, P.h_row_ptr.data(), S, P.h_slice_base, P.maxw);
+  P.nslices = int64_t(P.h_slice_base.size()) - 1;
   P.nslots = P.h_slice_base[P.nslices];
   std::vector<int32_t> scol(P.nslots, -1), diag_slot(n);
   P.h_slot_of_bsr.resize(P.nnzb);
   for (int64_t r = 0; r < n; ++r) {
-    int64_t s = r / kSlice, lane = r % kSlice;
+    int64_t s = r / S, lane = r % S;
     for (int32_t k = 0; k < P.h_row_ptr[r + 1] - P.h_row_ptr[r]; ++k) {
-      int64_t slot = P.h_slice_base[s] + int64_t(k) * kSlice + lane;
+      int64_t slot = P.h_slice_base[s] + int64_t(k) * S + lane;
       int32_t col = P.h_col[P.h_row_ptr[r] + k];
       scol[slot] = col;
       P.h_slot_of_bsr[P.h_row_ptr[r] + k] = slot;
@@ -121,7 +160,7 @@ ms_status build_pattern(ms_ctx* c) {
     const int32_t* b = &P.h_col[P.h_row_ptr[i]];
     const int32_t* e = &P.h_col[P.h_row_ptr[i + 1]];
     int64_t k = std::lower_bound(b, e, j) - b;
-    return P.h_slice_base[i / kSlice] + k * kSlice + (i % kSlice);
+    return P.h_slice_base[i / S] + k * S + (i % S);
   };
   std::vector<int32_t> gcnt(P.nslots + 1, 0);
   std::vector<int64_t> tslot(16 * T);

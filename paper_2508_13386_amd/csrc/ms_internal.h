@@ -1,12 +1,14 @@
 // Internal state of an ms_ctx and declarations shared by the library's
 // translation units.  Device layouts:
 //   * positions / vectors: [n][3] doubles (or floats in the FP32 parts);
-//   * Hessian: sliced BSR3 ("SBSR3"): rows are grouped in slices of
-//     kSlice = 64 consecutive vertices; slice s holds width_s block columns;
-//     block k of row (64 s + lane) stores its 9 components at
-//       vals[9 * base_s + (9 k + c) * 64 + lane],  base_s = 64 * sum_{s'<s} width_s',
-//     and its column at col[base_s + 64 k + lane] (-1 for padding).  A wave
-//     reading component c of block k of a slice reads 64 consecutive values.
+//   * Hessian: sliced BSR3 ("SBSR3"): rows are grouped in slices of S
+//     consecutive vertices (S = 16, 32 or 64, chosen per mesh by timing);
+//     slice s holds width_s block columns; block k of row (S s + r) stores its
+//     9 components at
+//       vals[9 * base_s + (9 k + c) * S + r],  base_s = S * sum_{s'<s} width_s',
+//     and its column at col[base_s + S k + r] (-1 for padding).  One wave
+//     serves one slice with 64 / S lanes per row, so a load of component c
+//     touches 64 / S runs of S consecutive values.
 //   * per-tet element blocks: 10 blocks (a <= b of the 4 local vertices) of
 //     3x3, [T][10][9], written by the element kernel and gathered without
 //     atomics into the slots above.
@@ -21,7 +23,8 @@
 
 namespace ms {
 
-constexpr int kSlice = 64;
+// Start of the 9 values of the block in slot `slot` (component stride S).
+__host__ __device__ inline int64_t vbase(int64_t slot, int S) { return 9 * slot - 8 * (slot & (S - 1)); }
 
 struct Buf {
   void* p = nullptr;
@@ -30,6 +33,8 @@ struct Buf {
 
 // Sliced BSR3 pattern on the device plus host copies needed by queries.
 struct Pattern {
+  int S = 64;  // slice height
+  int maxw = 0;  // largest slice width
   int64_t n = 0, nnzb = 0, nslots = 0, nslices = 0;
   int32_t* d_slice_base = nullptr;   // [nslices+1] block-slot base of each slice (multiple of 64)
   int32_t* d_col = nullptr;          // [nslots]
@@ -55,13 +60,24 @@ struct Basis {
   int32_t* d_hptr = nullptr;      // [m+1]
   int32_t* d_hv = nullptr;        // [nnz] vertex of each (handle, vertex) pair
   int32_t* d_hk = nullptr;        // [nnz] index into the per-vertex arrays
-  // Galerkin pair lists: for each coarse block (i <= j) the list of
-  // (Hessian slot, k_v, k_w) contributions; built on first use
+  int32_t nchunks = 0;            // restriction chunks
+  int32_t* d_hchunk = nullptr;    // [m+1] chunk range of each handle
+  int32_t* d_chunk_beg = nullptr; // [nchunks+1] entry range of each chunk
+  double* d_cpart = nullptr;      // [nchunks][12] restriction partials
+  // Galerkin lists.  Stage 1 (Z = H U): one entry per (v, j in h'(v)) with
+  // its (Hessian slot, k_w) contributions; stage 2 (U^T Z): one entry per
+  // coarse pair (i <= j) with its (k_v, z) contributions.
+  int64_t nz = 0, z_L = 0;
+  int32_t* d_zptr = nullptr;      // [nz+1]
+  int32_t* d_zent = nullptr;      // [z_L][2]
+  uint8_t* d_zmask = nullptr;     // [nz] 1 on Dirichlet rows
+  double* d_Z = nullptr;          // [nz][36]
   int32_t npairs = 0;
   int32_t* d_pair_ij = nullptr;   // [npairs][2]
   int32_t* d_pair_ptr = nullptr;  // [npairs+1]
-  int32_t* d_pair_ent = nullptr;  // [L][3]
+  int32_t* d_pair_ent = nullptr;  // [pair_L][2]
   int64_t pair_L = 0;
+  double* d_Minv = nullptr;       // (U^T M U)^-1, [r][r]
 };
 
 }  // namespace ms
@@ -123,17 +139,18 @@ struct ms_ctx {
   float* d_Dinv32 = nullptr;
   // PCG workspace
   double *d_d = nullptr, *d_r = nullptr, *d_u = nullptr, *d_w = nullptr, *d_p = nullptr, *d_s = nullptr;
-  float *f_r = nullptr, *f_u = nullptr, *f_w = nullptr, *f_p = nullptr, *f_s = nullptr;
   double* d_scal = nullptr;   // device scalars of the solvers
   double* h_scal = nullptr;   // pinned host mirror
   double* d_part = nullptr;   // reduction partials
+  double* d_cgst = nullptr;   // PCG recurrence state, two buffers
   unsigned* d_counter = nullptr;
   int nblk_vert = 0;          // blocks of the per-vertex kernels
   // graphs of fixed-size PCG chunks (per precision x preconditioner)
-  hipGraphExec_t cg_graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  hipGraphExec_t cg_graph[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
   int cg_chunk = 16;
   bool use_graphs = true;
   bool own_stream = false;
+  int verbose = 0;
   // basis / two-level preconditioner
   ms::Basis basis;
   bool has_basis = false;
@@ -142,6 +159,13 @@ struct ms_ctx {
   double* d_e = nullptr;      // coarse solution [r]
   double* d_Ac = nullptr;     // coarse matrix [r][r] (row-major), then its Cholesky factor
   double* d_Ainv = nullptr;   // explicit inverse of the coarse matrix [r][r]
+  int32_t rp = 0;             // r padded to the factorisation tile
+  double* d_Lc = nullptr;     // Cholesky factor workspace [rp][rp]
+  double* d_Y = nullptr;      // inverse factor workspace [rp][rp]
+  double* d_Ldiag = nullptr;  // factored diagonal tiles
+  double* d_Linvd = nullptr;  // inverses of the factored diagonal tiles
+  double* d_diag0 = nullptr;  // regularised diagonal [r]
+  int* d_nreg = nullptr;      // regularised pivots
   float* d_Ac32 = nullptr;    // FP32 Galerkin accumulation
   double* d_cpart = nullptr;  // coarse restriction partials
   int coarse_valid = 0;
@@ -193,14 +217,22 @@ ms_status upload(ms_ctx* c, T** p, const T* h, size_t n) {
   return MS_OK;
 }
 
-// host precompute (mesh.cpp) ------------------------------------------------
+// host precompute (mesh.cpp, basis.cpp) -------------------------------------
+ms_status mesh_geometry(ms_ctx* c);
 ms_status build_mesh(ms_ctx* c);
 ms_status build_pattern(ms_ctx* c);
+void slice_layout(int64_t n, const int32_t* row_ptr, int S, std::vector<int32_t>& slice_base, int& maxw);
+double time_spmv_layout(ms_ctx* c, int S, const int32_t* d_slice_base, const int32_t* d_col, int64_t nslices,
+                        int64_t nslots, int reps);
+ms_status build_basis_host(ms_ctx* c, const ms_basis_params& P, Basis& B);
+ms_status install_basis(ms_ctx* c, Basis&& B);
+ms_status coarse_coordinates(ms_ctx* c, const double* x_dev, double* q_host, double* q_dev);
 
 // kernel launchers (kernels_*.hip) -------------------------------------------
 enum Scal {  // indices into ctx->d_scal
   S_GAMMA = 0, S_DELTA, S_RHO, S_ALPHA, S_BETA, S_GAMMA_OLD, S_ALPHA_OLD, S_ITER, S_DONE, S_TOL2,
-  S_RHO0, S_MAXIT, S_E0, S_E1, S_E2, S_E3, S_CCD, S_DOT0, S_DOT1, S_DOT2, S_G0SQ, S_COUNT = 32
+  S_RHO0, S_MAXIT, S_E0, S_E1, S_E2, S_E3, S_CCD, S_DOT0, S_DOT1, S_DOT2, S_G0SQ, S_GPREV, S_ETAPREV, S_ETA,
+  S_COUNT = 32
 };
 
 void launch_predict(ms_ctx* c, double dt);
@@ -215,13 +247,20 @@ void launch_dots(ms_ctx* c, const double* a, const double* b, const double* a2, 
                  const double* a3, const double* b3);
 void launch_axpy(ms_ctx* c, double* y, const double* x, double alpha, int64_t len);
 void launch_velocity(ms_ctx* c, double inv_h);
-void launch_cg_init(ms_ctx* c, int prec, double eta_max, double eta_min, bool first, int max_it);
-void launch_coarse_correction(ms_ctx* c, int prec);
-void launch_cg_iteration(ms_ctx* c, int prec, int pc);
+void launch_cg_init(ms_ctx* c, int prec, double eta_max, double eta_min, bool first, int max_it, int forcing);
+void launch_coarse_correction(ms_ctx* c, int prec, bool from_w);
+void launch_precond_apply(ms_ctx* c, int prec, int pc);
+void launch_coarse_start(ms_ctx* c, int prec);
+void launch_spmv_resid(ms_ctx* c, int prec, bool from_d);
+void launch_bj(ms_ctx* c, int prec);
+void launch_prolong_set_d(ms_ctx* c);
+inline bool two_level(int pc) { return pc == MS_PC_TWO_LEVEL || pc == MS_PC_TWO_LEVEL_ADDITIVE; }
+void launch_cg_iteration(ms_ctx* c, int prec, int pc, int parity);
 void launch_precond(ms_ctx* c, int pc, int prec, const double* r, double* z);
 void launch_spmv(ms_ctx* c, int prec, const double* x, double* y);
 ms_status launch_galerkin(ms_ctx* c, int prec);
 ms_status coarse_factor(ms_ctx* c);
+int coarse_pad(int r);
 void launch_extract_bsr(ms_ctx* c, const int64_t* slot_of_bsr_dev, int64_t nnzb, double* out, int prec);
 void launch_fill(ms_ctx* c, double* p, double v, int64_t len);
 
@@ -229,14 +268,18 @@ void launch_fill(ms_ctx* c, double* p, double v, int64_t len);
 ms_status sync(ms_ctx* c);
 ms_status read_scal(ms_ctx* c);
 ms_status pcg_solve(ms_ctx* c, int prec, int pc, double eta_max, double eta_min, bool first, int max_it, int* iters,
-                    int* code);
-ms_status assemble(ms_ctx* c, const double* x, double h2, int prec, bool project, bool need_pc, int pc);
+                    int* code, int forcing);
+ms_status assemble(ms_ctx* c, const double* x, double h2, int prec, bool project, bool need_pc, int pc,
+                   bool refresh_coarse);
 ms_status energy(ms_ctx* c, const double* x, const double* d, double alpha, double h2, double parts[4]);
 ms_status plain_step(ms_ctx* c, double dt, const ms_solver_params& P, ms_step_stats* st);
 ms_status paper_step(ms_ctx* c, double dt, const ms_solver_params& P, ms_step_stats* st);
 void release_all(ms_ctx* c);
 ms_status line_search(ms_ctx* c, double h2, double gd, int max_bt, double* alpha_out, int* nbt);
 ms_status warm_start(ms_ctx* c, double dt, int32_t* used);
+ms_status inertial_start(ms_ctx* c, double h2);
+ms_status try_move(ms_ctx* c, double h2);
+void launch_predictor_dir(ms_ctx* c);
 ms_status record_coarse(ms_ctx* c);
 ms_status mat_build(struct ::ms_mat* A, int64_t n, const int32_t* row_ptr, const int32_t* col, const double* vals);
 void mat_spmv(struct ::ms_mat* A, const void* x, void* y);

@@ -14,6 +14,7 @@
 // redone with the projection.  A failed step restores x (transactional).
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 
 #include "ms_internal.h"
 
@@ -59,12 +60,37 @@ ms_status line_search(ms_ctx* c, double h2, double gd, int max_bt, double* alpha
   return MS_OK;
 }
 
+// Initial iterate from the inertial predictor: d = x~ - x on the free
+// vertices (zero on Dirichlet ones), truncated by the contact filter; the
+// move is kept only if it lowers the energy.
+ms_status inertial_start(ms_ctx* c, double h2) {
+  launch_predictor_dir(c);  // d = x~ - x, zero on pinned vertices
+  return try_move(c, h2);
+}
+
+// x <- x + alpha d with alpha from the contact filter when E decreases.
+ms_status try_move(ms_ctx* c, double h2) {
+  ms_status s;
+  double alpha = 1.0;
+  if (c->has_hs) {
+    launch_ccd(c, c->d_x, c->d_d);
+    if ((s = read_scal(c))) return s;
+    alpha = std::fmin(1.0, c->h_scal[S_CCD]);
+  }
+  double e0[4], e1[4];
+  if ((s = energy(c, c->d_x, nullptr, 0.0, h2, e0))) return s;
+  if ((s = energy(c, c->d_x, c->d_d, alpha, h2, e1))) return s;
+  const double E0 = e0[0] + e0[1] + e0[2] + e0[3], E1 = e1[0] + e1[1] + e1[2] + e1[3];
+  if (std::isfinite(E1) && E1 < E0) launch_axpy(c, c->d_x, c->d_d, alpha, 3 * c->n);
+  return MS_OK;
+}
+
 ms_status plain_step(ms_ctx* c, double dt, const ms_solver_params& P, ms_step_stats* st) {
   const double t0 = now_ms();
   const double h2 = dt * dt;
   const int prec = P.precision == MS_PREC_MIXED ? MS_PREC_MIXED : MS_PREC_FP64;
-  const int pc = P.preconditioner == MS_PC_TWO_LEVEL ? MS_PC_TWO_LEVEL : MS_PC_BLOCK_JACOBI;
-  if (pc == MS_PC_TWO_LEVEL && !c->has_basis) return fail(c, MS_E_ORDER, "two-level preconditioner needs a basis");
+  const int pc = (P.preconditioner >= 0 && P.preconditioner <= 2) ? P.preconditioner : MS_PC_BLOCK_JACOBI;
+  if (two_level(pc) && !c->has_basis) return fail(c, MS_E_ORDER, "two-level preconditioner needs a basis");
   launch_predict(c, dt);
   launch_apply_dbc(c, int64_t(c->h_dbc.size()));
   ms_step_stats S{};
@@ -72,15 +98,18 @@ ms_status plain_step(ms_ctx* c, double dt, const ms_solver_params& P, ms_step_st
   ms_status s;
   if (P.warm_start && c->mlp) {
     if ((s = warm_start(c, dt, &S.warm_start_used))) return restore(c, s);
+  } else if (P.predictor == 1) {
+    if ((s = inertial_start(c, h2))) return restore(c, s);
   }
   bool endgame = false, converged = false, first = true;
   double dnorm = 0.0, disp = 0.0;
   int it = 0;
   for (; it < P.max_newton; ++it) {
     const bool project = !(P.exact_endgame && endgame);
-    if ((s = assemble(c, c->d_x, h2, prec, project, true, pc))) return restore(c, s);
+    const bool refresh = it == 0 || (P.coarse_every > 0 && it % P.coarse_every == 0);
+    if ((s = assemble(c, c->d_x, h2, prec, project, true, pc, refresh))) return restore(c, s);
     int iters = 0, code = 0;
-    if ((s = pcg_solve(c, prec, pc, P.pcg_eta_max, P.pcg_eta_min, first, P.max_pcg, &iters, &code)))
+    if ((s = pcg_solve(c, prec, pc, P.pcg_eta_max, P.pcg_eta_min, first, P.max_pcg, &iters, &code, P.forcing)))
       return restore(c, s);
     first = false;
     S.pcg_iters += iters;
@@ -116,12 +145,17 @@ ms_status plain_step(ms_ctx* c, double dt, const ms_solver_params& P, ms_step_st
     if ((s = read_scal(c))) return restore(c, s);
     disp = std::sqrt(c->h_scal[S_DOT2]);
     const double ref = std::max(disp, P.abs_floor);
+    if (c->verbose)
+      std::fprintf(stderr,
+                   "[ms] it %d proj %d pcg %d code %d eta %.2e |g| %.3e gd %.3e |d| %.3e alpha %.3g bt %d disp %.3e\n",
+                   it, int(project), iters, code, c->h_scal[S_ETA], std::sqrt(c->h_scal[S_RHO0]), gd, dnorm, alpha, nbt,
+                   disp);
     if (alpha == 1.0 && dnorm <= P.newton_tol * ref) {
       converged = true;
       ++it;
       break;
     }
-    if (dnorm <= 1e-3 * ref) endgame = true;
+    if (dnorm <= P.endgame_ratio * ref) endgame = true;
   }
   if (!converged) return restore(c, fail(c, MS_E_NOCONV, "Newton did not converge"));
   launch_velocity(c, 1.0 / dt);

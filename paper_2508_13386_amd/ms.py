@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libms.so")
 MS_OK, MS_E_ARG, MS_E_MESH, MS_E_ORDER, MS_E_DEVICE, MS_E_NOMEM, MS_E_NOCONV, MS_E_LINESEARCH, MS_E_NONFINITE = \
     0, -1, -2, -3, -4, -5, -6, -7, -8
 PREC_FP64, PREC_MIXED = 0, 1
-PC_BLOCK_JACOBI, PC_TWO_LEVEL = 0, 1
+PC_BLOCK_JACOBI, PC_TWO_LEVEL, PC_TWO_LEVEL_ADDITIVE = 0, 1, 2
 MODE_PLAIN, MODE_PAPER = 0, 1
 
 _ALLOC = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -37,7 +37,8 @@ class ms_solver_params(C.Structure):
                 ("replace_every", C.c_int32), ("max_backtracks", C.c_int32), ("exact_endgame", C.c_int32),
                 ("warm_start", C.c_int32), ("paper_eps", C.c_double), ("subspace_rtol", C.c_double),
                 ("refine_iters", C.c_int32), ("lag_window", C.c_int32), ("lag_threshold", C.c_double),
-                ("lag_min_gap", C.c_int32)]
+                ("lag_min_gap", C.c_int32), ("forcing", C.c_int32), ("endgame_ratio", C.c_double),
+                ("coarse_every", C.c_int32), ("predictor", C.c_int32)]
 
 
 class ms_step_stats(C.Structure):
