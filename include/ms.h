@@ -109,6 +109,9 @@ typedef struct {
   int32_t predictor;       /* initial Newton iterate: 0 x^t; 1 the inertial predictor
                               x^t + h v^t (truncated by the contact filter, Dirichlet
                               vertices at their targets), kept only if it lowers E     */
+  int32_t time_kernels;    /* 1: bracket every PCG product launch of this step with HIP
+                              events (PCG runs without graphs); ms_time_kernel with
+                              reps = 0 then reports their average duration             */
 } ms_solver_params;
 
 /* Statistics of the last ms_step. */
@@ -263,6 +266,19 @@ ms_status ms_apply_preconditioner(ms_ctx* c, int32_t kind, int32_t prec, const d
 
 /* Coarse operator U^T H U (12m x 12m, row-major) of the last ms_eval. */
 ms_status ms_get_coarse_matrix(ms_ctx* c, double* A);
+
+/* Measurement of kernel 0, the PCG product w = H u fused with the dots
+ * (r.u, w.u, r.r) that every PCG iteration runs, in precision prec.
+ * reps > 0: average duration in microseconds of `reps` back-to-back launches
+ * on the context's stream, bracketed by HIP events, on the Hessian of the
+ * last assembly (overwrites PCG scratch vectors).  reps = 0: average over
+ * the launches recorded inside the PCG solves of ms_step calls made with
+ * time_kernels = 1 (launches after convergence excluded), then the record
+ * is cleared.  *bytes receives the kernel's algorithmic bytes per launch
+ * (matrix values and column indices of the stored blocks, slice offsets,
+ * u and r read, w written, Dirichlet mask; each counted once).
+ * Errors: MS_E_ORDER (nothing assembled / recorded yet), MS_E_ARG. */
+ms_status ms_time_kernel(ms_ctx* c, int32_t kernel, int32_t prec, int32_t reps, double* avg_us, double* bytes);
 
 /* ---- standalone sliced-BSR3 matrix for SpMV measurements ----------------
  * A block-sparse matrix with 3x3 blocks given in BSR form (host row_ptr

@@ -128,8 +128,16 @@ ms_status pcg_solve(ms_ctx* c, int prec, int pc, double eta_max, double eta_min,
     (void)hipGraphDestroy(g);
   }
   int launched = 0;
+  if (c->timing && int(c->tev.size()) < 2 * chunk) {
+    c->tev.resize(2 * chunk, nullptr);
+    for (auto& e : c->tev)
+      if (!e) MS_HIP(hipEventCreate(&e));
+  }
   while (true) {
-    if (c->use_graphs) {
+    const int before = launched == 0 ? 0 : int(c->h_scal[S_ITER]);
+    if (c->timing) {
+      for (int i = 0; i < chunk; ++i) launch_cg_iteration(c, prec, pc, i & 1, c->tev[2 * i], c->tev[2 * i + 1]);
+    } else if (c->use_graphs) {
       MS_HIP(hipGraphLaunch(ge, c->stream));
     } else {
       for (int i = 0; i < chunk; ++i) launch_cg_iteration(c, prec, pc, i & 1);
@@ -137,6 +145,17 @@ ms_status pcg_solve(ms_ctx* c, int prec, int pc, double eta_max, double eta_min,
     launched += chunk;
     ms_status s = read_scal(c);
     if (s) return s;
+    if (c->timing) {
+      // launches that ran a real iteration: those before convergence was flagged
+      const int ran = std::min(chunk, int(c->h_scal[S_ITER]) - before + (c->h_scal[S_DONE] != 0.0 ? 1 : 0));
+      for (int i = 0; i < std::max(0, ran); ++i) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, c->tev[2 * i], c->tev[2 * i + 1]) == hipSuccess) {
+          c->timed_ms[prec == MS_PREC_FP64 ? 0 : 1] += ms;
+          c->timed_n[prec == MS_PREC_FP64 ? 0 : 1] += 1;
+        }
+      }
+    }
     if (c->h_scal[S_DONE] != 0.0) break;
     if (launched > max_it + 2 * chunk) return fail(c, MS_E_DEVICE, "PCG flag never set");
   }
@@ -147,6 +166,7 @@ ms_status pcg_solve(ms_ctx* c, int prec, int pc, double eta_max, double eta_min,
 
 ms_status assemble(ms_ctx* c, const double* x, double h2, int prec, bool project, bool need_pc, int pc,
                    bool refresh_coarse) {
+  c->assembled[prec == MS_PREC_FP64 ? 0 : 1] = true;
   launch_element(c, x, h2, prec, true, project);
   launch_gather_grad(c, x, h2, c->d_g);
   launch_gather_hess(c, x, h2, prec);
@@ -447,6 +467,8 @@ void ms_destroy(ms_ctx* c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
   destroy_graphs(c);
+  for (auto& e : c->tev)
+    if (e) (void)hipEventDestroy(e);
   release_all(c);
   if (c->h_scal) (void)hipHostFree(c->h_scal);
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
@@ -475,6 +497,22 @@ ms_status ms_mat_spmv(ms_mat* A, const void* x, void* y) {
   return hipGetLastError() == hipSuccess ? MS_OK : MS_E_DEVICE;
 }
 double ms_mat_bytes(const ms_mat* A) { return A ? A->bytes : 0.0; }
+
+ms_status ms_time_kernel(ms_ctx* c, int32_t kernel, int32_t prec, int32_t reps, double* avg_us, double* bytes) {
+  if (!c || !avg_us || !bytes || reps < 0 || kernel != 0 || (prec != MS_PREC_FP64 && prec != MS_PREC_MIXED))
+    return MS_E_ARG;
+  if (!c->assembled[prec == MS_PREC_FP64 ? 0 : 1]) return fail(c, MS_E_ORDER, "no Hessian assembled in that precision");
+  if (reps == 0) {
+    const int q = prec == MS_PREC_FP64 ? 0 : 1;
+    if (c->timed_n[q] == 0) return fail(c, MS_E_ORDER, "no PCG products recorded");
+    *avg_us = 1e3 * c->timed_ms[q] / double(c->timed_n[q]);
+    *bytes = cg_spmv_bytes(c, prec);
+    c->timed_ms[q] = 0.0;
+    c->timed_n[q] = 0;
+    return MS_OK;
+  }
+  return time_cg_spmv(c, prec, reps, avg_us, bytes);
+}
 void ms_mat_destroy(ms_mat* A) {
   if (!A) return;
   release_all(&A->ctx);

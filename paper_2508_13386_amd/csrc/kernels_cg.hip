@@ -19,6 +19,8 @@
 #include <cstdlib>
 #include <type_traits>
 
+#include <hip/hip_ext.h>
+
 #include "ms_internal.h"
 #include "reduce.h"
 
@@ -490,19 +492,27 @@ void launch_cg_init(ms_ctx* c, int prec, double eta_max, double eta_min, bool fi
 
 // One PCG iteration; `parity` selects the recurrence-state buffers
 // (iteration k reads state k % 2 and writes (k + 1) % 2).
-void launch_cg_iteration(ms_ctx* c, int prec, int pc, int parity) {
+void launch_cg_iteration(ms_ctx* c, int prec, int pc, int parity, hipEvent_t ev0, hipEvent_t ev1) {
   const int64_t ns = c->pat.nslices;
   const unsigned nbs = unsigned((ns + 3) / 4), nb = nblocks(c->n, 256);
   const double* st_in = c->d_cgst + ST_N * parity;
   double* st_out = c->d_cgst + ST_N * (1 - parity);
   with_slice(c->pat.S, [&](auto SS) {
     constexpr int S = decltype(SS)::value;
+    auto go = [&](auto kernel, const auto* vals) {
+      if (ev0)  // the events take the dispatch's own start and end timestamps
+        hipExtLaunchKernelGGL(kernel, dim3(nbs), dim3(256), 0, c->stream, ev0, ev1, 0, c->n, ns,
+                              (const int32_t*)c->pat.d_slice_base, (const int32_t*)c->pat.d_col, vals,
+                              (const double*)c->d_u, c->d_w, (const double*)c->d_r, (const uint8_t*)c->d_pinned,
+                              (const double*)c->d_scal, c->d_part);
+      else
+        kernel<<<nbs, 256, 0, c->stream>>>(c->n, ns, c->pat.d_slice_base, c->pat.d_col, vals, c->d_u, c->d_w, c->d_r,
+                                           c->d_pinned, c->d_scal, c->d_part);
+    };
     if (prec == MS_PREC_FP64)
-      k_cg_spmv<double, S><<<nbs, 256, 0, c->stream>>>(c->n, ns, c->pat.d_slice_base, c->pat.d_col, c->d_vals, c->d_u,
-                                                       c->d_w, c->d_r, c->d_pinned, c->d_scal, c->d_part);
+      go(k_cg_spmv<double, S>, (const double*)c->d_vals);
     else
-      k_cg_spmv<float, S><<<nbs, 256, 0, c->stream>>>(c->n, ns, c->pat.d_slice_base, c->pat.d_col, c->d_vals32, c->d_u,
-                                                      c->d_w, c->d_r, c->d_pinned, c->d_scal, c->d_part);
+      go(k_cg_spmv<float, S>, (const float*)c->d_vals32);
   });
   if (prec == MS_PREC_FP64)
     k_cg_update<double><<<nb, 256, 0, c->stream>>>(c->n, int(nbs), c->d_part, st_in, st_out, c->d_p, c->d_s, c->d_d,
@@ -511,6 +521,47 @@ void launch_cg_iteration(ms_ctx* c, int prec, int pc, int parity) {
     k_cg_update<float><<<nb, 256, 0, c->stream>>>(c->n, int(nbs), c->d_part, st_in, st_out, c->d_p, c->d_s, c->d_d,
                                                   c->d_r, c->d_u, c->d_w, c->d_Dinv32, c->d_scal);
   launch_precond_apply(c, prec, pc);
+}
+
+ms_status time_cg_spmv(ms_ctx* c, int prec, int reps, double* avg_us, double* bytes) {
+  const int64_t ns = c->pat.nslices;
+  const unsigned nbs = unsigned((ns + 3) / 4);
+  MS_HIP(hipMemsetAsync(c->d_scal + S_DONE, 0, sizeof(double), c->stream));
+  auto run = [&]() {
+    with_slice(c->pat.S, [&](auto SS) {
+      constexpr int S = decltype(SS)::value;
+      if (prec == MS_PREC_FP64)
+        k_cg_spmv<double, S><<<nbs, 256, 0, c->stream>>>(c->n, ns, c->pat.d_slice_base, c->pat.d_col, c->d_vals,
+                                                         c->d_u, c->d_w, c->d_r, c->d_pinned, c->d_scal, c->d_part);
+      else
+        k_cg_spmv<float, S><<<nbs, 256, 0, c->stream>>>(c->n, ns, c->pat.d_slice_base, c->pat.d_col, c->d_vals32,
+                                                        c->d_u, c->d_w, c->d_r, c->d_pinned, c->d_scal, c->d_part);
+    });
+  };
+  for (int i = 0; i < 3; ++i) run();
+  hipEvent_t e0, e1;
+  MS_HIP(hipEventCreate(&e0));
+  MS_HIP(hipEventCreate(&e1));
+  MS_HIP(hipEventRecord(e0, c->stream));
+  for (int i = 0; i < reps; ++i) run();
+  MS_HIP(hipEventRecord(e1, c->stream));
+  MS_HIP(hipEventSynchronize(e1));
+  float ms = 0.0f;
+  MS_HIP(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *avg_us = 1e3 * double(ms) / reps;
+  *bytes = cg_spmv_bytes(c, prec);
+  return MS_OK;
+}
+
+// Algorithmic bytes of one k_cg_spmv launch: 9 values + 1 column index per
+// stored block, the slice offsets, u and r read and w written (FP64), the
+// Dirichlet mask; padding lanes and the per-block partials are not counted.
+double cg_spmv_bytes(const ms_ctx* c, int prec) {
+  const double vb = prec == MS_PREC_FP64 ? 8.0 : 4.0;
+  return double(c->pat.nnzb) * (9.0 * vb + 4.0) + 4.0 * double(c->pat.nslices + 1) +
+         double(c->n) * (3.0 * 8.0 * 3.0 + 1.0);
 }
 
 // ---------------------------------------------------------------------------

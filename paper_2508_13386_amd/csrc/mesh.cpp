@@ -114,30 +114,46 @@ ms_status build_pattern(ms_ctx* c) {
   P.nnzb = P.h_row_ptr[n];
   P.h_col.resize(P.nnzb);
   for (int64_t v = 0; v < n; ++v) std::copy(adj[v].begin(), adj[v].end(), P.h_col.begin() + P.h_row_ptr[v]);
-  // slice height: forced by MS_SLICE, else the fastest of 16/32/64 rows per
-  // wave on this pattern (timed SpMV with random values)
+  // slice height: forced by MS_SLICE, else 32 rows per slice unless 16 or 64
+  // is at least 3% faster on this pattern (timed FP64 SpMV with constant
+  // values; candidates timed in interleaved rounds, best round kept, so that
+  // the choice is stable under timing noise)
   int S = 0;
   if (const char* e = std::getenv("MS_SLICE")) S = std::atoi(e);
   if (S != 16 && S != 32 && S != 64) {
-    double best = 1e300;
-    for (int cand : {16, 32, 64}) {
+    const int cands[3] = {16, 32, 64};
+    int32_t *d_sb[3] = {nullptr, nullptr, nullptr}, *d_sc[3] = {nullptr, nullptr, nullptr};
+    int64_t ns[3], nsl[3];
+    double best[3] = {1e300, 1e300, 1e300};
+    ms_status st = MS_OK;
+    for (int q = 0; q < 3 && !st; ++q) {
+      const int cand = cands[q];
       std::vector<int32_t> sb;
       int mw = 0;
       slice_layout(n, P.h_row_ptr.data(), cand, sb, mw);
-      const int64_t ns = int64_t(sb.size()) - 1, nsl = sb.back();
-      std::vector<int32_t> sc(nsl, -1);
+      ns[q] = int64_t(sb.size()) - 1;
+      nsl[q] = sb.back();
+      std::vector<int32_t> sc(nsl[q], -1);
       for (int64_t r = 0; r < n; ++r)
         for (int32_t k = 0; k < P.h_row_ptr[r + 1] - P.h_row_ptr[r]; ++k)
           sc[sb[r / cand] + int64_t(k) * cand + r % cand] = P.h_col[P.h_row_ptr[r] + k];
-      int32_t *d_sb = nullptr, *d_sc = nullptr;
-      ms_status st;
-      if ((st = upload(c, &d_sb, sb.data(), sb.size())) || (st = upload(c, &d_sc, sc.data(), sc.size()))) return st;
-      const double t = time_spmv_layout(c, cand, d_sb, d_sc, ns, nsl, 20);
-      dfree(c, d_sb);
-      dfree(c, d_sc);
-      if (t < 0) return fail(c, MS_E_DEVICE, "SpMV layout timing failed");
-      if (t < best) best = t, S = cand;
+      if (!(st = upload(c, &d_sb[q], sb.data(), sb.size()))) st = upload(c, &d_sc[q], sc.data(), sc.size());
     }
+    for (int round = 0; round < 5 && !st; ++round)
+      for (int q = 0; q < 3 && !st; ++q) {
+        const double t = time_spmv_layout(c, cands[q], d_sb[q], d_sc[q], ns[q], nsl[q], 10);
+        if (t < 0) st = fail(c, MS_E_DEVICE, "SpMV layout timing failed");
+        best[q] = std::min(best[q], t);
+      }
+    for (int q = 0; q < 3; ++q) {
+      dfree(c, d_sb[q]);
+      dfree(c, d_sc[q]);
+    }
+    if (st) return st;
+    S = 32;
+    double bt = best[1];
+    for (int q : {0, 2})
+      if (best[q] < 0.97 * best[1] && best[q] < bt) bt = best[q], S = cands[q];
   }
   P.S = S;
   slice_layout(n, P.h_row_ptr.data(), S, P.h_slice_base, P.maxw);

@@ -176,6 +176,12 @@ struct ms_ctx {
   // last eval
   int eval_prec = 0;
   bool eval_valid = false;
+  bool assembled[2] = {false, false};  // a Hessian of that precision is in place
+  // live timing of the PCG product (time_kernels)
+  bool timing = false;
+  std::vector<hipEvent_t> tev;      // 2 per iteration of a chunk
+  double timed_ms[2] = {0.0, 0.0};  // per precision: accumulated duration
+  int64_t timed_n[2] = {0, 0};
 };
 
 struct ms_mat {
@@ -255,7 +261,7 @@ void launch_spmv_resid(ms_ctx* c, int prec, bool from_d);
 void launch_bj(ms_ctx* c, int prec);
 void launch_prolong_set_d(ms_ctx* c);
 inline bool two_level(int pc) { return pc == MS_PC_TWO_LEVEL || pc == MS_PC_TWO_LEVEL_ADDITIVE; }
-void launch_cg_iteration(ms_ctx* c, int prec, int pc, int parity);
+void launch_cg_iteration(ms_ctx* c, int prec, int pc, int parity, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 void launch_precond(ms_ctx* c, int pc, int prec, const double* r, double* z);
 void launch_spmv(ms_ctx* c, int prec, const double* x, double* y);
 ms_status launch_galerkin(ms_ctx* c, int prec);
@@ -275,6 +281,8 @@ ms_status energy(ms_ctx* c, const double* x, const double* d, double alpha, doub
 ms_status plain_step(ms_ctx* c, double dt, const ms_solver_params& P, ms_step_stats* st);
 ms_status paper_step(ms_ctx* c, double dt, const ms_solver_params& P, ms_step_stats* st);
 void release_all(ms_ctx* c);
+ms_status time_cg_spmv(ms_ctx* c, int prec, int reps, double* avg_us, double* bytes);
+double cg_spmv_bytes(const ms_ctx* c, int prec);
 ms_status line_search(ms_ctx* c, double h2, double gd, int max_bt, double* alpha_out, int* nbt);
 ms_status warm_start(ms_ctx* c, double dt, int32_t* used);
 ms_status inertial_start(ms_ctx* c, double h2);

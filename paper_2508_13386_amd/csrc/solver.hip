@@ -93,6 +93,7 @@ ms_status plain_step(ms_ctx* c, double dt, const ms_solver_params& P, ms_step_st
   if (two_level(pc) && !c->has_basis) return fail(c, MS_E_ORDER, "two-level preconditioner needs a basis");
   launch_predict(c, dt);
   launch_apply_dbc(c, int64_t(c->h_dbc.size()));
+  c->timing = P.time_kernels != 0;
   ms_step_stats S{};
   S.min_alpha = 1.0;
   ms_status s;

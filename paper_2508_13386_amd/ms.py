@@ -38,7 +38,7 @@ class ms_solver_params(C.Structure):
                 ("warm_start", C.c_int32), ("paper_eps", C.c_double), ("subspace_rtol", C.c_double),
                 ("refine_iters", C.c_int32), ("lag_window", C.c_int32), ("lag_threshold", C.c_double),
                 ("lag_min_gap", C.c_int32), ("forcing", C.c_int32), ("endgame_ratio", C.c_double),
-                ("coarse_every", C.c_int32), ("predictor", C.c_int32)]
+                ("coarse_every", C.c_int32), ("predictor", C.c_int32), ("time_kernels", C.c_int32)]
 
 
 class ms_step_stats(C.Structure):
@@ -101,6 +101,9 @@ def lib():
             "ms_mat_create": [C.POINTER(ms_device), i64, ip, ip, dp, i32, C.POINTER(C.c_void_p)],
             "ms_mat_spmv": [vp, vp, vp],
             "ms_batch_step": [C.POINTER(C.c_void_p), i32, d, C.POINTER(ms_solver_params), C.POINTER(ms_step_stats)],
+            "ms_time_kernel": [vp, i32, i32, i32, C.POINTER(d), C.POINTER(d)],
+            "ms_basis_compute": [i64, dp, i64, ip, dp, i64, ip, C.POINTER(ms_basis_params), C.POINTER(C.c_void_p)],
+            "ms_basis_get": [vp, C.POINTER(i32), C.POINTER(i64), dp, ip, ip, dp, ip],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -110,6 +113,8 @@ def lib():
         L.ms_mat_bytes.restype = C.c_double
         L.ms_mat_destroy.argtypes = [vp]
         L.ms_mat_destroy.restype = None
+        L.ms_basis_free.argtypes = [vp]
+        L.ms_basis_free.restype = None
         L.ms_destroy.argtypes = [vp]
         L.ms_destroy.restype = None
         L.ms_last_error.argtypes = [vp]
@@ -312,10 +317,42 @@ class Context:
         self._check(self.L.ms_apply_preconditioner(self.h, int(kind), int(prec), _ptr(r), _ptr(z)))
         return z
 
+    def ms_time_kernel(self, kernel=0, prec=PREC_FP64, reps=100):
+        us = C.c_double()
+        nb = C.c_double()
+        self._check(self.L.ms_time_kernel(self.h, int(kernel), int(prec), int(reps), C.byref(us), C.byref(nb)))
+        return us.value, nb.value
+
     def ms_get_coarse_matrix(self, r):
         A = np.empty((r, r))
         self._check(self.L.ms_get_coarse_matrix(self.h, _ptr(A)))
         return A
+
+
+def ms_basis_compute(rest, tets, E, dbc=(), params=None, **kw):
+    """Host-only basis construction; returns the dict of ms_basis_get."""
+    L = lib()
+    rest, tets, E = _f64(rest), _i32(tets), _f64(E)
+    dbc = _i32(np.asarray(dbc, dtype=np.int32))
+    p = params or basis_defaults(**kw)
+    h = C.c_void_p()
+    code = L.ms_basis_compute(len(rest), _ptr(rest), len(tets), _ptr(tets), _ptr(E), len(dbc),
+                              _ptr(dbc) if len(dbc) else None, C.byref(p), C.byref(h))
+    if code != MS_OK:
+        raise MSError(code, "ms_basis_compute")
+    try:
+        m = C.c_int32()
+        nnz = C.c_int64()
+        L.ms_basis_get(h, C.byref(m), C.byref(nnz), None, None, None, None, None)
+        o = np.empty((m.value, 3))
+        vp = np.empty(len(rest) + 1, dtype=np.int64)
+        vh = np.empty(nnz.value, dtype=np.int32)
+        w = np.empty(nnz.value)
+        part = np.empty(len(tets), dtype=np.int32)
+        L.ms_basis_get(h, C.byref(m), C.byref(nnz), _ptr(o), _ptr(vp), _ptr(vh), _ptr(w), _ptr(part))
+    finally:
+        L.ms_basis_free(h)
+    return dict(origins=o, vptr=vp, vhandle=vh, vphi=w, part=part, m=m.value)
 
 
 def ms_batch_step(contexts, dt, params=None, **kw):
