@@ -259,6 +259,17 @@ ms_status ms_get_pattern(const ms_ctx* c, int64_t* nnzb, int32_t* row_ptr, int32
 ms_status ms_eval(ms_ctx* c, const double* x, double dt, int32_t prec, double* e4, double* grad,
                   double* hess);
 
+/* Energy difference E(x + alpha d) - E(x) of the incremental potential
+ * (Eq. IP with the implicit Euler inertia term), with x~ from the current
+ * state, evaluated term by term so that the large totals never cancel:
+ * parts5 = {dK, h^2 dPsi, h^2 dG, h^2 dB, magnitude}, where magnitude is the
+ * sum of the absolute values of the terms (the scale of the round-off in
+ * the sum of the first four).  This is the quantity the line search tests
+ * the Armijo condition on.  x, d [n][3] host.  Errors: MS_E_ORDER before
+ * ms_set_state, MS_E_NONFINITE for non-finite x or d. */
+ms_status ms_energy_difference(ms_ctx* c, const double* x, const double* d, double alpha, double dt,
+                               double* parts5);
+
 /* Apply the preconditioner built for the Hessian of the last ms_eval
  * (kind = ms_preconditioner) to r [n][3]; z [n][3].  Dirichlet DOFs of z
  * are zero. */
@@ -277,7 +288,13 @@ ms_status ms_get_coarse_matrix(ms_ctx* c, double* A);
  * is cleared.  *bytes receives the kernel's algorithmic bytes per launch
  * (matrix values and column indices of the stored blocks, slice offsets,
  * u and r read, w written, Dirichlet mask; each counted once).
- * Errors: MS_E_ORDER (nothing assembled / recorded yet), MS_E_ARG. */
+ * kernel 1..5 (reps > 0 only) replays the other kernels of a PCG iteration
+ * on the current buffers: 1 the update (p, s, d, r, u), 2 the restriction
+ * c = U^T r, 3 the coarse GEMV e = A^-1 c, 4 the prolongation u += U e,
+ * 5 one whole iteration (bytes 0: not a single kernel).  These overwrite
+ * the PCG vectors.
+ * Errors: MS_E_ORDER (nothing assembled / recorded yet, or no basis for
+ * 2..4), MS_E_ARG. */
 ms_status ms_time_kernel(ms_ctx* c, int32_t kernel, int32_t prec, int32_t reps, double* avg_us, double* bytes);
 
 /* ---- standalone sliced-BSR3 matrix for SpMV measurements ----------------

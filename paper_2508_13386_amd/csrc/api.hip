@@ -182,6 +182,16 @@ ms_status assemble(ms_ctx* c, const double* x, double h2, int prec, bool project
   return MS_OK;
 }
 
+ms_status energy_delta(ms_ctx* c, const double* x, const double* d, double alpha, double h2, double* dE,
+                       double* err) {
+  launch_energy_delta(c, x, d, alpha, h2);
+  ms_status s = read_scal(c);
+  if (s) return s;
+  *dE = c->h_scal[S_DE0] + c->h_scal[S_DE1] + c->h_scal[S_DE2] + c->h_scal[S_DE3];
+  *err = c->h_scal[S_DE4];
+  return MS_OK;
+}
+
 ms_status energy(ms_ctx* c, const double* x, const double* d, double alpha, double h2, double parts[4]) {
   launch_energy(c, x, d, alpha, h2);
   ms_status s = read_scal(c);
@@ -434,6 +444,22 @@ ms_status ms_eval(ms_ctx* c, const double* x, double dt, int32_t prec, double* e
   return sync(c);
 }
 
+ms_status ms_energy_difference(ms_ctx* c, const double* x, const double* d, double alpha, double dt,
+                               double* parts5) {
+  if (!c || !x || !d || !parts5 || !std::isfinite(alpha) || !(dt > 0)) return MS_E_ARG;
+  if (c->stage < 3) return fail(c, MS_E_ORDER, "set a state first");
+  const int64_t n3 = 3 * c->n;
+  if (!finite_all(x, n3) || !finite_all(d, n3)) return fail(c, MS_E_NONFINITE, "non-finite x or d");
+  MS_HIP(hipMemcpyAsync(c->d_xtrial, x, n3 * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  MS_HIP(hipMemcpyAsync(c->d_w, d, n3 * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  launch_predict(c, dt);
+  launch_energy_delta(c, c->d_xtrial, c->d_w, alpha, dt * dt);
+  ms_status s = read_scal(c);
+  if (s) return s;
+  for (int k = 0; k < 5; ++k) parts5[k] = c->h_scal[S_DE0 + k];
+  return MS_OK;
+}
+
 ms_status ms_apply_preconditioner(ms_ctx* c, int32_t kind, int32_t prec, const double* r, double* z) {
   if (!c || !r || !z) return MS_E_ARG;
   if (!c->eval_valid) return fail(c, MS_E_ORDER, "call ms_eval first");
@@ -499,7 +525,7 @@ ms_status ms_mat_spmv(ms_mat* A, const void* x, void* y) {
 double ms_mat_bytes(const ms_mat* A) { return A ? A->bytes : 0.0; }
 
 ms_status ms_time_kernel(ms_ctx* c, int32_t kernel, int32_t prec, int32_t reps, double* avg_us, double* bytes) {
-  if (!c || !avg_us || !bytes || reps < 0 || kernel != 0 || (prec != MS_PREC_FP64 && prec != MS_PREC_MIXED))
+  if (!c || !avg_us || !bytes || reps < 0 || kernel < 0 || kernel > 5 || (prec != MS_PREC_FP64 && prec != MS_PREC_MIXED))
     return MS_E_ARG;
   if (!c->assembled[prec == MS_PREC_FP64 ? 0 : 1]) return fail(c, MS_E_ORDER, "no Hessian assembled in that precision");
   if (reps == 0) {
@@ -510,6 +536,10 @@ ms_status ms_time_kernel(ms_ctx* c, int32_t kernel, int32_t prec, int32_t reps, 
     c->timed_ms[q] = 0.0;
     c->timed_n[q] = 0;
     return MS_OK;
+  }
+  if (kernel > 0) {
+    if (reps == 0) return fail(c, MS_E_ARG, "in-loop timing is recorded for kernel 0 only");
+    return time_loop_kernel(c, kernel, prec, reps, avg_us, bytes);
   }
   return time_cg_spmv(c, prec, reps, avg_us, bytes);
 }

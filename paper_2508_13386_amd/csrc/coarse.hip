@@ -2,9 +2,10 @@
 // Eq. (LBS): the columns of U at vertex v are phi_vi (I_3 (x) [1, x_v - o_i]).
 //
 //   restriction   c = U^T r          one block per handle, fixed-order sums
-//   coarse solve  e = (U^T H U)^-1 c  FP64 Cholesky of the Galerkin matrix,
-//                                     applied as a GEMV with its inverse
-//   prolongation  u += U e            one thread per vertex
+//   coarse solve  e = (U^T H U)^-1 c  explicit inverse of the Galerkin matrix
+//                                     (FP64 Gauss-Jordan), applied as a GEMV
+//                                     (FP32 copy in mixed precision)
+//   prolongation  u += U e            8 lanes per vertex
 // The PCG preconditioner is additive: z = D^-1 r + U (U^T H U)^-1 U^T r with
 // D the 3x3 block diagonal of H (Sec. 3.6 uses the same triple product
 // U^T H U matrix-free; here it is formed once per Newton iteration).
@@ -32,67 +33,118 @@ __global__ void k_sub(int64_t len, const double* __restrict__ a, const double* _
   if (i < len) out[i] = a[i] - b[i];
 }
 
-// Partial restriction over one chunk of a handle's vertex list:
-// part[chunk] = sum_{v in chunk} W_vi (x) (weight_v r_v); chunks of the
-// same handle are contiguous and are summed in order by the GEMV kernel.
-template <typename VT>
-__global__ void __launch_bounds__(64) k_restrict(int nchunks, const int32_t* __restrict__ chunk_beg,
-                                                 const int32_t* __restrict__ hv, const int32_t* __restrict__ hk,
-                                                 const double* __restrict__ vw, const VT* __restrict__ r,
-                                                 const double* __restrict__ weight, double* __restrict__ part,
-                                                 const double* __restrict__ scal) {
-  if (scal && scal[S_DONE] != 0.0) return;
-  const int ch = blockIdx.x;
-  const int e0 = chunk_beg[ch], e1 = chunk_beg[ch + 1];
+// Restriction partials of c = U^T (weight .* v).  One block of 256 threads
+// per chunk of at most kRChunk entries of one handle's vertex list (entries
+// in handle order: vertex hv[e] and weights hw[e] = W_vi, so the weight
+// loads are contiguous); each thread takes four entries with every load
+// issued before any is used (clamped index, zero scale past the chunk end).
+// The chunk's 12 sums are reduced in a fixed order and stored as a partial;
+// the coarse GEMV adds a handle's partials in chunk order (no inter-block
+// communication, hence no device-scope fences).
+constexpr int kRChunk = 1024;
+__global__ void __launch_bounds__(256) k_restrict(const int4* __restrict__ chunk_info, const int32_t* __restrict__ hv,
+                                                  const double* __restrict__ hw, const double* __restrict__ v,
+                                                  const double* __restrict__ weight, double* __restrict__ part,
+                                                  const double* __restrict__ scal) {
+  const int ch = blockIdx.x, t = threadIdx.x;
+  const int4 info = chunk_info[ch];  // {handle, first entry, end entry, unused}
+  const double done = scal ? scal[S_DONE] : 0.0;
+  const int e0 = info.y, e1 = info.z;
+  int vv[4];
+  double w[4][4], sc[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int e = e0 + t + 256 * u;
+    const bool ok = e < e1;
+    const int ec = ok ? e : 0;
+    vv[u] = hv[ec];
+    const double2 wa = *reinterpret_cast<const double2*>(hw + 4 * int64_t(ec));
+    const double2 wb = *reinterpret_cast<const double2*>(hw + 4 * int64_t(ec) + 2);
+    w[u][0] = wa.x;
+    w[u][1] = wa.y;
+    w[u][2] = wb.x;
+    w[u][3] = wb.y;
+    sc[u] = ok ? 1.0 : 0.0;
+  }
+  if (done != 0.0) return;  // the flag is the same for the whole grid
+  double rv[4][3];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) rv[u][a] = v[3 * int64_t(vv[u]) + a];
+  if (weight)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) sc[u] *= weight[vv[u]];
   double acc[12];
 #pragma unroll
   for (int q = 0; q < 12; ++q) acc[q] = 0.0;
-  for (int eb = e0 + 4 * threadIdx.x; eb < e1; eb += 4 * blockDim.x) {
-    int64_t v[4], kk[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const bool ok = eb + u < e1;
-      v[u] = ok ? hv[eb + u] : -1;
-      kk[u] = ok ? hk[eb + u] : 0;
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+      const double wl = sc[u] * w[u][l];
+      acc[l] += wl * rv[u][0];
+      acc[4 + l] += wl * rv[u][1];
+      acc[8 + l] += wl * rv[u][2];
     }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      if (v[u] < 0) continue;
-      const double* w = vw + 4 * kk[u];
-      const double s = weight ? weight[v[u]] : 1.0;
-      const double r0 = s * double(r[3 * v[u]]), r1 = s * double(r[3 * v[u] + 1]), r2 = s * double(r[3 * v[u] + 2]);
-#pragma unroll
-      for (int l = 0; l < 4; ++l) {
-        acc[l] += w[l] * r0;
-        acc[4 + l] += w[l] * r1;
-        acc[8 + l] += w[l] * r2;
-      }
-    }
-  }
   block_sum<12>(acc);
-  if (threadIdx.x == 0)
+  if (t < 12) {
+    double out = 0.0;
 #pragma unroll
-    for (int q = 0; q < 12; ++q) part[12 * ch + q] = acc[q];
+    for (int q = 0; q < 12; ++q)
+      if (t == q) out = acc[q];
+    part[12 * int64_t(ch) + t] = out;
+  }
 }
 
-// c = U^T v from the restriction partials: handle i owns chunks
-// hchunk[i] .. hchunk[i+1], summed in order.
-__global__ void k_chunk_sum(int r, const int32_t* __restrict__ hchunk, const double* __restrict__ part,
-                            double* __restrict__ c, const double* __restrict__ scal) {
-  if (scal && scal[S_DONE] != 0.0) return;
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= r) return;
-  const int i = q / 12, comp = q % 12;
-  const int c0 = hchunk[i], c1 = hchunk[i + 1];
-  double s = 0.0;
-  for (int cb = c0; cb < c1; cb += 4) {
-    double v[4];
+// e = A c for a dense row-major r x r matrix A (FP64, or its FP32 copy in
+// mixed precision; leading dimension ld a multiple of 4) with c given by the
+// restriction partials: every block first forms c in LDS (c_(12 i + q) = sum
+// of handle i's partials q, in chunk order), then one wave per row, 8 rows
+// per 512-thread block.
+constexpr int kGemvRows = 8;
+template <typename AT>
+__global__ void __launch_bounds__(64 * kGemvRows) k_coarse_gemv(int r, int ld, const AT* __restrict__ A,
+                                                      const int2* __restrict__ hinfo,
+                                                      const double* __restrict__ part, double* __restrict__ e,
+                                                      const double* __restrict__ scal) {
+  extern __shared__ double sc[];
+  const double done = scal ? scal[S_DONE] : 0.0;
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  const int row = blockIdx.x * kGemvRows + wave;
+  const AT* a = A + int64_t(row < r ? row : 0) * ld;
+  constexpr int VW = 16 / sizeof(AT);  // elements per 16-byte load
+  // the first columns of the row are loaded before the flag is tested
+  AT a0[VW];
+  {
+    const int j = VW * lane;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) v[u] = (cb + u < c1) ? part[12 * (cb + u) + comp] : 0.0;
-#pragma unroll
-    for (int u = 0; u < 4; ++u) s += v[u];
+    for (int q = 0; q < VW; ++q) a0[q] = j + q < r ? a[j + q] : AT(0);
   }
-  c[q] = s;
+  if (done != 0.0) return;  // the flag is the same for the whole grid
+  for (int idx = t; idx < r; idx += blockDim.x) {
+    const int2 hi = hinfo[idx / 12];
+    const int q = idx % 12;
+    double s = 0.0;
+    for (int k = 0; k < hi.y; ++k) s += part[12 * int64_t(hi.x + k) + q];
+    sc[idx] = s;
+  }
+  __syncthreads();
+  if (row >= r) return;
+  double s = 0.0;
+  {
+    const int j = VW * lane;
+#pragma unroll
+    for (int q = 0; q < VW; ++q)
+      if (j + q < r) s += double(a0[q]) * sc[j + q];
+  }
+  for (int j = VW * lane + 64 * VW; j < r; j += 64 * VW) {
+#pragma unroll
+    for (int q = 0; q < VW; ++q)
+      if (j + q < r) s += double(a[j + q]) * sc[j + q];
+  }
+  s = wave_sum(s);
+  if (lane == 0) e[row] = s;
 }
 
 // e = A c for a dense row-major r x r matrix (leading dimension ld), one
@@ -109,6 +161,56 @@ __global__ void __launch_bounds__(256) k_gemv(int r, int ld, const double* __res
   for (int j = lane; j < r; j += 64) s += a[j] * c[j];
   s = wave_sum(s);
   if (lane == 0) e[row] = s;
+}
+
+// u_v += sum_i W_vi (x) e_i with 8 lanes per vertex (entry j of the vertex on
+// lane j mod 8), reduced across the 8 lanes in a fixed order.
+__global__ void __launch_bounds__(256) k_prolong8(int64_t n, const int32_t* __restrict__ vptr,
+                                                  const int32_t* __restrict__ vh, const double* __restrict__ vw,
+                                                  const double* __restrict__ e, const uint8_t* __restrict__ pinned,
+                                                  double* __restrict__ u, const double* __restrict__ scal) {
+  const double done = scal ? scal[S_DONE] : 0.0;
+  const int64_t v = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 3;
+  const int j = threadIdx.x & 7;
+  const int64_t vc = v < n ? v : 0;
+  const bool active = v < n && !(pinned && pinned[vc]);
+  const int k0 = vptr[vc], k1 = vptr[vc + 1];
+  const double uo = u[3 * vc + (j < 3 ? j : 0)];
+  // first entry of this lane, loads issued unconditionally (clamped)
+  const int kf = k0 + j;
+  const int kc = kf < k1 ? kf : 0;
+  const int hf = vh[kc];
+  const double2 wa = *reinterpret_cast<const double2*>(vw + 4 * int64_t(kc));
+  const double2 wb = *reinterpret_cast<const double2*>(vw + 4 * int64_t(kc) + 2);
+  if (done != 0.0) return;  // the flag is the same for the whole grid
+  double a[3] = {0.0, 0.0, 0.0};
+  {
+    const double fw = (active && kf < k1) ? 1.0 : 0.0;
+    const double w[4] = {fw * wa.x, fw * wa.y, fw * wb.x, fw * wb.y};
+    const double* q = e + 12 * int64_t(hf);
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+      a[0] += w[l] * q[l];
+      a[1] += w[l] * q[4 + l];
+      a[2] += w[l] * q[8 + l];
+    }
+  }
+  if (active)
+    for (int k = kf + 8; k < k1; k += 8) {  // vertices with more than 8 handles
+      const double* wk = vw + 4 * int64_t(k);
+      const double* q = e + 12 * int64_t(vh[k]);
+#pragma unroll
+      for (int l = 0; l < 4; ++l) {
+        a[0] += wk[l] * q[l];
+        a[1] += wk[l] * q[4 + l];
+        a[2] += wk[l] * q[8 + l];
+      }
+    }
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int o = 4; o > 0; o >>= 1) a[i] += __shfl_xor(a[i], o, 64);
+  if (active && j < 3) u[3 * v + j] = uo + (j == 0 ? a[0] : (j == 1 ? a[1] : a[2]));
 }
 
 // u_v += sum_i W_vi (x) e_i, entries batched four at a time.
@@ -132,21 +234,6 @@ __device__ __forceinline__ void prolong_sum(int k0, int k1, const int32_t* __res
       }
     }
   }
-}
-
-template <typename VT>
-__global__ void __launch_bounds__(64) k_prolong(int64_t n, const int32_t* __restrict__ vptr,
-                                                const int32_t* __restrict__ vh, const double* __restrict__ vw,
-                                                const double* __restrict__ e, const uint8_t* __restrict__ pinned,
-                                                VT* __restrict__ u, const double* __restrict__ scal) {
-  if (scal && scal[S_DONE] != 0.0) return;
-  const int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (v >= n || (pinned && pinned[v])) return;
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-  prolong_sum(vptr[v], vptr[v + 1], vh, vw, e, a0, a1, a2);
-  u[3 * v] = VT(double(u[3 * v]) + a0);
-  u[3 * v + 1] = VT(double(u[3 * v + 1]) + a1);
-  u[3 * v + 2] = VT(double(u[3 * v + 2]) + a2);
 }
 
 // Stage 1: one thread per (v, j) entry of Z = H U.
@@ -228,6 +315,7 @@ ms_status install_basis(ms_ctx* c, Basis&& B) {
   if (int64_t(B.vptr.size()) != n + 1 || B.vptr[0] != 0) return fail(c, MS_E_ARG, "bad vptr");
   const int64_t nnz = B.vptr[n];
   if (nnz > (int64_t(1) << 30)) return fail(c, MS_E_ARG, "basis too large");
+  if (nnz < 1) return fail(c, MS_E_ARG, "basis has no entries");
   B.nnz = nnz;
   for (int64_t k = 0; k < nnz; ++k)
     if (B.vhandle[k] < 0 || B.vhandle[k] >= m || !std::isfinite(B.vphi[k]))
@@ -255,14 +343,21 @@ ms_status install_basis(ms_ctx* c, Basis&& B) {
         hk[pos] = int32_t(k);
       }
   }
-  // restriction chunks: each handle's vertex list split into runs of at most kChunk
-  constexpr int kChunk = 256;
-  std::vector<int32_t> hchunk(m + 1, 0), chunk_beg;
+  // restriction chunks: handle i's entries split into runs of kRChunk
+  std::vector<double> hw(4 * size_t(std::max<int64_t>(nnz, 1)));
+  for (int64_t e = 0; e < nnz; ++e)
+    for (int l = 0; l < 4; ++l) hw[4 * e + l] = vw[4 * size_t(hk[e]) + l];
+  std::vector<int4> chunk_info;
+  std::vector<int2> hinfo(m);
   for (int i = 0; i < m; ++i) {
-    for (int32_t e = hptr[i]; e < hptr[i + 1]; e += kChunk) chunk_beg.push_back(e);
-    hchunk[i + 1] = int32_t(chunk_beg.size());
+    const int nchk = std::max(1, (hptr[i + 1] - hptr[i] + kRChunk - 1) / kRChunk);
+    hinfo[i] = make_int2(int(chunk_info.size()), nchk);
+    for (int q = 0; q < nchk; ++q) {
+      const int e0 = hptr[i] + q * kRChunk;
+      chunk_info.push_back(make_int4(i, e0, std::min(hptr[i + 1], e0 + kRChunk), 0));
+    }
   }
-  chunk_beg.push_back(hptr[m]);
+  const int32_t nrchunks = int32_t(chunk_info.size());
   // Galerkin stage-1 lists: for each vertex v the handles reachable through
   // its Hessian row, h'(v) = union of h(w) for w in N(v)
   const Pattern& P = c->pat;
@@ -401,23 +496,24 @@ ms_status install_basis(ms_ctx* c, Basis&& B) {
   if ((s = upload(c, &D.d_vptr, vptr.data(), vptr.size())) || (s = upload(c, &D.d_vh, B.vhandle.data(), nnz)) ||
       (s = upload(c, &D.d_vw, vw.data(), vw.size())) || (s = upload(c, &D.d_hptr, hptr.data(), hptr.size())) ||
       (s = upload(c, &D.d_hv, hv.data(), nnz)) || (s = upload(c, &D.d_hk, hk.data(), nnz)) ||
-      (s = upload(c, &D.d_hchunk, hchunk.data(), hchunk.size())) ||
-      (s = upload(c, &D.d_chunk_beg, chunk_beg.data(), chunk_beg.size())) ||
-      (s = alloc_n(c, &D.d_cpart, 12 * (chunk_beg.size() + 1))) ||
       (s = upload(c, &D.d_zptr, zptr.data(), zptr.size())) || (s = upload(c, &D.d_zent, zent.data(), zent.size())) ||
       (s = upload(c, &D.d_zmask, zmask.data(), zmask.size())) || (s = alloc_n(c, &D.d_Z, 36 * std::max<int64_t>(nz, 1))) ||
       (s = upload(c, &D.d_pair_ij, pair_ij.data(), pair_ij.size())) ||
       (s = upload(c, &D.d_pair_ptr, pptr.data(), pptr.size())) ||
       (s = upload(c, &D.d_pair_ent, pent.data(), pent.size())) ||
       (s = upload(c, &D.d_Minv, Minv.data(), Minv.size())) || (s = alloc_n(c, &c->d_c, r)) ||
+      (s = upload(c, &D.d_hw, hw.data(), hw.size())) ||
+      (s = upload(c, &D.d_chunk_info, chunk_info.data(), chunk_info.size())) ||
+      (s = alloc_n(c, &D.d_rpart, 12 * size_t(nrchunks))) || (s = upload(c, &D.d_hinfo, hinfo.data(), hinfo.size())) ||
+      (s = alloc_n(c, &c->d_Ainv32, size_t(rp) * rp)) ||
       (s = alloc_n(c, &c->d_e, r)) || (s = alloc_n(c, &c->d_Ac, size_t(r) * r)) ||
       (s = alloc_n(c, &c->d_Lc, size_t(rp) * rp)) || (s = alloc_n(c, &c->d_Ainv, size_t(rp) * rp)) ||
       (s = alloc_n(c, &c->d_Y, size_t(rp) * rp)) || (s = alloc_n(c, &c->d_Ldiag, size_t(rp) * 64)) ||
       (s = alloc_n(c, &c->d_Linvd, size_t(rp) * 64)) || (s = alloc_n(c, &c->d_diag0, rp + 1)) || (s = alloc_n(c, &c->d_nreg, 4)))
     return s;
+  D.nrchunks = nrchunks;
   D.m = m;
   D.nnz = nnz;
-  D.nchunks = int32_t(chunk_beg.size()) - 1;
   D.nz = nz;
   D.npairs = int32_t(pairs.size());
   D.pair_L = int64_t(pent.size() / 2);
@@ -458,17 +554,37 @@ ms_status launch_galerkin(ms_ctx* c, int prec) {
   return MS_OK;
 }
 
+// e = A^-1 c in the precision of the mode (FP32 inverse in mixed precision).
+void launch_coarse_gemv(ms_ctx* c, int prec) {
+  Basis& D = c->basis;
+  const unsigned nb = nblocks(c->r, kGemvRows);
+  const size_t lds = size_t(c->r) * sizeof(double);
+  if (prec == MS_PREC_MIXED)
+    k_coarse_gemv<float><<<nb, 64 * kGemvRows, lds, c->stream>>>(c->r, c->rp, c->d_Ainv32, D.d_hinfo, D.d_rpart,
+                                                                 c->d_e, c->d_scal);
+  else
+    k_coarse_gemv<double><<<nb, 64 * kGemvRows, lds, c->stream>>>(c->r, c->rp, c->d_Ainv, D.d_hinfo, D.d_rpart,
+                                                                  c->d_e, c->d_scal);
+}
+
+void launch_prolong_add(ms_ctx* c) {
+  Basis& D = c->basis;
+  k_prolong8<<<nblocks(8 * c->n, 256), 256, 0, c->stream>>>(c->n, D.d_vptr, D.d_vh, D.d_vw, c->d_e, c->d_pinned,
+                                                             c->d_u, c->d_scal);
+}
+
+// Restriction partials of U^T (weight .* v) into d_rpart.
+void launch_restrict(ms_ctx* c, const double* v, const double* weight, const double* scal) {
+  Basis& D = c->basis;
+  k_restrict<<<unsigned(D.nrchunks), 256, 0, c->stream>>>(D.d_chunk_info, D.d_hv, D.d_hw, v, weight, D.d_rpart,
+                                                          scal);
+}
+
 // u += U A^-1 U^T v with v = r (from_w false) or the scratch vector w.
 void launch_coarse_correction(ms_ctx* c, int prec, bool from_w) {
-  Basis& D = c->basis;
-  (void)prec;
-  k_restrict<double><<<unsigned(D.nchunks), 64, 0, c->stream>>>(D.nchunks, D.d_chunk_beg, D.d_hv, D.d_hk, D.d_vw,
-                                                               from_w ? c->d_w : c->d_r, nullptr, D.d_cpart,
-                                                               c->d_scal);
-  k_chunk_sum<<<nblocks(c->r, 256), 256, 0, c->stream>>>(c->r, D.d_hchunk, D.d_cpart, c->d_c, c->d_scal);
-  k_gemv<<<nblocks(c->r, 4), 256, 0, c->stream>>>(c->r, c->rp, c->d_Ainv, c->d_c, c->d_e, c->d_scal);
-  k_prolong<double><<<nblocks(c->n, 64), 64, 0, c->stream>>>(c->n, D.d_vptr, D.d_vh, D.d_vw, c->d_e, c->d_pinned,
-                                                              c->d_u, c->d_scal);
+  launch_restrict(c, from_w ? c->d_w : c->d_r, nullptr, c->d_scal);
+  launch_coarse_gemv(c, prec);
+  launch_prolong_add(c);
 }
 
 // Preconditioner applied to r, with u = S r already in place.
@@ -505,11 +621,8 @@ void launch_prolong_set_d(ms_ctx* c) {
 // PCG starting vector d_0 = Q r_0 (r_0 = -g): afterwards r = -g - H d_0 and
 // u = S r.
 void launch_coarse_start(ms_ctx* c, int prec) {
-  Basis& D = c->basis;
-  k_restrict<double><<<unsigned(D.nchunks), 64, 0, c->stream>>>(D.nchunks, D.d_chunk_beg, D.d_hv, D.d_hk, D.d_vw,
-                                                               c->d_r, nullptr, D.d_cpart, c->d_scal);
-  k_chunk_sum<<<nblocks(c->r, 256), 256, 0, c->stream>>>(c->r, D.d_hchunk, D.d_cpart, c->d_c, c->d_scal);
-  k_gemv<<<nblocks(c->r, 4), 256, 0, c->stream>>>(c->r, c->rp, c->d_Ainv, c->d_c, c->d_e, c->d_scal);
+  launch_restrict(c, c->d_r, nullptr, c->d_scal);
+  launch_coarse_gemv(c, prec);
   launch_prolong_set_d(c);
   launch_spmv_resid(c, prec, true);  // r = r - H d
   launch_bj(c, prec);                 // u = S r
@@ -520,10 +633,9 @@ ms_status coarse_coordinates(ms_ctx* c, const double* x_dev, double* q_host, dou
   Basis& D = c->basis;
   // d_w <- x - rest (scratch)
   k_sub<<<nblocks(3 * c->n, 256), 256, 0, c->stream>>>(3 * c->n, x_dev, c->d_rest, c->d_w);
-  k_restrict<double><<<unsigned(D.nchunks), 64, 0, c->stream>>>(D.nchunks, D.d_chunk_beg, D.d_hv, D.d_hk, D.d_vw,
-                                                               c->d_w, c->d_mass, D.d_cpart, nullptr);
-  k_chunk_sum<<<nblocks(c->r, 256), 256, 0, c->stream>>>(c->r, D.d_hchunk, D.d_cpart, c->d_c, nullptr);
-  k_gemv<<<nblocks(c->r, 4), 256, 0, c->stream>>>(c->r, c->r, D.d_Minv, c->d_c, q_dev ? q_dev : c->d_e, nullptr);
+  launch_restrict(c, c->d_w, c->d_mass, nullptr);
+  k_coarse_gemv<double><<<nblocks(c->r, kGemvRows), 64 * kGemvRows, size_t(c->r) * sizeof(double), c->stream>>>(
+      c->r, c->r, D.d_Minv, D.d_hinfo, D.d_rpart, q_dev ? q_dev : c->d_e, nullptr);
   if (q_host)
     MS_HIP(hipMemcpyAsync(q_host, q_dev ? q_dev : c->d_e, c->r * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   return sync(c);

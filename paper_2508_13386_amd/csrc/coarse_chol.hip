@@ -191,6 +191,15 @@ __global__ void k_pad_copy(int r, int rp, const double* __restrict__ A, double* 
   }
 }
 
+// FP32 copy of the inverse, symmetrised: out_ij = (A_ij + A_ji) / 2.
+__global__ void k_inverse_f32(int rp, const double* __restrict__ A, float* __restrict__ out) {
+  for (int64_t q = threadIdx.x + int64_t(blockIdx.x) * blockDim.x; q < int64_t(rp) * rp;
+       q += int64_t(blockDim.x) * gridDim.x) {
+    const int64_t i = q / rp, j = q % rp;
+    out[q] = float(0.5 * (A[q] + A[j * rp + i]));
+  }
+}
+
 ms_status coarse_factor(ms_ctx* c) {
   const int r = c->r, rp = c->rp, nt = rp / NB;
   MS_HIP(hipMemsetAsync(c->d_nreg, 0, sizeof(int), c->stream));
@@ -204,6 +213,7 @@ ms_status coarse_factor(ms_ctx* c) {
     }
     k_gj_fix<<<unsigned(nt), 256, 0, c->stream>>>(rp, k, c->d_Ainv, c->d_Y, c->d_Lc, c->d_Linvd);
   }
+  k_inverse_f32<<<1024, 256, 0, c->stream>>>(rp, c->d_Ainv, c->d_Ainv32);
   c->coarse_valid = 1;
   return MS_OK;
 }

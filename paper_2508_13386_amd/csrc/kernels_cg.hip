@@ -26,33 +26,63 @@
 
 namespace ms {
 
-// Row sums of y = A x for the rows of slice s handled by this wave; lane =
-// kq * S + r serves row S s + r and block columns k = kq, kq + R, ...
-// (R = 64 / S).  Every lane of a row returns the full sum.
+// Row sums of y = A x for the rows of one slice (slots base .. base + width S)
+// handled by this wave; lane = kq * S + r serves row r of the slice and
+// block columns k = kq, kq + R, ... (R = 64 / S).  Columns are taken four at
+// a time with every load of a batch issued before any is used (column
+// index, nine values, three x entries), so the index -> x dependence costs
+// one memory latency per batch instead of one per block.  Padding slots
+// (column -1, zero values) and batch positions past the row end read x at
+// column 0 and are weighted by zero.  Every lane of a row returns the full
+// sum.
 template <typename VT, typename XT, int S>
-__device__ __forceinline__ void row_product(int64_t s, int lane, const int32_t* __restrict__ slice_base,
-                                            const int32_t* __restrict__ scol, const VT* __restrict__ vals,
-                                            const XT* __restrict__ x, double y[3]) {
+__device__ __forceinline__ void row_product_range(int base, int width, int lane, const int32_t* __restrict__ scol,
+                                                  const VT* __restrict__ vals, const XT* __restrict__ x,
+                                                  double y[3]) {
   constexpr int R = 64 / S;
+  constexpr int NB = 4;
   const int r = lane % S, kq = lane / S;
-  const int base = slice_base[s];
-  const int width = (slice_base[s + 1] - base) / S;
   y[0] = y[1] = y[2] = 0.0;
-  for (int k = kq; k < width; k += R) {
-    const int64_t slot = int64_t(base) + int64_t(k) * S + r;
-    const int col = scol[slot];
-    if (col < 0) continue;
-    const VT* a = vals + vbase(slot, S);
-    const double x0 = double(x[3 * int64_t(col)]), x1 = double(x[3 * int64_t(col) + 1]),
-                 x2 = double(x[3 * int64_t(col) + 2]);
-    y[0] += double(a[0]) * x0 + double(a[S]) * x1 + double(a[2 * S]) * x2;
-    y[1] += double(a[3 * S]) * x0 + double(a[4 * S]) * x1 + double(a[5 * S]) * x2;
-    y[2] += double(a[6 * S]) * x0 + double(a[7 * S]) * x1 + double(a[8 * S]) * x2;
+  for (int k0 = kq; k0 < width; k0 += NB * R) {
+    int64_t slot[NB];
+    int col[NB];
+    double f[NB];
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int k = k0 + u * R;
+      slot[u] = int64_t(base) + int64_t(k < width ? k : k0) * S + r;
+      col[u] = scol[slot[u]];
+    }
+    double a[NB][9], xv[NB][3];
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int k = k0 + u * R;
+      f[u] = (k < width && col[u] >= 0) ? 1.0 : 0.0;
+      const int64_t cc = col[u] >= 0 ? col[u] : 0;
+      const VT* ap = vals + vbase(slot[u], S);
+#pragma unroll
+      for (int q = 0; q < 9; ++q) a[u][q] = double(ap[q * S]);
+#pragma unroll
+      for (int q = 0; q < 3; ++q) xv[u][q] = double(x[3 * cc + q]);
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u)
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+        y[i] += f[u] * (a[u][3 * i] * xv[u][0] + a[u][3 * i + 1] * xv[u][1] + a[u][3 * i + 2] * xv[u][2]);
   }
 #pragma unroll
   for (int o = S; o < 64; o <<= 1)
 #pragma unroll
     for (int i = 0; i < 3; ++i) y[i] += __shfl_xor(y[i], o, 64);
+}
+
+template <typename VT, typename XT, int S>
+__device__ __forceinline__ void row_product(int64_t s, int lane, const int32_t* __restrict__ slice_base,
+                                            const int32_t* __restrict__ scol, const VT* __restrict__ vals,
+                                            const XT* __restrict__ x, double y[3]) {
+  const int base = slice_base[s];
+  row_product_range<VT, XT, S>(base, (slice_base[s + 1] - base) / S, lane, scol, vals, x, y);
 }
 
 // One slice per wave, 4 waves per block.
@@ -112,14 +142,18 @@ __global__ void __launch_bounds__(256) k_cg_spmv(int64_t n, int64_t nslices, con
                                                  const double* __restrict__ u, double* __restrict__ w,
                                                  const double* __restrict__ r, const uint8_t* __restrict__ pinned,
                                                  const double* __restrict__ scal, double* __restrict__ part) {
-  if (scal[S_DONE] != 0.0) return;
+  const double done = scal[S_DONE];
   const int64_t s = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int64_t row = s * S + lane % S;
+  const bool has = s < nslices;
+  const int base = has ? slice_base[s] : 0;
+  const int width = has ? (slice_base[s + 1] - base) / S : 0;
+  if (done != 0.0) return;  // the flag is the same for the whole grid
   double dots[3] = {0.0, 0.0, 0.0};
-  if (s < nslices) {
+  if (has) {
     double acc[3];
-    row_product<VT, double, S>(s, lane, slice_base, scol, vals, u, acc);
+    row_product_range<VT, double, S>(base, width, lane, scol, vals, u, acc);
     if (lane < S && row < n) {
       const bool pin = pinned[row];
 #pragma unroll
@@ -151,15 +185,31 @@ __device__ __forceinline__ void bj_apply(const VT* __restrict__ Dinv, int64_t v,
 // Every block reduces the SpMV partials in the same order (identical,
 // deterministic scalars in all blocks), block 0 records the recurrence state
 // and the done flag, then p = u + beta p, s = w + beta s, d += alpha p,
-// r -= alpha s, u = S r.
+// r -= alpha s, u = S r.  The vector operands are loaded before the partials
+// are reduced so that both memory latencies overlap.
 template <typename VT>
-__global__ void __launch_bounds__(256) k_cg_update(int64_t n, int nparts, const double* __restrict__ part,
-                                                   const double* __restrict__ st_in, double* __restrict__ st_out,
-                                                   double* __restrict__ p, double* __restrict__ s,
-                                                   double* __restrict__ d, double* __restrict__ r,
-                                                   double* __restrict__ u, const double* __restrict__ w,
-                                                   const VT* __restrict__ Dinv, double* __restrict__ scal) {
-  if (scal[S_DONE] != 0.0) return;
+__global__ void __launch_bounds__(kUpdBlock) k_cg_update(int64_t n, int nparts, const double* __restrict__ part,
+                                                         const double* __restrict__ st_in, double* __restrict__ st_out,
+                                                         double* __restrict__ p, double* __restrict__ s,
+                                                         double* __restrict__ d, double* __restrict__ r,
+                                                         double* __restrict__ u, const double* __restrict__ w,
+                                                         const VT* __restrict__ Dinv, double* __restrict__ scal) {
+  const double done = scal[S_DONE];
+  const int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const bool own = v < n;
+  double uo[3], po[3], wo[3], so[3], ro[3], dd[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const int64_t k = own ? 3 * v + i : 0;
+    uo[i] = u[k];
+    po[i] = p[k];
+    wo[i] = w[k];
+    so[i] = s[k];
+    ro[i] = r[k];
+  }
+#pragma unroll
+  for (int q = 0; q < 9; ++q) dd[q] = double(Dinv[own ? 9 * v + q : q]);
+  if (done != 0.0) return;  // the flag is the same for the whole grid
   double dots[3] = {0.0, 0.0, 0.0};
   for (int b = threadIdx.x; b < nparts; b += blockDim.x)
 #pragma unroll
@@ -179,26 +229,23 @@ __global__ void __launch_bounds__(256) k_cg_update(int64_t n, int nparts, const 
       scal[S_ITER] = st_in[ST_ITER] + 1.0;
     }
   }
-  if (code != 0) return;
-  const int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (v >= n) return;
+  if (code != 0 || !own) return;
   double rr[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     const int64_t k = 3 * v + i;
-    const double pi = u[k] + beta * p[k];
-    const double si = w[k] + beta * s[k];
+    const double pi = uo[i] + beta * po[i];
+    const double si = wo[i] + beta * so[i];
     p[k] = pi;
     s[k] = si;
     d[k] += alpha * pi;
-    rr[i] = r[k] - alpha * si;
+    rr[i] = ro[i] - alpha * si;
     r[k] = rr[i];
   }
-  double uu[3];
-  bj_apply<VT>(Dinv, v, rr, uu);
 #pragma unroll
-  for (int i = 0; i < 3; ++i) u[3 * v + i] = uu[i];
+  for (int i = 0; i < 3; ++i) u[3 * v + i] = dd[3 * i] * rr[0] + dd[3 * i + 1] * rr[1] + dd[3 * i + 2] * rr[2];
 }
+
 
 // d = 0, r = -g (zero on pinned DOFs), u = S r, p = s = 0; rho0 = r.r and the
 // PCG scalars are initialised in the last block, with the forcing term
@@ -492,9 +539,68 @@ void launch_cg_init(ms_ctx* c, int prec, double eta_max, double eta_min, bool fi
 
 // One PCG iteration; `parity` selects the recurrence-state buffers
 // (iteration k reads state k % 2 and writes (k + 1) % 2).
+void launch_cg_update(ms_ctx* c, int prec, int parity) {
+  const unsigned nbs = unsigned((c->pat.nslices + 3) / 4), nb = nblocks(c->n, kUpdBlock);
+  const double* st_in = c->d_cgst + ST_N * parity;
+  double* st_out = c->d_cgst + ST_N * (1 - parity);
+  if (prec == MS_PREC_FP64)
+    k_cg_update<double><<<nb, kUpdBlock, 0, c->stream>>>(c->n, int(nbs), c->d_part, st_in, st_out, c->d_p, c->d_s,
+                                                         c->d_d, c->d_r, c->d_u, c->d_w, c->d_Dinv, c->d_scal);
+  else
+    k_cg_update<float><<<nb, kUpdBlock, 0, c->stream>>>(c->n, int(nbs), c->d_part, st_in, st_out, c->d_p, c->d_s,
+                                                        c->d_d, c->d_r, c->d_u, c->d_w, c->d_Dinv32, c->d_scal);
+}
+
+// Average duration of `reps` back-to-back launches of one kernel of the PCG
+// loop on the current buffers (1 update, 2 restriction, 3 coarse GEMV,
+// 4 prolongation, 5 one whole iteration), with its algorithmic bytes.
+ms_status time_loop_kernel(ms_ctx* c, int kernel, int prec, int reps, double* avg_us, double* bytes) {
+  const int pc = c->has_basis ? MS_PC_TWO_LEVEL_ADDITIVE : MS_PC_BLOCK_JACOBI;
+  if (kernel >= 2 && kernel <= 4 && !c->has_basis) return fail(c, MS_E_ORDER, "no basis");
+  const double n = double(c->n), vb = prec == MS_PREC_FP64 ? 8.0 : 4.0;
+  const double nnz = double(c->basis.nnz), r = double(c->r);
+  auto run = [&]() {
+    switch (kernel) {
+      case 1: launch_cg_update(c, prec, 0); break;
+      case 2: launch_restrict(c, c->d_r, nullptr, c->d_scal); break;
+      case 3: launch_coarse_gemv(c, prec); break;
+      case 4: launch_prolong_add(c); break;
+      default: launch_cg_iteration(c, prec, pc, 0); break;
+    }
+  };
+  switch (kernel) {
+    case 1: *bytes = n * (6 * 24 + 9 * vb) + n * 5 * 24; break;
+    case 2: *bytes = nnz * (4 + 32) + 24 * n + 8 * r; break;
+    case 3: *bytes = r * r * (prec == MS_PREC_FP64 ? 8 : 4) + 16 * r; break;
+    case 4: *bytes = 4 * n + nnz * (4 + 32) + 8 * r + 48 * n + n; break;
+    default: *bytes = 0.0; break;
+  }
+  MS_HIP(hipMemsetAsync(c->d_scal + S_DONE, 0, sizeof(double), c->stream));
+  for (int i = 0; i < 3; ++i) run();
+  hipEvent_t e0, e1;
+  MS_HIP(hipEventCreate(&e0));
+  MS_HIP(hipEventCreate(&e1));
+  MS_HIP(hipEventRecord(e0, c->stream));
+  for (int i = 0; i < reps; ++i) {
+    // the update may flag convergence, which would turn later replays into
+    // early exits; it and the whole iteration re-clear the flag (a memset
+    // between launches, included in their time)
+    if (kernel == 1 || kernel == 5) MS_HIP(hipMemsetAsync(c->d_scal + S_DONE, 0, sizeof(double), c->stream));
+    run();
+  }
+  MS_HIP(hipEventRecord(e1, c->stream));
+  MS_HIP(hipEventSynchronize(e1));
+  float ms = 0.0f;
+  MS_HIP(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *avg_us = 1e3 * double(ms) / reps;
+  return MS_OK;
+}
+
 void launch_cg_iteration(ms_ctx* c, int prec, int pc, int parity, hipEvent_t ev0, hipEvent_t ev1) {
   const int64_t ns = c->pat.nslices;
-  const unsigned nbs = unsigned((ns + 3) / 4), nb = nblocks(c->n, 256);
+  const unsigned nbs = unsigned((ns + 3) / 4), nb = nblocks(c->n, kUpdBlock);
   const double* st_in = c->d_cgst + ST_N * parity;
   double* st_out = c->d_cgst + ST_N * (1 - parity);
   with_slice(c->pat.S, [&](auto SS) {
@@ -514,12 +620,7 @@ void launch_cg_iteration(ms_ctx* c, int prec, int pc, int parity, hipEvent_t ev0
     else
       go(k_cg_spmv<float, S>, (const float*)c->d_vals32);
   });
-  if (prec == MS_PREC_FP64)
-    k_cg_update<double><<<nb, 256, 0, c->stream>>>(c->n, int(nbs), c->d_part, st_in, st_out, c->d_p, c->d_s, c->d_d,
-                                                   c->d_r, c->d_u, c->d_w, c->d_Dinv, c->d_scal);
-  else
-    k_cg_update<float><<<nb, 256, 0, c->stream>>>(c->n, int(nbs), c->d_part, st_in, st_out, c->d_p, c->d_s, c->d_d,
-                                                  c->d_r, c->d_u, c->d_w, c->d_Dinv32, c->d_scal);
+  launch_cg_update(c, prec, parity);
   launch_precond_apply(c, prec, pc);
 }
 

@@ -60,10 +60,15 @@ struct Basis {
   int32_t* d_hptr = nullptr;      // [m+1]
   int32_t* d_hv = nullptr;        // [nnz] vertex of each (handle, vertex) pair
   int32_t* d_hk = nullptr;        // [nnz] index into the per-vertex arrays
-  int32_t nchunks = 0;            // restriction chunks
-  int32_t* d_hchunk = nullptr;    // [m+1] chunk range of each handle
-  int32_t* d_chunk_beg = nullptr; // [nchunks+1] entry range of each chunk
-  double* d_cpart = nullptr;      // [nchunks][12] restriction partials
+  // restriction: entries in handle order with their weights, split into
+  // chunks of at most 1024 entries; chunk q is described by
+  // chunk_info[q] = {handle, first entry, end entry, 0}; handle i owns the
+  // hinfo[i].y chunks starting at hinfo[i].x
+  double* d_hw = nullptr;         // [nnz][4] W of entry e (handle order)
+  int32_t nrchunks = 0;
+  int4* d_chunk_info = nullptr;   // [nrchunks]
+  int2* d_hinfo = nullptr;        // [m]
+  double* d_rpart = nullptr;      // [nrchunks][12] chunk partials
   // Galerkin lists.  Stage 1 (Z = H U): one entry per (v, j in h'(v)) with
   // its (Hessian slot, k_w) contributions; stage 2 (U^T Z): one entry per
   // coarse pair (i <= j) with its (k_v, z) contributions.
@@ -159,6 +164,7 @@ struct ms_ctx {
   double* d_e = nullptr;      // coarse solution [r]
   double* d_Ac = nullptr;     // coarse matrix [r][r] (row-major), then its Cholesky factor
   double* d_Ainv = nullptr;   // explicit inverse of the coarse matrix [r][r]
+  float* d_Ainv32 = nullptr;  // its symmetrised FP32 copy (mixed precision)
   int32_t rp = 0;             // r padded to the factorisation tile
   double* d_Lc = nullptr;     // Cholesky factor workspace [rp][rp]
   double* d_Y = nullptr;      // inverse factor workspace [rp][rp]
@@ -238,6 +244,7 @@ ms_status coarse_coordinates(ms_ctx* c, const double* x_dev, double* q_host, dou
 enum Scal {  // indices into ctx->d_scal
   S_GAMMA = 0, S_DELTA, S_RHO, S_ALPHA, S_BETA, S_GAMMA_OLD, S_ALPHA_OLD, S_ITER, S_DONE, S_TOL2,
   S_RHO0, S_MAXIT, S_E0, S_E1, S_E2, S_E3, S_CCD, S_DOT0, S_DOT1, S_DOT2, S_G0SQ, S_GPREV, S_ETAPREV, S_ETA,
+  S_DE0, S_DE1, S_DE2, S_DE3, S_DE4,
   S_COUNT = 32
 };
 
@@ -248,6 +255,7 @@ void launch_gather_grad(ms_ctx* c, const double* x, double h2, double* g);
 void launch_gather_hess(ms_ctx* c, const double* x, double h2, int prec);
 void launch_block_jacobi(ms_ctx* c, int prec);
 void launch_energy(ms_ctx* c, const double* x, const double* d, double alpha, double h2);
+void launch_energy_delta(ms_ctx* c, const double* x, const double* d, double alpha, double h2);
 void launch_ccd(ms_ctx* c, const double* x, const double* d);
 void launch_dots(ms_ctx* c, const double* a, const double* b, const double* a2, const double* b2,
                  const double* a3, const double* b3);
@@ -261,6 +269,12 @@ void launch_spmv_resid(ms_ctx* c, int prec, bool from_d);
 void launch_bj(ms_ctx* c, int prec);
 void launch_prolong_set_d(ms_ctx* c);
 inline bool two_level(int pc) { return pc == MS_PC_TWO_LEVEL || pc == MS_PC_TWO_LEVEL_ADDITIVE; }
+constexpr int kUpdBlock = 256;  // vertices per PCG update block
+void launch_coarse_gemv(ms_ctx* c, int prec);
+void launch_prolong_add(ms_ctx* c);
+void launch_restrict(ms_ctx* c, const double* v, const double* weight, const double* scal);
+void launch_cg_update(ms_ctx* c, int prec, int parity);
+ms_status time_loop_kernel(ms_ctx* c, int kernel, int prec, int reps, double* avg_us, double* bytes);
 void launch_cg_iteration(ms_ctx* c, int prec, int pc, int parity, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 void launch_precond(ms_ctx* c, int pc, int prec, const double* r, double* z);
 void launch_spmv(ms_ctx* c, int prec, const double* x, double* y);
@@ -278,6 +292,8 @@ ms_status pcg_solve(ms_ctx* c, int prec, int pc, double eta_max, double eta_min,
 ms_status assemble(ms_ctx* c, const double* x, double h2, int prec, bool project, bool need_pc, int pc,
                    bool refresh_coarse);
 ms_status energy(ms_ctx* c, const double* x, const double* d, double alpha, double h2, double parts[4]);
+ms_status energy_delta(ms_ctx* c, const double* x, const double* d, double alpha, double h2, double* dE,
+                       double* err);
 ms_status plain_step(ms_ctx* c, double dt, const ms_solver_params& P, ms_step_stats* st);
 ms_status paper_step(ms_ctx* c, double dt, const ms_solver_params& P, ms_step_stats* st);
 void release_all(ms_ctx* c);

@@ -3,9 +3,9 @@
 // Per Newton iteration: element kernel + atomic-free gathers assemble g
 // (FP64) and H (FP64 or FP32) at x; PCG (block-Jacobi or two-level) solves
 // H d = -g to the forcing tolerance eta = min(eta_max, sqrt(||g|| / ||g_0||));
-// the step is truncated by the half-space CCD bound and backtracked on the
-// FP64 energy until the Armijo condition holds (skipped when the predicted
-// decrease is below the round-off level of E).  The iteration stops after a
+// the step is truncated by the half-space CCD bound and backtracked until the
+// Armijo condition holds on the FP64 energy difference (evaluated term by
+// term, with a round-off allowance).  The iteration stops after a
 // full step with ||d|| <= newton_tol * max(||x - x^t||, abs_floor).
 //
 // Near the minimiser the element Hessians are used without the PSD
@@ -31,6 +31,9 @@ static ms_status restore(ms_ctx* c, ms_status s) {
 }
 
 // Backtracking line search along d from x; returns the accepted alpha.
+// The Armijo test uses the energy difference computed term by term (no
+// cancellation of the large totals), with an allowance of 1e-14 times the
+// magnitude of its terms for round-off.
 ms_status line_search(ms_ctx* c, double h2, double gd, int max_bt, double* alpha_out, int* nbt) {
   double alpha = 1.0;
   ms_status s;
@@ -39,21 +42,13 @@ ms_status line_search(ms_ctx* c, double h2, double gd, int max_bt, double* alpha
     if ((s = read_scal(c))) return s;
     alpha = std::fmin(1.0, c->h_scal[S_CCD]);
   }
-  double e0[4];
-  if ((s = energy(c, c->d_x, nullptr, 0.0, h2, e0))) return s;
-  const double E0 = e0[0] + e0[1] + e0[2] + e0[3];
-  const double scale = std::fabs(e0[0]) + std::fabs(e0[1]) + std::fabs(e0[2]) + std::fabs(e0[3]);
-  if (!std::isfinite(E0)) return fail(c, MS_E_NONFINITE, "non-finite energy");
   int k = 0;
-  if (-gd > 1e-12 * scale) {
-    while (true) {
-      double e1[4];
-      if ((s = energy(c, c->d_x, c->d_d, alpha, h2, e1))) return s;
-      const double E1 = e1[0] + e1[1] + e1[2] + e1[3];
-      if (std::isfinite(E1) && E1 <= E0 + 1e-4 * alpha * gd) break;
-      alpha *= 0.5;
-      if (++k > max_bt) return fail(c, MS_E_LINESEARCH, "no energy decrease within the backtracking budget");
-    }
+  while (true) {
+    double dE, err;
+    if ((s = energy_delta(c, c->d_x, c->d_d, alpha, h2, &dE, &err))) return s;
+    if (std::isfinite(dE) && dE <= 1e-4 * alpha * gd + 1e-14 * err) break;
+    alpha *= 0.5;
+    if (++k > max_bt) return fail(c, MS_E_LINESEARCH, "no energy decrease within the backtracking budget");
   }
   *alpha_out = alpha;
   *nbt = k;
@@ -77,11 +72,9 @@ ms_status try_move(ms_ctx* c, double h2) {
     if ((s = read_scal(c))) return s;
     alpha = std::fmin(1.0, c->h_scal[S_CCD]);
   }
-  double e0[4], e1[4];
-  if ((s = energy(c, c->d_x, nullptr, 0.0, h2, e0))) return s;
-  if ((s = energy(c, c->d_x, c->d_d, alpha, h2, e1))) return s;
-  const double E0 = e0[0] + e0[1] + e0[2] + e0[3], E1 = e1[0] + e1[1] + e1[2] + e1[3];
-  if (std::isfinite(E1) && E1 < E0) launch_axpy(c, c->d_x, c->d_d, alpha, 3 * c->n);
+  double dE, err;
+  if ((s = energy_delta(c, c->d_x, c->d_d, alpha, h2, &dE, &err))) return s;
+  if (std::isfinite(dE) && dE < 0.0) launch_axpy(c, c->d_x, c->d_d, alpha, 3 * c->n);
   return MS_OK;
 }
 

@@ -102,6 +102,7 @@ def lib():
             "ms_mat_spmv": [vp, vp, vp],
             "ms_batch_step": [C.POINTER(C.c_void_p), i32, d, C.POINTER(ms_solver_params), C.POINTER(ms_step_stats)],
             "ms_time_kernel": [vp, i32, i32, i32, C.POINTER(d), C.POINTER(d)],
+            "ms_energy_difference": [vp, dp, dp, d, d, dp],
             "ms_basis_compute": [i64, dp, i64, ip, dp, i64, ip, C.POINTER(ms_basis_params), C.POINTER(C.c_void_p)],
             "ms_basis_get": [vp, C.POINTER(i32), C.POINTER(i64), dp, ip, ip, dp, ip],
         }
@@ -310,6 +311,13 @@ class Context:
             H = np.empty((nnzb.value, 3, 3))
         self._check(self.L.ms_eval(self.h, _ptr(x), float(dt), int(prec), _ptr(e4), _ptr(g), _ptr(H)))
         return e4, g, H
+
+    def ms_energy_difference(self, x, d, alpha, dt):
+        """{dK, h^2 dPsi, h^2 dG, h^2 dB, magnitude} of E(x + alpha d) - E(x)."""
+        x, d = _f64(x), _f64(d)
+        out = np.empty(5)
+        self._check(self.L.ms_energy_difference(self.h, _ptr(x), _ptr(d), float(alpha), float(dt), _ptr(out)))
+        return out
 
     def ms_apply_preconditioner(self, kind, r, prec=PREC_FP64):
         r = _f64(r)

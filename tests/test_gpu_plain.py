@@ -74,6 +74,38 @@ def test_eval_with_barrier(dev):
     c.close()
 
 
+def test_energy_difference_matches_oracle(dev):
+    """E(x + alpha d) - E(x) by parts (the line-search quantity) equals the
+    difference of the oracle's energies where no cancellation hides it, and
+    tends to alpha g.d for small alpha (first-order term)."""
+    s = scenes.inclusion_block(6, seed=1, steps=1)
+    s["halfspace"] = dict(normal=np.array([0.0, 0.0, 1.0]), offset=-0.002, dhat=5e-3, kappa=3e4)
+    rng = np.random.default_rng(4)
+    s["v0"] = 0.1 * rng.standard_normal(s["rest"].shape)
+    c = _ctx(dev, s)
+    x = s["rest"] + 0.004 * rng.standard_normal(s["rest"].shape)
+    x[:, 2] = np.maximum(x[:, 2], -0.0015)
+    d = 0.002 * rng.standard_normal(s["rest"].shape)
+    d[:, 2] = np.abs(d[:, 2])  # away from the plane: barrier stays finite
+    body = fem.Body(s["rest"], s["tets"], s["E"], s["nu"], s["rho"])
+    prob = fem.StepProblem(body, s["x0"], s["v0"], s["dt"], s["gravity"], s["halfspace"])
+    say("energy difference inclusion_block_6")
+    alpha = 0.7
+    got = c.ms_energy_difference(x, d, alpha, s["dt"])
+    p0, p1 = prob.energy_parts(x), prob.energy_parts(x + alpha * d)
+    for k, key in enumerate(("K", "Psi", "G", "B")):
+        ref = p1[key] - p0[key]
+        assert abs(got[k] - ref) <= 1e-9 * (abs(p0[key]) + abs(p1[key])) + 1e-300, key
+    assert got[3] != 0.0  # the barrier term is exercised
+    assert got[4] >= abs(got[:4]).max()
+    # first order: dE / alpha -> g.d
+    gd = float((prob.gradient(x) * d).sum())
+    a = 1e-7
+    small = c.ms_energy_difference(x, d, a, s["dt"])
+    assert abs(small[:4].sum() / a - gd) <= 1e-5 * abs(gd)
+    c.close()
+
+
 @pytest.mark.parametrize("dtype,tol", [(0, 1e-13), (1, 1e-5)])
 def test_spmv_matches_oracle(dev, dtype, tol):
     import torch
