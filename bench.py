@@ -32,6 +32,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_cg_spmv_heterogeneous_block_32.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2508_13386_amd", "csrc", "kernels_cg.hip")
 METRIC = "Newton-PCG timesteps/s at <=1e-6 rel. disp. error; BSR SpMV HBM GB/s vs peak"
 
 
@@ -47,6 +49,13 @@ def parse():
     ap.add_argument("--no-reference", action="store_true", help="skip the plain FP64 block-Jacobi run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=200, help="back-to-back replays of the product kernel")
+    ap.add_argument("--trace-summary", metavar="CSV",
+                    help="only summarise a rocprofv3 kernel_trace.csv: per kernel, the mean duration over all "
+                         "dispatches and over those that did work (longer than --work-us)")
+    ap.add_argument("--work-us", type=float, default=4.0)
+    ap.add_argument("--tail", nargs=2, metavar=("NAME", "N"),
+                    help="with --trace-summary: also split the dispatches of kernels whose name contains NAME "
+                         "into their last N and the rest")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (scale for HBM byte counters)")
     return ap.parse_args()
@@ -70,6 +79,60 @@ def cpu_baseline():
     return dict(value=1.0 / (dt * 8.0), unit="timesteps/s", cores=1, kind="oracle",
                 sample=f"one timestep of the same generator at 16^3 (24,576 tets) took {dt:.1f} s on 1 thread; "
                        f"value = 1/(8 x that), linear tet-count scaling to the 32^3 workload")
+
+
+def measured_traffic(kernel_name):
+    """HBM bytes per launch of the product kernel from the committed counter
+    summary (FETCH_SIZE x copy factor + WRITE_SIZE x copy factor), or None
+    when the summary is missing, was taken for another kernel instance, or
+    the kernel source has changed since."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    fields = {}
+    for line in text.splitlines():
+        if line.startswith("- ") and ": " in line:
+            k, v = line[2:].split(": ", 1)
+            fields[k.strip()] = v.strip().strip("`")
+    src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    if fields.get("kernel_source_sha256") != src or fields.get("kernel") != kernel_name:
+        return None
+    try:
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def trace_summary(path, work_us, tail=None):
+    """Per-kernel dispatch statistics of a rocprofv3 kernel trace.  Kernels of
+    the PCG loop that start after the solve has converged return at once;
+    'working' dispatches are those longer than work_us."""
+    import csv
+    acc = {}
+    with open(path) as f:
+        for row in csv.DictReader(f):
+            d = (int(row["End_Timestamp"]) - int(row["Start_Timestamp"])) * 1e-3
+            a = acc.setdefault(row["Kernel_Name"], [0, 0.0, 0, 0.0])
+            a[0] += 1
+            a[1] += d
+            if d > work_us:
+                a[2] += 1
+                a[3] += d
+    rows = sorted(acc.items(), key=lambda kv: -kv[1][1])
+    for name, (n, tot, nw, totw) in rows[:25]:
+        print(json.dumps({"kernel": name[:90], "dispatches": n, "mean_us": tot / n, "working": nw,
+                          "working_mean_us": (totw / nw) if nw else None, "total_ms": tot * 1e-3}))
+    if tail:
+        key, last = tail[0], int(tail[1])
+        with open(path) as f:
+            ds = sorted((int(r["Start_Timestamp"]), (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3)
+                        for r in csv.DictReader(f) if key in r["Kernel_Name"])
+        for part, sel in (("last", ds[-last:]), ("rest", ds[:-last])):
+            w = [d for _, d in sel if d > work_us]
+            print(json.dumps({"kernel_contains": key, "part": part, "dispatches": len(sel), "working": len(w),
+                              "working_mean_us": sum(w) / len(w) if w else None}))
 
 
 def copy_probe(mib):
@@ -124,6 +187,9 @@ def main():
     if a.copy_probe:
         copy_probe(a.copy_probe)
         return
+    if a.trace_summary:
+        trace_summary(a.trace_summary, a.work_us, a.tail)
+        return
     import scenes
     from paper_2508_13386_amd import ms
 
@@ -135,17 +201,28 @@ def main():
     params = ms.solver_defaults(precision=prec, preconditioner=pc, forcing=1)
     value, elapsed, stats, states, ctx, basis_s = run(dev, s, params, a.warmup, a.steps,
                                                       handles=a.handles if pc != ms.PC_BLOCK_JACOBI else 0)
+    # the product kernel replayed back to back on the last Hessian (hot caches)
+    r_us, _ = ctx.ms_time_kernel(0, prec, a.kernel_reps)
     # roofline of the dominant kernel, the PCG product fused with its dots:
     # one more timestep (outside the timed region) runs with every product
     # launch bracketed by HIP events on the library's stream, inside the real
     # PCG loop; the average over those launches is the kernel's duration.
+    # These are the last product launches of the run (a profile can pick
+    # them out as the kernel's last timed_step_pcg_iters + timed_step_solves
+    # dispatches).
     k = a.warmup + a.steps + 1
     ctx.ms_set_dirichlet(s["dirichlet"], s["dbc_targets"](k))
     tparams = ms.solver_defaults(precision=prec, preconditioner=pc, forcing=1, time_kernels=1)
     tstat = ctx.ms_step(s["dt"], tparams)
     k_us, k_bytes = ctx.ms_time_kernel(0, prec, 0)
-    # the same kernel replayed back to back on the last Hessian (hot caches)
-    r_us, _ = ctx.ms_time_kernel(0, prec, a.kernel_reps)
+    # slice height of the chosen layout, from the byte count of the product
+    # (4 bytes per slice offset; the rest is fixed by nnzb and n)
+    _, col = ctx.ms_get_pattern()
+    n = len(s["rest"])
+    vb = 8 if prec == ms.PREC_FP64 else 4
+    nslices = int(round((k_bytes - len(col) * (9 * vb + 4) - 73 * n) / 4)) - 1
+    S = next(c for c in (16, 32, 64) if -(-n // c) == nslices)
+    kernel_name = f"k_cg_spmv<{'double' if vb == 8 else 'float'}, {S}>"
     achieved = k_bytes / (k_us * 1e-6) / 1e9
     ctx.close()
 
@@ -181,10 +258,11 @@ def main():
                    "handles": a.handles if pc != ms.PC_BLOCK_JACOBI else None,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_cg_spmv (PCG product w = H u fused with its three dots, sliced BSR3)",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kernel_name),
+                     "kernel": kernel_name + " (PCG product w = H u fused with its three dots, sliced BSR3)",
                      "bytes_per_launch": k_bytes, "avg_launch_us": k_us,
                      "timed_step_pcg_iters": int(tstat["pcg_iters"]),
+                     "timed_step_solves": int(tstat["newton_iters"]),
                      "replay_avg_launch_us": r_us,
                      "replay_frac": k_bytes / (r_us * 1e-6) / 1e9 / HBM_PEAK_GBS},
         "solver": {"newton_iters": [st["newton_iters"] for st in stats],

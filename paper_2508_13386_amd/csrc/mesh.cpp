@@ -4,6 +4,7 @@
 // element blocks into Hessian slots and element gradients into vertices
 // without atomics and in a fixed order (so results are bitwise reproducible).
 #include <algorithm>
+#include <cstring>
 #include <cmath>
 #include <cstdlib>
 #include <numeric>
@@ -114,13 +115,18 @@ ms_status build_pattern(ms_ctx* c) {
   P.nnzb = P.h_row_ptr[n];
   P.h_col.resize(P.nnzb);
   for (int64_t v = 0; v < n; ++v) std::copy(adj[v].begin(), adj[v].end(), P.h_col.begin() + P.h_row_ptr[v]);
-  // slice height: forced by MS_SLICE, else 32 rows per slice unless 16 or 64
-  // is at least 3% faster on this pattern (timed FP64 SpMV with constant
-  // values; candidates timed in interleaved rounds, best round kept, so that
-  // the choice is stable under timing noise)
-  int S = 0;
-  if (const char* e = std::getenv("MS_SLICE")) S = std::atoi(e);
-  if (S != 16 && S != 32 && S != 64) {
+  // slice height: 32 rows per slice (two lanes per row), or MS_SLICE = 16,
+  // 32 or 64; MS_SLICE = auto times the three layouts on this pattern (FP64
+  // SpMV with constant values, interleaved rounds, best round kept) and keeps
+  // 32 unless another is at least 3% faster.  The default is fixed so that
+  // runs and profiles of one mesh use the same kernel instance.
+  int S = 32;
+  const char* env = std::getenv("MS_SLICE");
+  if (env && std::strcmp(env, "auto") != 0) {
+    const int want = std::atoi(env);
+    if (want == 16 || want == 32 || want == 64) S = want;
+  }
+  if (env && std::strcmp(env, "auto") == 0) {
     const int cands[3] = {16, 32, 64};
     int32_t *d_sb[3] = {nullptr, nullptr, nullptr}, *d_sc[3] = {nullptr, nullptr, nullptr};
     int64_t ns[3], nsl[3];
