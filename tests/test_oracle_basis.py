@@ -1,0 +1,164 @@
+"""Pins of the basis oracle (Sec. 3.4-3.5) and parity of the library's host
+basis construction with it (CPU only)."""
+import os
+
+import numpy as np
+import pytest
+
+import scenes
+from oracle import basis, linops
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2508_13386_amd", "libms.so")
+
+
+def _octant_partition(rest, tets, k=2):
+    """A simple partitioning independent of the library: k^3 boxes by tet centroid."""
+    c = rest[tets].mean(axis=1)
+    lo, hi = rest.min(axis=0), rest.max(axis=0)
+    idx = np.minimum((k * (c - lo) / (hi - lo)).astype(int), k - 1)
+    return idx[:, 0] * k * k + idx[:, 1] * k + idx[:, 2]
+
+
+def _boundary_vertices(tets, n):
+    f = np.sort(np.concatenate([tets[:, [1, 2, 3]], tets[:, [0, 2, 3]], tets[:, [0, 1, 3]], tets[:, [0, 1, 2]]]),
+                axis=1)
+    u, cnt = np.unique(f, axis=0, return_counts=True)
+    b = np.zeros(n, bool)
+    b[u[cnt == 1].ravel()] = True
+    return b
+
+
+def test_weighted_laplacian_constants_and_affine_fields():
+    rest, tets, _, _ = scenes.kuhn_cube(4)
+    n = len(rest)
+    E = np.full(len(tets), 3.0)
+    L, mv = basis.weighted_laplacian(rest, tets, E)
+    # constants are in the kernel
+    assert np.abs(L @ np.ones(n)).max() <= 1e-12 * np.abs(L).max()
+    # a linear field has zero Laplacian at interior vertices (constant weight)
+    a = np.array([0.3, -1.2, 0.7])
+    f = rest @ a + 0.4
+    interior = ~_boundary_vertices(tets, n)
+    assert interior.sum() > 0
+    assert np.abs((L @ f)[interior]).max() <= 1e-12 * np.abs(L).max()
+    # the stiffness weight scales the operator; lumped volumes sum to the volume
+    L2, _ = basis.weighted_laplacian(rest, tets, 2.5 * E)
+    assert np.abs(L2 - 2.5 * L).max() <= 1e-12 * np.abs(L).max()
+    assert mv.sum() == pytest.approx(1.0, rel=1e-12)
+    # symmetric positive semi-definite
+    assert np.abs(L - L.T).max() == 0.0
+
+
+def test_constrained_biharmonic_is_the_constrained_minimiser():
+    rest, tets, _, _ = scenes.kuhn_cube(3)
+    rng = np.random.default_rng(3)
+    E = np.exp(rng.uniform(np.log(1e5), np.log(1e8), len(tets)))
+    L, mv = basis.weighted_laplacian(rest, tets, E)
+    verts = np.arange(len(rest))
+    fixed = {0: 1.0, 21: 0.0, 42: 0.0, len(rest) - 1: 0.0}
+    u = basis.constrained_biharmonic(L, mv, verts, fixed)
+    for v, val in fixed.items():
+        assert u[v] == val
+    K = (L.T @ np.diag(1.0 / mv) @ L)
+    e0 = u @ K @ u
+    free = np.array([v not in fixed for v in verts])
+    for _ in range(20):
+        d = rng.standard_normal(len(verts)) * free
+        for s in (1e-3, 1e-1):
+            assert (u + s * d) @ K @ (u + s * d) >= e0 * (1 - 1e-12)
+    # first-order optimality on the free rows
+    assert np.abs((K @ u)[free]).max() <= 1e-9 * np.abs(K).max()
+
+
+def _weights(out, n, m):
+    W = np.zeros((n, m))
+    for v, row in enumerate(out["rows"]):
+        for i, phi in row:
+            W[v, i] = phi
+    return W
+
+
+def test_basis_partition_of_unity_support_and_affine_reproduction():
+    s = scenes.plain_cube(6, seed=2)
+    rest, tets = s["rest"], s["tets"]
+    part = _octant_partition(rest, tets)
+    n, m = len(rest), int(part.max()) + 1
+    out = basis.basis_weights(rest, tets, s["E"], [], part)
+    W = _weights(out, n, m)
+    assert (W >= 0).all()
+    assert np.abs(W.sum(axis=1) - 1.0).max() <= 1e-12
+    # support of phi_i inside partition i and its face neighbours
+    for i in range(m):
+        members = {i} | set(out["nbr"][i])
+        dom = np.unique(tets[np.isin(part, sorted(members))])
+        outside = np.setdiff1d(np.arange(n), dom)
+        assert (W[outside, i] == 0).all()
+        assert W[out["centre"][i], i] == pytest.approx(1.0, abs=1e-12)
+    # U q reproduces an affine field exactly (linear precision, Sec. 3.4)
+    vptr = np.zeros(n + 1, np.int64)
+    vptr[1:] = np.cumsum([len(r) for r in out["rows"]])
+    vh = np.array([i for r in out["rows"] for i, _ in r])
+    vw = np.array([p for r in out["rows"] for _, p in r])
+    U = linops.dense_basis(rest, out["origins"], vptr, vh, vw, m)
+    A = np.array([[0.01, 0.002, -0.003], [0.0, -0.004, 0.001], [0.005, 0.0, 0.002]])
+    t = np.array([0.1, -0.2, 0.05])
+    q = np.zeros(12 * m)
+    for i in range(m):
+        o = out["origins"][i]
+        for a in range(3):
+            q[12 * i + 4 * a] = t[a] + A[a] @ o
+            q[12 * i + 4 * a + 1:12 * i + 4 * a + 4] = A[a]
+    assert np.abs(linops.prolong(U, q) - (rest @ A.T + t)).max() <= 1e-13
+
+
+def test_basis_with_dirichlet_vertices():
+    s = scenes.plain_cube(6, seed=4)
+    rest, tets, dbc = s["rest"], s["tets"], s["dirichlet"]
+    part = _octant_partition(rest, tets)
+    n, m = len(rest), int(part.max()) + 1
+    out = basis.basis_weights(rest, tets, s["E"], dbc, part)
+    W = _weights(out, n, m)
+    assert (W[dbc] == 0).all()
+    verts, udbc = out["dbc_weight"]
+    wdbc = np.zeros(n)
+    total = W.sum(axis=1)
+    # where the Dirichlet weight is present, sum phi_i + phi_DBC = 1
+    denom_share = np.zeros(n)
+    denom_share[verts] = udbc
+    covered = total > 0
+    # phi_DBC = u_DBC / (sum u_i + u_DBC): reconstruct from the normalised phi
+    ratio = np.zeros(n)
+    # for vertices reached by some partition: u_DBC / sum u_i = (1 - sum phi) / sum phi
+    ratio[covered] = (1.0 - total[covered]) / total[covered]
+    assert (total <= 1.0 + 1e-12).all()
+    assert (ratio >= -1e-12).all()
+    # the Dirichlet weight is one on the Dirichlet vertices and no partition reaches them
+    assert np.allclose(denom_share[dbc], 1.0)
+    assert (1.0 - total[dbc] == 1.0).all()
+    del wdbc
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+@pytest.mark.parametrize("scene,m,dbc,rtol,atol", [("plain_cube", 8, False, 1e-9, 1e-12),
+                                                   ("inclusion_block", 10, True, 0.0, 2e-5)])
+def test_host_basis_matches_oracle(scene, m, dbc, rtol, atol):
+    """The library's host build (ms_basis_compute) against the oracle, given
+    the library's own partitioning: same handles per vertex, same weights.
+    The local operator K = L M^-1 L scales with E^2, so the 1e5 stiffness
+    contrast of the inclusion block makes its condition number exceed 1e12
+    and two backward-stable sparse solvers (envelope Cholesky, SuperLU) agree
+    to about cond * eps there (weights lie in [0, 1]: compared absolutely);
+    the plain cube's 1e3 contrast allows 1e-9 relative."""
+    from paper_2508_13386_amd import ms
+    s = scenes.plain_cube(6, seed=1) if scene == "plain_cube" else scenes.inclusion_block(8, seed=2, steps=1)
+    d = s["dirichlet"] if dbc else np.zeros(0, np.int32)
+    b = ms.ms_basis_compute(s["rest"], s["tets"], s["E"], d, n_handles=m, seed=5, n_threads=2)
+    out = basis.basis_weights(s["rest"], s["tets"], s["E"], d, b["part"])
+    assert b["m"] == len(out["origins"])
+    assert np.abs(b["origins"] - out["origins"]).max() <= 1e-12
+    for v in range(len(s["rest"])):
+        lib_row = [(int(b["vhandle"][k]), float(b["vphi"][k])) for k in range(b["vptr"][v], b["vptr"][v + 1])]
+        orc_row = out["rows"][v]
+        assert [i for i, _ in lib_row] == [i for i, _ in orc_row], v
+        assert np.allclose([p for _, p in lib_row], [p for _, p in orc_row], rtol=rtol, atol=atol), v
