@@ -95,7 +95,8 @@ typedef struct {
   /* paper mode (Alg. 1 and 2) */
   double paper_eps;        /* termination on mean per-vertex ||d_s,v|| / h  (m/s)       */
   double subspace_rtol;    /* relative residual of the affine and subspace PCG solves   */
-  int32_t refine_iters;    /* fixed Jacobi-PCG iterations of the full-space refinement  */
+  int32_t refine_iters;    /* fixed Jacobi-PCG iterations of the full-space refinement;
+                              0: 20 or 40 from the partitions' mean hop diameter      */
   int32_t lag_window;      /* step sizes averaged by the Hessian-lag trigger             */
   double lag_threshold;    /* refresh the lagged elastic Hessian below this average     */
   int32_t lag_min_gap;     /* at most one refresh every lag_min_gap iterations          */

@@ -224,7 +224,7 @@ void ms_solver_defaults(ms_solver_params* p) {
   p->warm_start = 0;
   p->paper_eps = 1e-3;
   p->subspace_rtol = 1e-4;
-  p->refine_iters = 20;
+  p->refine_iters = 0;
   p->lag_window = 3;
   p->lag_threshold = 0.5;
   p->lag_min_gap = 5;

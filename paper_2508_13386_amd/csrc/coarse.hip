@@ -440,6 +440,76 @@ ms_status install_basis(ms_ctx* c, Basis&& B) {
     }
     pptr.push_back(int32_t(pent.size() / 2));
   }
+  // paper mode: affine weights phi_a(v) = sum_i phi_i(v), the affine origin
+  // (rest centre of mass) and the refinement iteration count from the
+  // partitions' hop diameters (Sec. 3.8.2: the mean over partitions of the
+  // largest number of edge hops from the vertex nearest the partition
+  // centroid to a vertex of the partition, binned to 20 or 40)
+  std::vector<double> phia(n, 0.0);
+  for (int64_t v = 0; v < n; ++v)
+    for (int64_t k = B.vptr[v]; k < B.vptr[v + 1]; ++k) phia[v] += B.vphi[k];
+  {
+    double msum = 0.0, o[3] = {0, 0, 0};
+    for (int64_t v = 0; v < n; ++v) {
+      msum += c->h_mass[v];
+      for (int d = 0; d < 3; ++d) o[d] += c->h_mass[v] * c->h_rest[3 * v + d];
+    }
+    for (int d = 0; d < 3; ++d) c->oa[d] = msum > 0 ? o[d] / msum : 0.0;
+  }
+  c->refine_auto = 20;
+  if (int64_t(B.part.size()) == c->T && !B.part.empty() && B.part[0] >= 0) {
+    std::vector<std::vector<int32_t>> pverts(m);
+    {
+      std::vector<int32_t> last(n, -1);
+      for (int64_t t = 0; t < c->T; ++t) {
+        const int l = B.part[t];
+        if (l < 0 || l >= m) continue;
+        for (int q = 0; q < 4; ++q) {
+          const int32_t v = c->h_tets[4 * t + q];
+          if (last[v] != l) {
+            pverts[l].push_back(v);
+            last[v] = l;
+          }
+        }
+      }
+    }
+    std::vector<int32_t> mark(n, -1), dist(n, 0), queue;
+    double hop_sum = 0.0;
+    int counted = 0;
+    for (int l = 0; l < m; ++l) {
+      auto& pv = pverts[l];
+      std::sort(pv.begin(), pv.end());
+      pv.erase(std::unique(pv.begin(), pv.end()), pv.end());
+      if (pv.empty()) continue;
+      int32_t start = pv[0];
+      double best = 1e300;
+      for (int32_t v : pv) {
+        double dd = 0.0;
+        for (int d = 0; d < 3; ++d) dd += (c->h_rest[3 * v + d] - B.origins[3 * l + d]) * (c->h_rest[3 * v + d] - B.origins[3 * l + d]);
+        if (dd < best) best = dd, start = v;
+      }
+      for (int32_t v : pv) mark[v] = l;
+      queue.assign(1, start);
+      dist[start] = 0;
+      mark[start] = -2 - l;
+      int far = 0;
+      for (size_t qh = 0; qh < queue.size(); ++qh) {
+        const int32_t v = queue[qh];
+        far = std::max(far, dist[v]);
+        for (int32_t k = c->pat.h_row_ptr[v]; k < c->pat.h_row_ptr[v + 1]; ++k) {
+          const int32_t w = c->pat.h_col[k];
+          if (mark[w] == l) {
+            mark[w] = -2 - l;
+            dist[w] = dist[v] + 1;
+            queue.push_back(w);
+          }
+        }
+      }
+      hop_sum += far;
+      ++counted;
+    }
+    if (counted > 0) c->refine_auto = (hop_sum / counted) <= 30.0 ? 20 : 40;
+  }
   // coarse mass matrix (U^T M U) and its inverse for the coarse coordinates
   const int r = 12 * m;
   const int rp = coarse_pad(r);
@@ -505,7 +575,7 @@ ms_status install_basis(ms_ctx* c, Basis&& B) {
       (s = upload(c, &D.d_hw, hw.data(), hw.size())) ||
       (s = upload(c, &D.d_chunk_info, chunk_info.data(), chunk_info.size())) ||
       (s = alloc_n(c, &D.d_rpart, 12 * size_t(nrchunks))) || (s = upload(c, &D.d_hinfo, hinfo.data(), hinfo.size())) ||
-      (s = alloc_n(c, &c->d_Ainv32, size_t(rp) * rp)) ||
+      (s = alloc_n(c, &c->d_Ainv32, size_t(rp) * rp)) || (s = upload(c, &c->d_phia, phia.data(), phia.size())) ||
       (s = alloc_n(c, &c->d_e, r)) || (s = alloc_n(c, &c->d_Ac, size_t(r) * r)) ||
       (s = alloc_n(c, &c->d_Lc, size_t(rp) * rp)) || (s = alloc_n(c, &c->d_Ainv, size_t(rp) * rp)) ||
       (s = alloc_n(c, &c->d_Y, size_t(rp) * rp)) || (s = alloc_n(c, &c->d_Ldiag, size_t(rp) * 64)) ||
@@ -555,22 +625,22 @@ ms_status launch_galerkin(ms_ctx* c, int prec) {
 }
 
 // e = A^-1 c in the precision of the mode (FP32 inverse in mixed precision).
-void launch_coarse_gemv(ms_ctx* c, int prec) {
+void launch_coarse_gemv(ms_ctx* c, int prec, const double* scal) {
   Basis& D = c->basis;
   const unsigned nb = nblocks(c->r, kGemvRows);
   const size_t lds = size_t(c->r) * sizeof(double);
   if (prec == MS_PREC_MIXED)
     k_coarse_gemv<float><<<nb, 64 * kGemvRows, lds, c->stream>>>(c->r, c->rp, c->d_Ainv32, D.d_hinfo, D.d_rpart,
-                                                                 c->d_e, c->d_scal);
+                                                                 c->d_e, scal);
   else
     k_coarse_gemv<double><<<nb, 64 * kGemvRows, lds, c->stream>>>(c->r, c->rp, c->d_Ainv, D.d_hinfo, D.d_rpart,
-                                                                  c->d_e, c->d_scal);
+                                                                  c->d_e, scal);
 }
 
-void launch_prolong_add(ms_ctx* c) {
+void launch_prolong_add(ms_ctx* c, double* target, const double* scal) {
   Basis& D = c->basis;
   k_prolong8<<<nblocks(8 * c->n, 256), 256, 0, c->stream>>>(c->n, D.d_vptr, D.d_vh, D.d_vw, c->d_e, c->d_pinned,
-                                                             c->d_u, c->d_scal);
+                                                             target, scal);
 }
 
 // Restriction partials of U^T (weight .* v) into d_rpart.
@@ -583,8 +653,8 @@ void launch_restrict(ms_ctx* c, const double* v, const double* weight, const dou
 // u += U A^-1 U^T v with v = r (from_w false) or the scratch vector w.
 void launch_coarse_correction(ms_ctx* c, int prec, bool from_w) {
   launch_restrict(c, from_w ? c->d_w : c->d_r, nullptr, c->d_scal);
-  launch_coarse_gemv(c, prec);
-  launch_prolong_add(c);
+  launch_coarse_gemv(c, prec, c->d_scal);
+  launch_prolong_add(c, c->d_u, c->d_scal);
 }
 
 // Preconditioner applied to r, with u = S r already in place.
@@ -622,7 +692,7 @@ void launch_prolong_set_d(ms_ctx* c) {
 // u = S r.
 void launch_coarse_start(ms_ctx* c, int prec) {
   launch_restrict(c, c->d_r, nullptr, c->d_scal);
-  launch_coarse_gemv(c, prec);
+  launch_coarse_gemv(c, prec, c->d_scal);
   launch_prolong_set_d(c);
   launch_spmv_resid(c, prec, true);  // r = r - H d
   launch_bj(c, prec);                 // u = S r

@@ -563,8 +563,8 @@ ms_status time_loop_kernel(ms_ctx* c, int kernel, int prec, int reps, double* av
     switch (kernel) {
       case 1: launch_cg_update(c, prec, 0); break;
       case 2: launch_restrict(c, c->d_r, nullptr, c->d_scal); break;
-      case 3: launch_coarse_gemv(c, prec); break;
-      case 4: launch_prolong_add(c); break;
+      case 3: launch_coarse_gemv(c, prec, c->d_scal); break;
+      case 4: launch_prolong_add(c, c->d_u, c->d_scal); break;
       default: launch_cg_iteration(c, prec, pc, 0); break;
     }
   };

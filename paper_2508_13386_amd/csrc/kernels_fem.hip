@@ -16,6 +16,7 @@
 //   k_ccd          largest safe step toward the half-space
 #include <cfloat>
 
+#include "contact.h"
 #include "ms_internal.h"
 #include "reduce.h"
 
@@ -207,25 +208,6 @@ __global__ void __launch_bounds__(64) k_element(int64_t T, const int32_t* __rest
         }
       ++pr;
     }
-}
-
-struct HalfSpace {
-  double n[3];
-  double off, dhat, kappa;
-  int on;
-};
-
-__device__ __forceinline__ void barrier_terms(double d, double dhat, double& b, double& b1, double& b2) {
-  b = b1 = b2 = 0.0;
-  if (d <= 0.0) {
-    b = INFINITY;
-    return;
-  }
-  if (d >= dhat) return;
-  const double l = log(d / dhat), e = d - dhat;
-  b = -e * e * l;
-  b1 = -2.0 * e * l - e * e / d;
-  b2 = -2.0 * l - 4.0 * e / d + (e * e) / (d * d);
 }
 
 __global__ void k_gather_grad(int64_t n, const int32_t* __restrict__ vt_ptr, const int32_t* __restrict__ vt_code,
@@ -548,15 +530,6 @@ __global__ void k_velocity(int64_t n3, const double* __restrict__ x, const doubl
 
 static inline unsigned nblocks(int64_t n, int b) { return unsigned((n + b - 1) / b); }
 
-static HalfSpace hs_of(ms_ctx* c) {
-  HalfSpace h;
-  for (int i = 0; i < 3; ++i) h.n[i] = c->hs_n[i];
-  h.off = c->hs_off;
-  h.dhat = c->hs_dhat;
-  h.kappa = c->hs_kappa;
-  h.on = c->has_hs ? 1 : 0;
-  return h;
-}
 
 void launch_predict(ms_ctx* c, double dt) {
   k_predict<<<nblocks(3 * c->n, 256), 256, 0, c->stream>>>(3 * c->n, c->d_x, c->d_v, dt, c->d_xt, c->d_xtilde);
@@ -600,6 +573,35 @@ void launch_gather_hess(ms_ctx* c, const double* x, double h2, int prec) {
                                                            c->d_gcode, c->d_He32, c->d_mass, x, h2, hs_of(c),
                                                            c->d_vals32);
 }
+// vals[diag block of v] += sign * h^2 kappa b''(d_v) n n^T (the barrier
+// curvature that the gather kernel adds on diagonal slots).
+template <typename VT>
+__global__ void k_diag_barrier(int64_t n, int S, const int32_t* __restrict__ diag_slot,
+                               const double* __restrict__ x, HalfSpace hs, double h2, double sign,
+                               VT* __restrict__ vals) {
+  const int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  double b, b1, b2;
+  barrier_terms(hs.n[0] * x[3 * v] + hs.n[1] * x[3 * v + 1] + hs.n[2] * x[3 * v + 2] - hs.off, hs.dhat, b, b1, b2);
+  if (b2 == 0.0) return;
+  const double f = sign * h2 * hs.kappa * b2;
+  VT* out = vals + vbase(diag_slot[v], S);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) out[S * (3 * i + j)] = VT(double(out[S * (3 * i + j)]) + f * hs.n[i] * hs.n[j]);
+}
+
+void launch_diag_barrier(ms_ctx* c, int prec, void* vals, const double* x, double h2, double sign) {
+  if (!c->has_hs) return;
+  if (prec == MS_PREC_FP64)
+    k_diag_barrier<double><<<nblocks(c->n, 256), 256, 0, c->stream>>>(c->n, c->pat.S, c->pat.d_diag_slot, x, hs_of(c),
+                                                                      h2, sign, static_cast<double*>(vals));
+  else
+    k_diag_barrier<float><<<nblocks(c->n, 256), 256, 0, c->stream>>>(c->n, c->pat.S, c->pat.d_diag_slot, x, hs_of(c),
+                                                                     h2, sign, static_cast<float*>(vals));
+}
+
 void launch_energy(ms_ctx* c, const double* x, const double* d, double alpha, double h2) {
   const int64_t m = std::max(c->T, c->n);
   k_energy<<<nblocks(m, 256), 256, 0, c->stream>>>(c->T, c->n, c->d_tets, c->d_Dminv, c->d_vol, c->d_mu, c->d_lam,

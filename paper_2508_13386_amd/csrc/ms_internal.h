@@ -183,6 +183,17 @@ struct ms_ctx {
   int eval_prec = 0;
   bool eval_valid = false;
   bool assembled[2] = {false, false};  // a Hessian of that precision is in place
+  // paper mode (Alg. 1 and 2)
+  void* d_lag = nullptr;       // lagged elastic + inertia part of H, [slots][9] in the mode's value type
+  void* d_hlag = nullptr;      // H_lag = lag + barrier curvature at the current x
+  void* d_Dinv_lag = nullptr;  // 3x3 block-Jacobi inverses of H_lag
+  int lag_prec = -1;           // value type the lag buffers were allocated for
+  double* d_ds = nullptr;      // subspace direction d_s [n][3]
+  double* d_gsave = nullptr;   // gradient saved across the refinement solve
+  double* d_phia = nullptr;    // affine weight phi_a(v) = sum_i phi_i(v) [n]
+  double* d_aff = nullptr;     // affine system: columns [12][12], rhs [12], solution [12]
+  double oa[3] = {0, 0, 0};    // origin of the affine basis (rest centre of mass)
+  int refine_auto = 20;        // refinement iterations from the partition hop diameter
   // live timing of the PCG product (time_kernels)
   bool timing = false;
   std::vector<hipEvent_t> tev;      // 2 per iteration of a chunk
@@ -270,8 +281,11 @@ void launch_bj(ms_ctx* c, int prec);
 void launch_prolong_set_d(ms_ctx* c);
 inline bool two_level(int pc) { return pc == MS_PC_TWO_LEVEL || pc == MS_PC_TWO_LEVEL_ADDITIVE; }
 constexpr int kUpdBlock = 256;  // vertices per PCG update block
-void launch_coarse_gemv(ms_ctx* c, int prec);
-void launch_prolong_add(ms_ctx* c);
+void launch_coarse_gemv(ms_ctx* c, int prec, const double* scal);
+void launch_prolong_add(ms_ctx* c, double* target, const double* scal);
+void launch_diag_barrier(ms_ctx* c, int prec, void* vals, const double* x, double h2, double sign);
+ms_status pcg_solve(ms_ctx* c, int prec, int pc, double eta_max, double eta_min, bool first, int max_it, int* iters,
+                    int* code, int forcing);
 void launch_restrict(ms_ctx* c, const double* v, const double* weight, const double* scal);
 void launch_cg_update(ms_ctx* c, int prec, int parity);
 ms_status time_loop_kernel(ms_ctx* c, int kernel, int prec, int reps, double* avg_us, double* bytes);

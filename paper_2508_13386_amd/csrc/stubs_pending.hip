@@ -3,9 +3,6 @@
 #include "ms_internal.h"
 
 namespace ms {
-ms_status paper_step(ms_ctx* c, double, const ms_solver_params&, ms_step_stats*) {
-  return fail(c, MS_E_ORDER, "paper mode not available");
-}
 ms_status warm_start(ms_ctx* c, double, int32_t*) { return fail(c, MS_E_ORDER, "warm start not available"); }
 ms_status record_coarse(ms_ctx*) { return MS_OK; }
 }  // namespace ms

@@ -33,7 +33,7 @@ def test_exports_every_declared_symbol():
 def test_defaults_are_sane():
     from paper_2508_13386_amd import ms
     p = ms.solver_defaults()
-    assert p.max_newton > 0 and 0 < p.newton_tol < 1e-6 and p.refine_iters in (20, 40)
+    assert p.max_newton > 0 and 0 < p.newton_tol < 1e-6 and p.refine_iters in (0, 20, 40)
     assert p.subspace_rtol == 1e-4 and p.paper_eps == 1e-3
     b = ms.basis_defaults()
     assert b.prune_ratio == 1.75 and b.prune_every == 10 and b.prune_n == 5
