@@ -300,6 +300,8 @@ ms_status ms_upload_material(ms_ctx* c, const double* E, const double* nu, const
   c->h_mu.resize(T);
   c->h_lam.resize(T);
   c->h_E.assign(E, E + T);
+  c->h_nu.assign(nu, nu + T);
+  c->h_rho.assign(rho, rho + T);
   c->h_mass.assign(n, 0.0);
   for (int64_t t = 0; t < T; ++t) {
     if (!std::isfinite(E[t]) || !std::isfinite(nu[t]) || !std::isfinite(rho[t]))
@@ -492,6 +494,7 @@ ms_status ms_step(ms_ctx* c, double dt, const ms_solver_params* pin, ms_step_sta
 void ms_destroy(ms_ctx* c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
+  destroy_batch(c);
   destroy_graphs(c);
   for (auto& e : c->tev)
     if (e) (void)hipEventDestroy(e);

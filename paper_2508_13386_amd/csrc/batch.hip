@@ -1,0 +1,784 @@
+// Batched timesteps of many independent scenes in one set of launches.
+//
+// The scenes' meshes are joined into one disjoint union (a hidden context,
+// built once per list of scenes and cached), with every scene's vertex
+// range starting at a multiple of 256 (isolated, pinned, massless padding
+// vertices fill the gaps).  Then every 32-row slice, every 4-slice product
+// block and every 256-vertex update block belongs to exactly one scene, and
+// a scene's blocks cover its vertices exactly as in its own context.  All
+// kernels run once per stage over the union; what is per scene is
+// segmented:
+//   * PCG: each scene has its own recurrence state, tolerance, iteration
+//     count and done flag; the product kernel skips blocks of finished
+//     scenes, the update kernel reduces only its scene's dot partials, in
+//     the same order as the single-scene reduction;
+//   * Newton: per-scene line-search step (one energy-difference launch per
+//     backtracking round evaluates every scene at its own alpha),
+//     convergence test and exact-Hessian endgame flag (the element kernel
+//     takes its projection choice from the tet's scene).
+// With the reductions laid out this way each scene follows the arithmetic
+// of its own unbatched ms_step; finished scenes idle while the others
+// continue.  Supported: plain mode, block-Jacobi PCG, FP64 or mixed
+// precision, no half-space contact.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "cg_device.h"
+#include "energy_device.h"
+#include "ms_internal.h"
+#include "reduce.h"
+
+struct BatchPlan {
+  std::vector<ms_ctx*> scenes;
+  std::vector<int64_t> n_s, T_s;  // sizes the plan was built for
+  std::vector<int64_t> v0, t0;    // vertex / tet offsets in the union
+  std::vector<int64_t> npad;      // padded vertex count of each scene
+  ms_ctx* u = nullptr;
+  int ns = 0;
+  int64_t nub = 0, nbs = 0, ebx = 0;  // update blocks, product blocks, energy blocks per scene
+  int32_t* d_tscene = nullptr;    // [T] scene of each tet
+  int32_t* d_pbscene = nullptr;   // [nbs] scene of each product block
+  int32_t* d_ubscene = nullptr;   // [nub] scene of each update block
+  int4* d_sinfo = nullptr;        // [ns] {first product block, count, first update block, count}
+  int4* d_einfo = nullptr;        // [ns] {first tet, tets, first vertex, vertices}
+  double* d_sscal = nullptr;      // [ns][S_COUNT]
+  double* d_sst = nullptr;        // [2][ns][ST_N]
+  double* d_salpha = nullptr;     // [ns]
+  uint8_t* d_sproj = nullptr;     // [ns]
+  uint8_t* d_sactive = nullptr;   // [ns]
+  uint8_t* d_sfirst = nullptr;    // [ns]
+  double* d_spart = nullptr;      // partials of the segmented reductions
+  double* d_sout = nullptr;       // [ns][8] their results
+  int2* d_drange = nullptr;       // [ns] dot-partial range of each scene (blocks of 256 entries of 3n)
+  int2* d_erange = nullptr;       // [ns] energy-partial range of each scene
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
+  std::vector<double> h_sscal;
+};
+
+namespace ms {
+
+namespace {
+
+constexpr int kStride = S_COUNT;  // doubles of per-scene scalars
+
+inline unsigned nblk(int64_t n, int b) { return unsigned((n + b - 1) / b); }
+
+// --- PCG -------------------------------------------------------------------
+
+template <typename VT>
+__global__ void __launch_bounds__(256) k_bcg_init(int64_t n, const double* __restrict__ g,
+                                                  const uint8_t* __restrict__ pinned, double* __restrict__ p,
+                                                  double* __restrict__ s, double* __restrict__ d,
+                                                  double* __restrict__ r, double* __restrict__ u,
+                                                  const VT* __restrict__ Dinv, double* __restrict__ part) {
+  const int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  double rho[1] = {0.0};
+  if (v < n) {
+    const bool pin = pinned[v];
+    double rr[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const int64_t k = 3 * v + i;
+      const double gi = pin ? 0.0 : -g[k];
+      rr[i] = gi;
+      r[k] = gi;
+      p[k] = 0.0;
+      s[k] = 0.0;
+      d[k] = 0.0;
+      rho[0] += gi * gi;
+    }
+    double uu[3];
+    bj_apply<VT>(Dinv, v, rr, uu);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) u[3 * v + i] = uu[i];
+  }
+  block_sum<1>(rho);
+  if (threadIdx.x == 0) part[blockIdx.x] = rho[0];
+}
+
+// One block per scene: the initial residual, tolerance and flags (the
+// forcing rules of the single-scene PCG).  Inactive scenes get done = 5.
+__global__ void __launch_bounds__(256) k_bcg_init_finish(const int4* __restrict__ sinfo,
+                                                         const double* __restrict__ part,
+                                                         const uint8_t* __restrict__ active,
+                                                         const uint8_t* __restrict__ first, double eta_max,
+                                                         double eta_min, int forcing, double maxit,
+                                                         double* __restrict__ sst, double* __restrict__ sscal) {
+  const int sc = blockIdx.x;
+  const int4 in = sinfo[sc];
+  double acc[1] = {0.0};
+  for (int b = threadIdx.x; b < in.w; b += blockDim.x) acc[0] += part[in.z + b];
+  block_sum<1>(acc);
+  if (threadIdx.x != 0) return;
+  double* scal = sscal + kStride * sc;
+  double* st0 = sst + ST_N * sc;
+  const double rho0 = acc[0];
+  const bool fst = first[sc] != 0;
+  scal[S_RHO0] = rho0;
+  scal[S_RHO] = rho0;
+  if (fst) scal[S_G0SQ] = rho0;
+  double eta;
+  if (forcing == 1) {
+    if (fst || !(scal[S_GPREV] > 0.0)) {
+      eta = eta_max;
+    } else {
+      eta = 0.9 * rho0 / scal[S_GPREV];
+      const double safe = 0.9 * scal[S_ETAPREV] * scal[S_ETAPREV];
+      if (safe > 0.1) eta = fmax(eta, safe);
+    }
+  } else {
+    eta = scal[S_G0SQ] > 0.0 ? sqrt(sqrt(rho0 / scal[S_G0SQ])) : 1.0;
+  }
+  eta = fmin(eta_max, fmax(eta_min, eta));
+  if (active[sc]) {
+    scal[S_GPREV] = rho0;
+    scal[S_ETAPREV] = eta;
+  }
+  scal[S_ETA] = eta;
+  scal[S_TOL2] = eta * eta * rho0;
+  scal[S_ITER] = 0.0;
+  scal[S_MAXIT] = maxit;
+  st0[ST_GAMMA] = 0.0;
+  st0[ST_ALPHA] = 1.0;
+  st0[ST_ITER] = 0.0;
+  scal[S_DONE] = !active[sc] ? 5.0 : (rho0 > 0.0 ? 0.0 : 1.0);
+}
+
+template <typename VT, int S>
+__global__ void __launch_bounds__(256) k_bcg_spmv(int64_t n, int64_t nslices, const int32_t* __restrict__ slice_base,
+                                                  const int32_t* __restrict__ scol, const VT* __restrict__ vals,
+                                                  const double* __restrict__ u, double* __restrict__ w,
+                                                  const double* __restrict__ r, const uint8_t* __restrict__ pinned,
+                                                  const int32_t* __restrict__ pbscene,
+                                                  const double* __restrict__ sscal, double* __restrict__ part) {
+  const double done = sscal[kStride * pbscene[blockIdx.x] + S_DONE];
+  const int64_t s = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int64_t row = s * S + lane % S;
+  const bool has = s < nslices;
+  const int base = has ? slice_base[s] : 0;
+  const int width = has ? (slice_base[s + 1] - base) / S : 0;
+  if (done != 0.0) return;  // the same for every block of the scene
+  double dots[3] = {0.0, 0.0, 0.0};
+  if (has) {
+    double acc[3];
+    row_product_range<VT, double, S>(base, width, lane, scol, vals, u, acc);
+    if (lane < S && row < n) {
+      const bool pin = pinned[row];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const double wi = pin ? 0.0 : acc[i];
+        w[3 * row + i] = wi;
+        const double ui = u[3 * row + i], ri = r[3 * row + i];
+        dots[0] += ri * ui;
+        dots[1] += wi * ui;
+        dots[2] += ri * ri;
+      }
+    }
+  }
+  block_sum<3>(dots);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) part[3 * blockIdx.x + i] = dots[i];
+}
+
+template <typename VT>
+__global__ void __launch_bounds__(256) k_bcg_update(int64_t n, const int32_t* __restrict__ ubscene,
+                                                    const int4* __restrict__ sinfo, const double* __restrict__ part,
+                                                    const double* __restrict__ sst_in, double* __restrict__ sst_out,
+                                                    double* __restrict__ p, double* __restrict__ s,
+                                                    double* __restrict__ d, double* __restrict__ r,
+                                                    double* __restrict__ u, const double* __restrict__ w,
+                                                    const VT* __restrict__ Dinv, double* __restrict__ sscal) {
+  const int sc = ubscene[blockIdx.x];
+  double* scal = sscal + kStride * sc;
+  const double done = scal[S_DONE];
+  const int4 in = sinfo[sc];
+  const int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const bool own = v < n;
+  double uo[3], po[3], wo[3], so[3], ro[3], dd[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const int64_t k = own ? 3 * v + i : 0;
+    uo[i] = u[k];
+    po[i] = p[k];
+    wo[i] = w[k];
+    so[i] = s[k];
+    ro[i] = r[k];
+  }
+#pragma unroll
+  for (int q = 0; q < 9; ++q) dd[q] = double(Dinv[own ? 9 * v + q : q]);
+  if (done != 0.0) return;  // the same for every block of the scene
+  double dots[3] = {0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < in.y; b += blockDim.x)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) dots[i] += part[3 * (in.x + b) + i];
+  block_sum<3>(dots);
+  double alpha, beta;
+  const double* st_in = sst_in + ST_N * sc;
+  double* st_out = sst_out + ST_N * sc;
+  const int code = cg_scalars(st_in, scal, dots[0], dots[1], dots[2], alpha, beta);
+  if (int(blockIdx.x) == in.z && threadIdx.x == 0) {
+    scal[S_RHO] = dots[2];
+    if (code != 0) {
+      scal[S_DONE] = double(code);
+      scal[S_ITER] = st_in[ST_ITER];
+    } else {
+      st_out[ST_GAMMA] = dots[0];
+      st_out[ST_ALPHA] = alpha;
+      st_out[ST_ITER] = st_in[ST_ITER] + 1.0;
+      scal[S_ITER] = st_in[ST_ITER] + 1.0;
+    }
+  }
+  if (code != 0 || !own) return;
+  double rr[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const int64_t k = 3 * v + i;
+    const double pi = uo[i] + beta * po[i];
+    const double si = wo[i] + beta * so[i];
+    p[k] = pi;
+    s[k] = si;
+    d[k] += alpha * pi;
+    rr[i] = ro[i] - alpha * si;
+    r[k] = rr[i];
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) u[3 * v + i] = dd[3 * i] * rr[0] + dd[3 * i + 1] * rr[1] + dd[3 * i + 2] * rr[2];
+}
+
+// --- Newton-level segmented reductions -------------------------------------
+
+// Per-block partials of (a0.b0, a1.b1, |a2 - am2|^2) over blocks of 256
+// vector entries (the blocks of the single-scene dot kernel).
+__global__ void __launch_bounds__(256) k_bdots(int64_t len, const double* __restrict__ a0,
+                                               const double* __restrict__ b0, const double* __restrict__ a1,
+                                               const double* __restrict__ b1, const double* __restrict__ a2,
+                                               const double* __restrict__ am2, double* __restrict__ part) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  double v[3] = {0.0, 0.0, 0.0};
+  if (i < len) {
+    if (a0) v[0] = a0[i] * b0[i];
+    if (a1) v[1] = a1[i] * b1[i];
+    if (a2) {
+      const double z = a2[i] - (am2 ? am2[i] : 0.0);
+      v[2] = z * z;
+    }
+  }
+  block_sum<3>(v);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) part[3 * blockIdx.x + k] = v[k];
+}
+
+// One block per scene: out[8 s + k] = sum of the scene's NV-value partials
+// (first partial, count) in the order of the single-scene reduction.
+template <int NV>
+__global__ void __launch_bounds__(256) k_seg_finish(const int2* __restrict__ range, const double* __restrict__ part,
+                                                    double* __restrict__ out) {
+  const int sc = blockIdx.x;
+  const int2 rg = range[sc];
+  double acc[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+  for (int b = threadIdx.x; b < rg.y; b += blockDim.x)
+#pragma unroll
+    for (int k = 0; k < NV; ++k) acc[k] += part[NV * (rg.x + b) + k];
+  block_sum<NV>(acc);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < NV; ++k) out[8 * sc + k] = acc[k];
+}
+
+// Energy difference at each scene's own step alpha_s; grid (blocks per
+// scene, scenes): thread j of a scene takes its tet j and its vertex j, as
+// thread j of the single-scene kernel does.
+__global__ void __launch_bounds__(256) k_benergy_delta(const int4* __restrict__ einfo,
+                                                       const int32_t* __restrict__ tets,
+                                                       const double* __restrict__ Dminv,
+                                                       const double* __restrict__ vol, const double* __restrict__ mu_,
+                                                       const double* __restrict__ lam_,
+                                                       const double* __restrict__ mass, const double* __restrict__ x,
+                                                       const double* __restrict__ d,
+                                                       const double* __restrict__ salpha,
+                                                       const double* __restrict__ xtilde, double h2, double gx,
+                                                       double gy, double gz, HalfSpace hs, double* __restrict__ part) {
+  const int sc = blockIdx.y;
+  const int4 in = einfo[sc];
+  const double alpha = salpha[sc];
+  const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  double e[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (alpha != 0.0) {
+    if (j < in.y) tet_energy_delta(in.x + j, tets, Dminv, vol, mu_, lam_, x, d, alpha, h2, e);
+    if (j < in.w) vertex_energy_delta(in.z + j, mass, x, d, alpha, xtilde, h2, gx, gy, gz, hs, e);
+  }
+  block_sum<5>(e);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < 5; ++k) part[5 * (int64_t(sc) * gridDim.x + blockIdx.x) + k] = e[k];
+}
+
+// x += alpha_s d with s the scene of the vertex (256-vertex blocks are
+// single-scene).
+__global__ void k_baxpy(int64_t n, const int32_t* __restrict__ ubscene, const double* __restrict__ salpha,
+                        const double* __restrict__ d, double* __restrict__ x) {
+  const int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const double a = salpha[ubscene[v / 256]];
+  if (a == 0.0) return;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) x[3 * v + i] += a * d[3 * v + i];
+}
+
+}  // namespace
+
+void destroy_batch(ms_ctx* c) {
+  if (!c || !c->batch) return;
+  BatchPlan* B = c->batch;
+  for (auto& g : B->graph)
+    if (g) (void)hipGraphExecDestroy(g);
+  if (B->u) ms_destroy(B->u);
+  delete B;
+  c->batch = nullptr;
+}
+
+namespace {
+
+ms_status build_plan(ms_ctx* const* scenes, int ns, BatchPlan*& out) {
+  ms_ctx* c0 = scenes[0];
+  auto* B = new BatchPlan();
+  B->ns = ns;
+  B->scenes.assign(scenes, scenes + ns);
+  int64_t nv = 0, nt = 0;
+  for (int s = 0; s < ns; ++s) {
+    ms_ctx* c = scenes[s];
+    B->n_s.push_back(c->n);
+    B->T_s.push_back(c->T);
+    B->v0.push_back(nv);
+    B->t0.push_back(nt);
+    const int64_t pad = ((c->n + 255) / 256) * 256;
+    B->npad.push_back(pad);
+    nv += pad;
+    nt += c->T;
+  }
+  std::vector<double> rest(3 * nv, 0.0), E, nu, rho;
+  std::vector<int32_t> tets;
+  tets.reserve(4 * nt);
+  for (int s = 0; s < ns; ++s) {
+    ms_ctx* c = scenes[s];
+    std::copy(c->h_rest.begin(), c->h_rest.end(), rest.begin() + 3 * B->v0[s]);
+    for (int64_t q = 0; q < 4 * c->T; ++q) tets.push_back(int32_t(c->h_tets[q] + B->v0[s]));
+    E.insert(E.end(), c->h_E.begin(), c->h_E.end());
+    nu.insert(nu.end(), c->h_nu.begin(), c->h_nu.end());
+    rho.insert(rho.end(), c->h_rho.begin(), c->h_rho.end());
+  }
+  ms_device dev = c0->dev;
+  dev.hip_stream = c0->stream;
+  ms_ctx* u = nullptr;
+  ms_status st;
+  if ((st = ms_create(&dev, &u))) {
+    delete B;
+    return fail(c0, st, "batch: context creation failed");
+  }
+  B->u = u;
+  ms_ctx* const c = u;  // error reports of the HIP calls below
+  if ((st = ms_upload_mesh(u, nv, rest.data(), nt, tets.data())) ||
+      (st = ms_upload_material(u, E.data(), nu.data(), rho.data())) || (st = ms_set_gravity(u, c0->gravity))) {
+    const std::string msg = "batch: union mesh: " + u->err;
+    ms_destroy(u);
+    delete B;
+    return fail(c0, st, msg);
+  }
+  if (u->pat.S != c0->pat.S) {
+    ms_destroy(u);
+    delete B;
+    return fail(c0, MS_E_ARG, "batch: scenes use another slice height than the union");
+  }
+  // segment maps
+  const int64_t nbs = (u->pat.nslices + 3) / 4, nub = (nv + 255) / 256;
+  B->nbs = nbs;
+  B->nub = nub;
+  std::vector<int32_t> tscene(nt), pbscene(nbs), ubscene(nub);
+  std::vector<int4> sinfo(ns), einfo(ns);
+  int64_t emax = 1;
+  for (int s = 0; s < ns; ++s) {
+    for (int64_t t = 0; t < B->T_s[s]; ++t) tscene[B->t0[s] + t] = s;
+    const int64_t pb0 = B->v0[s] / 128, pbn = B->npad[s] / 128, ub0 = B->v0[s] / 256, ubn = B->npad[s] / 256;
+    for (int64_t b = 0; b < pbn; ++b) pbscene[pb0 + b] = s;
+    for (int64_t b = 0; b < ubn; ++b) ubscene[ub0 + b] = s;
+    sinfo[s] = make_int4(int(pb0), int(pbn), int(ub0), int(ubn));
+    einfo[s] = make_int4(int(B->t0[s]), int(B->T_s[s]), int(B->v0[s]), int(B->n_s[s]));
+    emax = std::max<int64_t>(emax, (std::max(B->T_s[s], B->n_s[s]) + 255) / 256);
+  }
+  for (int64_t b = 0; b < nbs; ++b)  // product blocks past the last scene (none with aligned ranges)
+    if (b * 128 >= nv) pbscene[b] = ns - 1;
+  B->ebx = emax;
+  const int64_t npart = std::max<int64_t>({3 * nbs, nub, 3 * ((3 * nv + 255) / 256), 5 * emax * ns});
+  std::vector<int2> drange(ns), erange(ns);
+  for (int s = 0; s < ns; ++s) {
+    drange[s] = make_int2(int(3 * B->v0[s] / 256), int(3 * B->npad[s] / 256));
+    erange[s] = make_int2(int(s * emax), int(emax));
+  }
+  if ((st = upload(u, &B->d_tscene, tscene.data(), tscene.size())) ||
+      (st = upload(u, &B->d_pbscene, pbscene.data(), pbscene.size())) ||
+      (st = upload(u, &B->d_ubscene, ubscene.data(), ubscene.size())) ||
+      (st = upload(u, &B->d_sinfo, sinfo.data(), sinfo.size())) ||
+      (st = upload(u, &B->d_einfo, einfo.data(), einfo.size())) ||
+      (st = upload(u, &B->d_drange, drange.data(), drange.size())) ||
+      (st = upload(u, &B->d_erange, erange.data(), erange.size())) ||
+      (st = alloc_n(u, &B->d_sscal, size_t(kStride) * ns)) || (st = alloc_n(u, &B->d_sst, size_t(2 * ST_N) * ns)) ||
+      (st = alloc_n(u, &B->d_salpha, size_t(ns))) || (st = alloc_n(u, &B->d_sproj, size_t(ns))) ||
+      (st = alloc_n(u, &B->d_sactive, size_t(ns))) || (st = alloc_n(u, &B->d_sfirst, size_t(ns))) ||
+      (st = alloc_n(u, &B->d_spart, size_t(npart))) || (st = alloc_n(u, &B->d_sout, size_t(8) * ns))) {
+    const std::string msg = "batch: allocation: " + u->err;
+    ms_destroy(u);
+    delete B;
+    return fail(c0, st, msg);
+  }
+  MS_HIP(hipMemsetAsync(B->d_sscal, 0, sizeof(double) * kStride * ns, u->stream));
+  // padding vertices rest at the origin, at rest, massless and pinned there
+  MS_HIP(hipMemsetAsync(u->d_x, 0, sizeof(double) * 3 * u->n, u->stream));
+  MS_HIP(hipMemsetAsync(u->d_v, 0, sizeof(double) * 3 * u->n, u->stream));
+  B->h_sscal.assign(size_t(kStride) * ns, 0.0);
+  out = B;
+  return MS_OK;
+}
+
+// Segmented dots: (a0.b0, a1.b1, |a2 - am2|^2) per scene into h[8 s + k].
+ms_status bdots(BatchPlan* B, const double* a0, const double* b0, const double* a1, const double* b1,
+                const double* a2, const double* am2, std::vector<double>& h) {
+  ms_ctx* u = B->u;
+  ms_ctx* const c = u;
+  const int64_t len = 3 * u->n;
+  k_bdots<<<nblk(len, 256), 256, 0, u->stream>>>(len, a0, b0, a1, b1, a2, am2, B->d_spart);
+  k_seg_finish<3><<<unsigned(B->ns), 256, 0, u->stream>>>(B->d_drange, B->d_spart, B->d_sout);
+  h.resize(size_t(8) * B->ns);
+  MS_HIP(hipMemcpyAsync(h.data(), B->d_sout, sizeof(double) * 8 * B->ns, hipMemcpyDeviceToHost, u->stream));
+  return sync(u);
+}
+
+// Per-scene energy differences at the scene steps in d_salpha: h[8 s + k],
+// k = 0..3 the parts, 4 the magnitude.
+ms_status benergy(BatchPlan* B, const double* d, double h2, std::vector<double>& h) {
+  ms_ctx* u = B->u;
+  ms_ctx* const c = u;
+  dim3 grid(unsigned(B->ebx), unsigned(B->ns));
+  k_benergy_delta<<<grid, 256, 0, u->stream>>>(B->d_einfo, u->d_tets, u->d_Dminv, u->d_vol, u->d_mu, u->d_lam,
+                                               u->d_mass, u->d_x, d, B->d_salpha, u->d_xtilde, h2, u->gravity[0],
+                                               u->gravity[1], u->gravity[2], hs_of(u), B->d_spart);
+  k_seg_finish<5><<<unsigned(B->ns), 256, 0, u->stream>>>(B->d_erange, B->d_spart, B->d_sout);
+  h.resize(size_t(8) * B->ns);
+  MS_HIP(hipMemcpyAsync(h.data(), B->d_sout, sizeof(double) * 8 * B->ns, hipMemcpyDeviceToHost, u->stream));
+  return sync(u);
+}
+
+void bcg_iteration(BatchPlan* B, int prec, int parity) {
+  ms_ctx* u = B->u;
+  const int64_t ns = u->pat.nslices;
+  const double* st_in = B->d_sst + ST_N * B->ns * parity;
+  double* st_out = B->d_sst + ST_N * B->ns * (1 - parity);
+  with_slice(u->pat.S, [&](auto SS) {
+    constexpr int S = decltype(SS)::value;
+    if (prec == MS_PREC_FP64)
+      k_bcg_spmv<double, S><<<unsigned(B->nbs), 256, 0, u->stream>>>(u->n, ns, u->pat.d_slice_base, u->pat.d_col,
+                                                                     u->d_vals, u->d_u, u->d_w, u->d_r, u->d_pinned,
+                                                                     B->d_pbscene, B->d_sscal, u->d_part);
+    else
+      k_bcg_spmv<float, S><<<unsigned(B->nbs), 256, 0, u->stream>>>(u->n, ns, u->pat.d_slice_base, u->pat.d_col,
+                                                                    u->d_vals32, u->d_u, u->d_w, u->d_r, u->d_pinned,
+                                                                    B->d_pbscene, B->d_sscal, u->d_part);
+  });
+  if (prec == MS_PREC_FP64)
+    k_bcg_update<double><<<unsigned(B->nub), 256, 0, u->stream>>>(u->n, B->d_ubscene, B->d_sinfo, u->d_part, st_in,
+                                                                  st_out, u->d_p, u->d_s, u->d_d, u->d_r, u->d_u,
+                                                                  u->d_w, u->d_Dinv, B->d_sscal);
+  else
+    k_bcg_update<float><<<unsigned(B->nub), 256, 0, u->stream>>>(u->n, B->d_ubscene, B->d_sinfo, u->d_part, st_in,
+                                                                 st_out, u->d_p, u->d_s, u->d_d, u->d_r, u->d_u,
+                                                                 u->d_w, u->d_Dinv32, B->d_sscal);
+}
+
+// PCG on every active scene at once; on return h_sscal holds each scene's
+// scalars (S_ITER, S_DONE: 1 converged, 2 iteration cap, 3 loss of positive
+// definiteness, 5 inactive).
+ms_status bpcg(BatchPlan* B, int prec, const ms_solver_params& P, const std::vector<uint8_t>& active,
+               const std::vector<uint8_t>& first) {
+  ms_ctx* u = B->u;
+  ms_ctx* const c = u;
+  MS_HIP(hipMemcpyAsync(B->d_sactive, active.data(), active.size(), hipMemcpyHostToDevice, u->stream));
+  MS_HIP(hipMemcpyAsync(B->d_sfirst, first.data(), first.size(), hipMemcpyHostToDevice, u->stream));
+  if (prec == MS_PREC_FP64)
+    k_bcg_init<double><<<unsigned(B->nub), 256, 0, u->stream>>>(u->n, u->d_g, u->d_pinned, u->d_p, u->d_s, u->d_d,
+                                                                u->d_r, u->d_u, u->d_Dinv, B->d_spart);
+  else
+    k_bcg_init<float><<<unsigned(B->nub), 256, 0, u->stream>>>(u->n, u->d_g, u->d_pinned, u->d_p, u->d_s, u->d_d,
+                                                               u->d_r, u->d_u, u->d_Dinv32, B->d_spart);
+  k_bcg_init_finish<<<unsigned(B->ns), 256, 0, u->stream>>>(B->d_sinfo, B->d_spart, B->d_sactive, B->d_sfirst,
+                                                            P.pcg_eta_max, P.pcg_eta_min, P.forcing,
+                                                            double(P.max_pcg), B->d_sst, B->d_sscal);
+  const int chunk = u->cg_chunk;
+  hipGraphExec_t& ge = B->graph[prec == MS_PREC_FP64 ? 0 : 1];
+  if (!ge && u->use_graphs) {
+    hipGraph_t g;
+    MS_HIP(hipStreamBeginCapture(u->stream, hipStreamCaptureModeThreadLocal));
+    for (int i = 0; i < chunk; ++i) bcg_iteration(B, prec, i & 1);
+    MS_HIP(hipStreamEndCapture(u->stream, &g));
+    MS_HIP(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+    (void)hipGraphDestroy(g);
+  }
+  int launched = 0;
+  while (true) {
+    if (u->use_graphs) {
+      MS_HIP(hipGraphLaunch(ge, u->stream));
+    } else {
+      for (int i = 0; i < chunk; ++i) bcg_iteration(B, prec, i & 1);
+    }
+    launched += chunk;
+    MS_HIP(hipMemcpyAsync(B->h_sscal.data(), B->d_sscal, sizeof(double) * B->h_sscal.size(), hipMemcpyDeviceToHost,
+                          u->stream));
+    ms_status s = sync(u);
+    if (s) return s;
+    bool all = true;
+    for (int q = 0; q < B->ns; ++q) all = all && B->h_sscal[size_t(kStride) * q + S_DONE] != 0.0;
+    if (all) break;
+    if (launched > P.max_pcg + 2 * chunk) return fail(u, MS_E_DEVICE, "batched PCG flags never set");
+  }
+  return MS_OK;
+}
+
+ms_status batch_step(BatchPlan* B, double dt, const ms_solver_params& P, ms_step_stats* out) {
+  ms_ctx* u = B->u;
+  ms_ctx* const c = u;
+  const int ns = B->ns;
+  const double h2 = dt * dt;
+  const int prec = P.precision == MS_PREC_MIXED ? MS_PREC_MIXED : MS_PREC_FP64;
+  const int64_t n3 = 3 * u->n;
+  std::vector<ms_step_stats> S(ns);
+  for (auto& st : S) st.min_alpha = 1.0;
+  std::vector<uint8_t> active(ns, 1), first(ns, 1), proj(ns, 1), endgame(ns, 0), done(ns, 0);
+  std::vector<double> alpha(ns, 0.0), h, he;
+  ms_status s = MS_OK;
+  u->timing = false;
+  launch_predict(u, dt);
+  launch_apply_dbc(u, int64_t(u->h_dbc.size()));
+  if (P.predictor == 1) {  // inertial start, kept per scene where it lowers E
+    launch_predictor_dir(u);
+    std::fill(alpha.begin(), alpha.end(), 1.0);
+    MS_HIP(hipMemcpyAsync(B->d_salpha, alpha.data(), sizeof(double) * ns, hipMemcpyHostToDevice, u->stream));
+    if ((s = benergy(B, u->d_d, h2, he))) return s;
+    for (int q = 0; q < ns; ++q) {
+      double dE = he[8 * q] + he[8 * q + 1] + he[8 * q + 2] + he[8 * q + 3];
+      alpha[q] = (std::isfinite(dE) && dE < 0.0) ? 1.0 : 0.0;
+    }
+    MS_HIP(hipMemcpyAsync(B->d_salpha, alpha.data(), sizeof(double) * ns, hipMemcpyHostToDevice, u->stream));
+    k_baxpy<<<nblk(u->n, 256), 256, 0, u->stream>>>(u->n, B->d_ubscene, B->d_salpha, u->d_d, u->d_x);
+  }
+  std::vector<double> dnorm(ns, 0.0), disp(ns, 0.0);
+  for (int it = 0; it < P.max_newton; ++it) {
+    bool any = false;
+    for (int q = 0; q < ns; ++q) any = any || active[q];
+    if (!any) break;
+    for (int q = 0; q < ns; ++q) proj[q] = !(P.exact_endgame && endgame[q]);
+    MS_HIP(hipMemcpyAsync(B->d_sproj, proj.data(), ns, hipMemcpyHostToDevice, u->stream));
+    launch_element(u, u->d_x, h2, prec, true, true, B->d_tscene, B->d_sproj);
+    launch_gather_grad(u, u->d_x, h2, u->d_g);
+    launch_gather_hess(u, u->d_x, h2, prec);
+    launch_block_jacobi(u, prec);
+    u->assembled[prec == MS_PREC_FP64 ? 0 : 1] = true;
+    if ((s = bpcg(B, prec, P, active, first))) break;
+    std::vector<uint8_t> step(ns, 0);
+    for (int q = 0; q < ns; ++q) {
+      if (!active[q]) continue;
+      const double* sc = &B->h_sscal[size_t(kStride) * q];
+      const int its = int(sc[S_ITER]), code = int(sc[S_DONE]);
+      first[q] = 0;
+      S[q].pcg_iters += its;
+      S[q].max_pcg_iters = std::max(S[q].max_pcg_iters, its);
+      if (!std::isfinite(sc[S_RHO0])) {
+        s = fail(u, MS_E_NONFINITE, "non-finite gradient in scene " + std::to_string(q));
+        break;
+      }
+      if (code == 3 && !proj[q]) {
+        endgame[q] = 0;  // indefinite exact Hessian: this scene redoes the iteration projected
+        continue;
+      }
+      step[q] = 1;
+    }
+    if (s) break;
+    if ((s = bdots(B, u->d_g, u->d_d, u->d_d, u->d_d, nullptr, nullptr, h))) break;
+    std::vector<double> gd(ns, 0.0);
+    for (int q = 0; q < ns; ++q) {
+      if (!step[q]) continue;
+      gd[q] = h[8 * q];
+      dnorm[q] = std::sqrt(h[8 * q + 1]);
+      if (!std::isfinite(gd[q]) || !std::isfinite(dnorm[q])) {
+        s = fail(u, MS_E_NONFINITE, "non-finite step in scene " + std::to_string(q));
+        break;
+      }
+      if (dnorm[q] == 0.0) {
+        step[q] = 0;
+        active[q] = 0;
+        done[q] = 1;
+        S[q].newton_iters = it;
+        continue;
+      }
+      if (!(gd[q] < 0.0)) {
+        step[q] = 0;
+        if (!proj[q]) {
+          endgame[q] = 0;
+          continue;
+        }
+        s = fail(u, MS_E_LINESEARCH, "search direction is not a descent direction in scene " + std::to_string(q));
+        break;
+      }
+    }
+    if (s) break;
+    // line search, every stepping scene at its own alpha
+    std::vector<uint8_t> searching(step);
+    std::vector<int> nbt(ns, 0);
+    for (int q = 0; q < ns; ++q) alpha[q] = step[q] ? 1.0 : 0.0;
+    while (true) {
+      bool any_search = false;
+      for (int q = 0; q < ns; ++q) any_search = any_search || searching[q];
+      if (!any_search) break;
+      std::vector<double> trial(ns, 0.0);
+      for (int q = 0; q < ns; ++q) trial[q] = searching[q] ? alpha[q] : 0.0;
+      MS_HIP(hipMemcpyAsync(B->d_salpha, trial.data(), sizeof(double) * ns, hipMemcpyHostToDevice, u->stream));
+      if ((s = benergy(B, u->d_d, h2, he))) break;
+      for (int q = 0; q < ns; ++q) {
+        if (!searching[q]) continue;
+        const double dE = he[8 * q] + he[8 * q + 1] + he[8 * q + 2] + he[8 * q + 3], err = he[8 * q + 4];
+        if (std::isfinite(dE) && dE <= 1e-4 * alpha[q] * gd[q] + 1e-14 * err) {
+          searching[q] = 0;
+        } else {
+          alpha[q] *= 0.5;
+          if (++nbt[q] > P.max_backtracks) {
+            s = fail(u, MS_E_LINESEARCH, "no energy decrease in scene " + std::to_string(q));
+            break;
+          }
+        }
+      }
+      if (s) break;
+    }
+    if (s) break;
+    MS_HIP(hipMemcpyAsync(B->d_salpha, alpha.data(), sizeof(double) * ns, hipMemcpyHostToDevice, u->stream));
+    k_baxpy<<<nblk(u->n, 256), 256, 0, u->stream>>>(u->n, B->d_ubscene, B->d_salpha, u->d_d, u->d_x);
+    if ((s = bdots(B, nullptr, nullptr, nullptr, nullptr, u->d_x, u->d_xt, h))) break;
+    for (int q = 0; q < ns; ++q) {
+      if (!step[q]) continue;
+      S[q].backtracks += nbt[q];
+      S[q].min_alpha = std::min(S[q].min_alpha, alpha[q]);
+      disp[q] = std::sqrt(h[8 * q + 2]);
+      const double ref = std::max(disp[q], P.abs_floor);
+      if (alpha[q] == 1.0 && dnorm[q] <= P.newton_tol * ref) {
+        active[q] = 0;
+        done[q] = 1;
+        S[q].newton_iters = it + 1;
+      } else if (dnorm[q] <= P.endgame_ratio * ref) {
+        endgame[q] = 1;
+      }
+    }
+  }
+  bool all_done = !s;
+  for (int q = 0; q < ns && all_done; ++q) all_done = done[q] != 0;
+  if (!s && !all_done) s = fail(u, MS_E_NOCONV, "Newton did not converge in every scene");
+  if (s) {
+    (void)hipMemcpyAsync(u->d_x, u->d_xt, n3 * sizeof(double), hipMemcpyDeviceToDevice, u->stream);
+    (void)hipStreamSynchronize(u->stream);
+    return s;
+  }
+  launch_velocity(u, 1.0 / dt);
+  if ((s = bdots(B, nullptr, nullptr, nullptr, nullptr, u->d_x, u->d_xt, h))) return s;
+  for (int q = 0; q < ns; ++q) {
+    S[q].last_dnorm = dnorm[q];
+    S[q].disp_norm = std::sqrt(h[8 * q + 2]);
+  }
+  if (out)
+    for (int q = 0; q < ns; ++q) out[q] = S[q];
+  return MS_OK;
+}
+
+}  // namespace
+
+}  // namespace ms
+
+using namespace ms;
+
+extern "C" ms_status ms_batch_step(ms_ctx* const* scenes, int32_t n_scenes, double dt, const ms_solver_params* pin,
+                                   ms_step_stats* per_scene) {
+  if (!scenes || n_scenes < 1) return MS_E_ARG;
+  for (int q = 0; q < n_scenes; ++q)
+    if (!scenes[q]) return MS_E_ARG;
+  ms_ctx* c0 = scenes[0];
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(c0, MS_E_ARG, "dt must be positive");
+  ms_solver_params P;
+  if (pin)
+    P = *pin;
+  else
+    ms_solver_defaults(&P);
+  if (P.mode != MS_MODE_PLAIN || P.preconditioner != MS_PC_BLOCK_JACOBI || P.warm_start)
+    return fail(c0, MS_E_ARG, "batched steps support plain mode with block-Jacobi PCG");
+  for (int q = 0; q < n_scenes; ++q) {
+    ms_ctx* sc = scenes[q];
+    if (sc->stage < 3) return fail(c0, MS_E_ORDER, "scene " + std::to_string(q) + " has no state");
+    if (sc->has_hs) return fail(c0, MS_E_ARG, "batched steps do not support half-space contact");
+    if (sc->dev.device != c0->dev.device) return fail(c0, MS_E_ARG, "scenes on different devices");
+    for (int i = 0; i < 3; ++i)
+      if (sc->gravity[i] != c0->gravity[i]) return fail(c0, MS_E_ARG, "scenes with different gravity");
+    for (int r = 0; r < q; ++r)
+      if (scenes[r] == sc) return fail(c0, MS_E_ARG, "a scene appears twice");
+  }
+  // reuse the cached union when the scene list is unchanged
+  BatchPlan* B = c0->batch;
+  bool same = B && B->ns == n_scenes;
+  for (int q = 0; same && q < n_scenes; ++q)
+    same = B->scenes[q] == scenes[q] && B->n_s[q] == scenes[q]->n && B->T_s[q] == scenes[q]->T;
+  if (!same) {
+    destroy_batch(c0);
+    BatchPlan* nb = nullptr;
+    ms_status s = build_plan(scenes, n_scenes, nb);
+    if (s) return s;
+    c0->batch = B = nb;
+  }
+  ms_ctx* u = B->u;
+  ms_ctx* const c = u;
+  // Dirichlet vertices of every scene plus the padding vertices, pinned
+  std::vector<int32_t> dv;
+  std::vector<double> dt3;
+  for (int q = 0; q < n_scenes; ++q) {
+    ms_ctx* sc = scenes[q];
+    for (size_t k = 0; k < sc->h_dbc.size(); ++k) {
+      dv.push_back(int32_t(sc->h_dbc[k] + B->v0[q]));
+      for (int i = 0; i < 3; ++i) dt3.push_back(sc->h_dbc_tgt[3 * k + i]);
+    }
+    for (int64_t v = sc->n; v < B->npad[q]; ++v) {
+      dv.push_back(int32_t(B->v0[q] + v));
+      for (int i = 0; i < 3; ++i) dt3.push_back(0.0);
+    }
+  }
+  ms_status s = ms_set_dirichlet(u, int64_t(dv.size()), dv.data(), dt3.data());
+  if (s) return fail(c0, s, "batch: " + u->err);
+  // states in
+  for (int q = 0; q < n_scenes; ++q) {
+    ms_ctx* sc = scenes[q];
+    if (sc->stream != u->stream) MS_HIP(hipStreamSynchronize(sc->stream));
+    MS_HIP(hipMemcpyAsync(u->d_x + 3 * B->v0[q], sc->d_x, 3 * sc->n * sizeof(double), hipMemcpyDeviceToDevice,
+                          u->stream));
+    MS_HIP(hipMemcpyAsync(u->d_v + 3 * B->v0[q], sc->d_v, 3 * sc->n * sizeof(double), hipMemcpyDeviceToDevice,
+                          u->stream));
+  }
+  u->stage = 3;
+  s = batch_step(B, dt, P, per_scene);
+  if (s) return fail(c0, s, "batch: " + u->err);
+  for (int q = 0; q < n_scenes; ++q) {
+    ms_ctx* sc = scenes[q];
+    MS_HIP(hipMemcpyAsync(sc->d_x, u->d_x + 3 * B->v0[q], 3 * sc->n * sizeof(double), hipMemcpyDeviceToDevice,
+                          u->stream));
+    MS_HIP(hipMemcpyAsync(sc->d_v, u->d_v + 3 * B->v0[q], 3 * sc->n * sizeof(double), hipMemcpyDeviceToDevice,
+                          u->stream));
+  }
+  return sync(u);
+}
+

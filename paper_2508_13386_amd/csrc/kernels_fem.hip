@@ -17,6 +17,7 @@
 #include <cfloat>
 
 #include "contact.h"
+#include "energy_device.h"
 #include "ms_internal.h"
 #include "reduce.h"
 
@@ -111,7 +112,9 @@ __global__ void __launch_bounds__(64) k_element(int64_t T, const int32_t* __rest
                                                 const double* __restrict__ Dminv, const double* __restrict__ vol,
                                                 const double* __restrict__ mu_, const double* __restrict__ lam_,
                                                 const double* __restrict__ x, double* __restrict__ ge,
-                                                HT* __restrict__ He, int project) {
+                                                HT* __restrict__ He, int project,
+                                                const int32_t* __restrict__ tscene,
+                                                const uint8_t* __restrict__ sproj) {
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= T) return;
   int vi[4];
@@ -169,7 +172,8 @@ __global__ void __launch_bounds__(64) k_element(int64_t T, const int32_t* __rest
   if (!HESS) return;
   double A[45];
   snh_hessian(F, cof, J, mu, lam, A);
-  if (project) {
+  // per-scene choice in a batch: scene of the tet, then that scene's flag
+  if (tscene ? sproj[tscene[t]] != 0 : project != 0) {
     double Q[9][9];
     jacobi9(A, Q);
     double lp[9];
@@ -382,74 +386,8 @@ __global__ void __launch_bounds__(256) k_energy_delta(int64_t T, int64_t n, cons
                                                       unsigned* __restrict__ counter, double* __restrict__ out) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   double e[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  if (i < T) {
-    double F[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, D[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-    double b0[3];
-#pragma unroll
-    for (int j = 0; j < 3; ++j) b0[j] = -(Dminv[9 * i + j] + Dminv[9 * i + 3 + j] + Dminv[9 * i + 6 + j]);
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      const int64_t v = tets[4 * i + a];
-#pragma unroll
-      for (int r = 0; r < 3; ++r) {
-        const double y = x[3 * v + r], dy = alpha * d[3 * v + r];
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-          const double bj = a == 0 ? b0[j] : Dminv[9 * i + 3 * (a - 1) + j];
-          F[r][j] += y * bj;
-          D[r][j] += dy * bj;
-        }
-      }
-    }
-    double cF[3][3], cD[3][3];
-#pragma unroll
-    for (int r = 0; r < 3; ++r)
-#pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        const int r1 = (r + 1) % 3, r2 = (r + 2) % 3, j1 = (j + 1) % 3, j2 = (j + 2) % 3;
-        cF[r][j] = F[r1][j1] * F[r2][j2] - F[r1][j2] * F[r2][j1];
-        cD[r][j] = D[r1][j1] * D[r2][j2] - D[r1][j2] * D[r2][j1];
-      }
-    double FD = 0.0, DD = 0.0, cFD = 0.0, FcD = 0.0;
-#pragma unroll
-    for (int r = 0; r < 3; ++r)
-#pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        FD += F[r][j] * D[r][j];
-        DD += D[r][j] * D[r][j];
-        cFD += cF[r][j] * D[r][j];
-        FcD += F[r][j] * cD[r][j];
-      }
-    const double J = F[0][0] * cF[0][0] + F[0][1] * cF[0][1] + F[0][2] * cF[0][2];
-    const double detD = D[0][0] * cD[0][0] + D[0][1] * cD[0][1] + D[0][2] * cD[0][2];
-    const double dIc = 2.0 * FD + DD;
-    const double dJ = cFD + FcD + detD;
-    const double mu = mu_[i], lam = lam_[i];
-    e[1] = h2 * vol[i] * (0.5 * mu * dIc - mu * dJ + 0.5 * lam * dJ * (dJ + 2.0 * (J - 1.0)));
-    e[4] = h2 * vol[i] * (0.5 * mu * (2.0 * fabs(FD) + DD) + mu * fabs(dJ) + 0.5 * lam * fabs(dJ) * (fabs(dJ) + 2.0 * fabs(J - 1.0)));
-  }
-  if (i < n) {
-    const double m = mass[i];
-    double dv[3], dot_xd = 0.0, dd = 0.0;
-#pragma unroll
-    for (int r = 0; r < 3; ++r) {
-      dv[r] = alpha * d[3 * i + r];
-      dot_xd += dv[r] * (x[3 * i + r] - xtilde[3 * i + r]);
-      dd += dv[r] * dv[r];
-    }
-    e[0] = m * (dot_xd + 0.5 * dd);
-    e[2] = -h2 * m * (gx * dv[0] + gy * dv[1] + gz * dv[2]);
-    e[4] += m * (fabs(dot_xd) + 0.5 * dd) + fabs(e[2]);
-    if (hs.on) {
-      double b, b1, b2, bn, bn1, bn2;
-      const double dist = hs.n[0] * x[3 * i] + hs.n[1] * x[3 * i + 1] + hs.n[2] * x[3 * i + 2] - hs.off;
-      const double ddist = hs.n[0] * dv[0] + hs.n[1] * dv[1] + hs.n[2] * dv[2];
-      barrier_terms(dist, hs.dhat, b, b1, b2);
-      barrier_terms(dist + ddist, hs.dhat, bn, bn1, bn2);
-      e[3] = h2 * hs.kappa * (bn - b);
-      e[4] += h2 * hs.kappa * (fabs(bn) + fabs(b));
-    }
-  }
+  if (i < T) tet_energy_delta(i, tets, Dminv, vol, mu_, lam_, x, d, alpha, h2, e);
+  if (i < n) vertex_energy_delta(i, mass, x, d, alpha, xtilde, h2, gx, gy, gz, hs, e);
   if (grid_sum<5>(e, part, counter) && threadIdx.x == 0)
 #pragma unroll
     for (int k = 0; k < 5; ++k) out[k] = e[k];
@@ -544,17 +482,18 @@ void launch_predictor_dir(ms_ctx* c) {
 void launch_velocity(ms_ctx* c, double inv_h) {
   k_velocity<<<nblocks(3 * c->n, 256), 256, 0, c->stream>>>(3 * c->n, c->d_x, c->d_xt, inv_h, c->d_v);
 }
-void launch_element(ms_ctx* c, const double* x, double /*h2*/, int prec, bool hess, bool project) {
+void launch_element(ms_ctx* c, const double* x, double /*h2*/, int prec, bool hess, bool project,
+                    const int32_t* tscene, const uint8_t* sproj) {
   const unsigned nb = nblocks(c->T, 64);
   if (!hess)
     k_element<false, double><<<nb, 64, 0, c->stream>>>(c->T, c->d_tets, c->d_Dminv, c->d_vol, c->d_mu, c->d_lam, x,
-                                                      c->d_ge, c->d_He, project);
+                                                      c->d_ge, c->d_He, project, tscene, sproj);
   else if (prec == MS_PREC_FP64)
     k_element<true, double><<<nb, 64, 0, c->stream>>>(c->T, c->d_tets, c->d_Dminv, c->d_vol, c->d_mu, c->d_lam, x,
-                                                     c->d_ge, c->d_He, project);
+                                                     c->d_ge, c->d_He, project, tscene, sproj);
   else
     k_element<true, float><<<nb, 64, 0, c->stream>>>(c->T, c->d_tets, c->d_Dminv, c->d_vol, c->d_mu, c->d_lam, x,
-                                                    c->d_ge, c->d_He32, project);
+                                                    c->d_ge, c->d_He32, project, tscene, sproj);
 }
 void launch_gather_grad(ms_ctx* c, const double* x, double h2, double* g) {
   k_gather_grad<<<nblocks(c->n, 64), 64, 0, c->stream>>>(c->n, c->d_vt_ptr, c->d_vt_code, c->d_ge, c->d_mass, x,

@@ -101,6 +101,7 @@ struct ms_ctx {
   std::vector<double> h_rest;
   std::vector<int32_t> h_tets;
   std::vector<double> h_vol, h_mu, h_lam, h_mass, h_Dminv;
+  std::vector<double> h_nu, h_rho;  // material as uploaded (batches rebuild from it)
   std::vector<double> h_E;
   double bbox_diag = 1.0;
   // device mesh
@@ -183,6 +184,7 @@ struct ms_ctx {
   int eval_prec = 0;
   bool eval_valid = false;
   bool assembled[2] = {false, false};  // a Hessian of that precision is in place
+  struct BatchPlan* batch = nullptr;  // cached union of the last ms_batch_step's scenes (owned)
   // paper mode (Alg. 1 and 2)
   void* d_lag = nullptr;       // lagged elastic + inertia part of H, [slots][9] in the mode's value type
   void* d_hlag = nullptr;      // H_lag = lag + barrier curvature at the current x
@@ -261,7 +263,8 @@ enum Scal {  // indices into ctx->d_scal
 
 void launch_predict(ms_ctx* c, double dt);
 void launch_apply_dbc(ms_ctx* c, int64_t nd);
-void launch_element(ms_ctx* c, const double* x, double h2, int prec, bool hess, bool project);
+void launch_element(ms_ctx* c, const double* x, double h2, int prec, bool hess, bool project,
+                    const int32_t* tscene = nullptr, const uint8_t* sproj = nullptr);
 void launch_gather_grad(ms_ctx* c, const double* x, double h2, double* g);
 void launch_gather_hess(ms_ctx* c, const double* x, double h2, int prec);
 void launch_block_jacobi(ms_ctx* c, int prec);
@@ -288,6 +291,7 @@ ms_status pcg_solve(ms_ctx* c, int prec, int pc, double eta_max, double eta_min,
                     int* code, int forcing);
 void launch_restrict(ms_ctx* c, const double* v, const double* weight, const double* scal);
 void launch_cg_update(ms_ctx* c, int prec, int parity);
+void destroy_batch(ms_ctx* c);
 ms_status time_loop_kernel(ms_ctx* c, int kernel, int prec, int reps, double* avg_us, double* bytes);
 void launch_cg_iteration(ms_ctx* c, int prec, int pc, int parity, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 void launch_precond(ms_ctx* c, int pc, int prec, const double* r, double* z);

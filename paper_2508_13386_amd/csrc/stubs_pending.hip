@@ -9,7 +9,4 @@ ms_status record_coarse(ms_ctx*) { return MS_OK; }
 
 extern "C" {
 ms_status ms_set_warmstart(ms_ctx*, const ms_mlp_desc*) { return MS_E_ORDER; }
-ms_status ms_batch_step(ms_ctx* const*, int32_t, double, const ms_solver_params*, ms_step_stats*) {
-  return MS_E_ORDER;
-}
 }
