@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="mixed")
     ap.add_argument("--pc", choices=["jacobi", "two_level", "additive"], default="additive")
     ap.add_argument("--handles", type=int, default=128)
+    ap.add_argument("--workload", choices=["block32", "batch64"], default="block32",
+                    help="block32: the heterogeneous block (default); batch64: 64 uneven scenes stepped together")
     ap.add_argument("--no-reference", action="store_true", help="skip the plain FP64 block-Jacobi run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=200, help="back-to-back replays of the product kernel")
@@ -178,6 +180,59 @@ def run(dev, s, params, warmup, steps, basis=None, handles=0, timed=True):
     return steps / elapsed, elapsed, stats, states, ctx, basis_s
 
 
+def batch_main(a):
+    """64 uneven scenes (cubes / ellipsoids, 1e3-5e4 tets each, E log-uniform
+    in [1e5, 1e9], bottom layer pinned, gravity) advanced by ms_batch_step;
+    the same scenes stepped one after another by ms_step are the reference
+    form (identical results)."""
+    import torch
+
+    import scenes
+    from paper_2508_13386_amd import ms
+    scs = scenes.batch_scenes(64, seed=0)
+    dev = ms.TorchDevice(0)
+    prec = ms.PREC_MIXED if a.precision == "mixed" else ms.PREC_FP64
+    params = ms.solver_defaults(precision=prec, forcing=1)
+    dt = scs[0]["dt"]
+
+    def timed(step_all):
+        ctxs = [ms.context_from_scene(dev, s) for s in scs]
+        for _ in range(a.warmup):
+            step_all(ctxs)
+        dev.stream.synchronize()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stats = [step_all(ctxs) for _ in range(a.steps)]
+        dev.stream.synchronize()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        xs = [c.ms_get_state()[0] for c in ctxs]
+        for c in ctxs:
+            c.close()
+        return a.steps / el, el, stats, xs
+
+    value, elapsed, stats, xb = timed(lambda cs: ms.ms_batch_step(cs, dt, params))
+    ref = None
+    if not a.no_reference:
+        rv, _, _, xr = timed(lambda cs: [c.ms_step(dt, params) for c in cs])
+        ref = {"form": "the same 64 scenes stepped one after another (ms_step)", "value": rv,
+               "unit": "batch timesteps/s", "speedup": value / rv,
+               "bitwise_equal_states": bool(all(np.array_equal(p, q) for p, q in zip(xb, xr)))}
+    out = {
+        "metric": "batched Newton-PCG timesteps/s (all 64 scenes per step)",
+        "value": value, "unit": "batch timesteps/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": 1e3 * elapsed / a.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if a.precision == "fp64" else "f32+f64", "data": "synthetic",
+        "config": {"workload": "64 uneven scenes, seed 0", "n_tets": int(sum(len(s["tets"]) for s in scs)),
+                   "n_verts": int(sum(len(s["rest"]) for s in scs)), "precision": a.precision,
+                   "preconditioner": "jacobi", "parallelism": "single GPU"},
+        "solver": {"max_newton_iters": [max(st["newton_iters"] for st in step) for step in stats],
+                   "max_pcg_iters": [max(st["pcg_iters"] for st in step) for step in stats]},
+        "reference_form": ref,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -189,6 +244,9 @@ def main():
         return
     if a.trace_summary:
         trace_summary(a.trace_summary, a.work_us, a.tail)
+        return
+    if a.workload == "batch64":
+        batch_main(a)
         return
     import scenes
     from paper_2508_13386_amd import ms

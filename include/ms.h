@@ -84,7 +84,9 @@ typedef struct {
   int32_t max_newton;      /* Newton iteration cap (MS_E_NOCONV beyond it)              */
   int32_t max_pcg;         /* PCG iteration cap per Newton iteration                   */
   double newton_tol;       /* plain mode: stop when a full step has
-                              ||d||_2 <= newton_tol * max(||x - x^t||_2, abs_floor)     */
+                              ||d||_2 <= newton_tol * max(||x - x^t||_2, abs_floor),
+                              or ||d||_2 <= 1e-13 ||x||_2 (below the resolution of the
+                              FP64 positions: an almost static step)                   */
   double abs_floor;        /* absolute displacement floor of that test (m)              */
   double pcg_eta_max;      /* upper bound of the PCG forcing term (see forcing)         */
   double pcg_eta_min;      /* lower bound of the forcing term                           */

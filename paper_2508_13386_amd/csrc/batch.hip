@@ -575,7 +575,9 @@ ms_status batch_step(BatchPlan* B, double dt, const ms_solver_params& P, ms_step
     MS_HIP(hipMemcpyAsync(B->d_salpha, alpha.data(), sizeof(double) * ns, hipMemcpyHostToDevice, u->stream));
     k_baxpy<<<nblk(u->n, 256), 256, 0, u->stream>>>(u->n, B->d_ubscene, B->d_salpha, u->d_d, u->d_x);
   }
-  std::vector<double> dnorm(ns, 0.0), disp(ns, 0.0);
+  std::vector<double> dnorm(ns, 0.0), disp(ns, 0.0), xres(ns, 0.0);
+  if ((s = bdots(B, nullptr, nullptr, u->d_x, u->d_x, nullptr, nullptr, h))) return s;
+  for (int q = 0; q < ns; ++q) xres[q] = 1e-13 * std::sqrt(h[8 * q + 1]);
   for (int it = 0; it < P.max_newton; ++it) {
     bool any = false;
     for (int q = 0; q < ns; ++q) any = any || active[q];
@@ -672,7 +674,7 @@ ms_status batch_step(BatchPlan* B, double dt, const ms_solver_params& P, ms_step
       S[q].min_alpha = std::min(S[q].min_alpha, alpha[q]);
       disp[q] = std::sqrt(h[8 * q + 2]);
       const double ref = std::max(disp[q], P.abs_floor);
-      if (alpha[q] == 1.0 && dnorm[q] <= P.newton_tol * ref) {
+      if (alpha[q] == 1.0 && (dnorm[q] <= P.newton_tol * ref || dnorm[q] <= xres[q])) {
         active[q] = 0;
         done[q] = 1;
         S[q].newton_iters = it + 1;

@@ -6,7 +6,8 @@
 // the step is truncated by the half-space CCD bound and backtracked until the
 // Armijo condition holds on the FP64 energy difference (evaluated term by
 // term, with a round-off allowance).  The iteration stops after a
-// full step with ||d|| <= newton_tol * max(||x - x^t||, abs_floor).
+// full step with ||d|| <= newton_tol * max(||x - x^t||, abs_floor) or with
+// ||d|| below the round-off resolution 1e-13 ||x|| of the positions.
 //
 // Near the minimiser the element Hessians are used without the PSD
 // projection (the exact Hessian), which restores quadratic convergence;
@@ -95,6 +96,10 @@ ms_status plain_step(ms_ctx* c, double dt, const ms_solver_params& P, ms_step_st
   } else if (P.predictor == 1) {
     if ((s = inertial_start(c, h2))) return restore(c, s);
   }
+  // round-off resolution of the positions (the step cannot be resolved below it)
+  launch_dots(c, nullptr, nullptr, c->d_x, c->d_x, nullptr, nullptr);
+  if ((s = read_scal(c))) return restore(c, s);
+  const double xres = 1e-13 * std::sqrt(c->h_scal[S_DOT1]);
   bool endgame = false, converged = false, first = true;
   double dnorm = 0.0, disp = 0.0;
   int it = 0;
@@ -144,7 +149,7 @@ ms_status plain_step(ms_ctx* c, double dt, const ms_solver_params& P, ms_step_st
                    "[ms] it %d proj %d pcg %d code %d eta %.2e |g| %.3e gd %.3e |d| %.3e alpha %.3g bt %d disp %.3e\n",
                    it, int(project), iters, code, c->h_scal[S_ETA], std::sqrt(c->h_scal[S_RHO0]), gd, dnorm, alpha, nbt,
                    disp);
-    if (alpha == 1.0 && dnorm <= P.newton_tol * ref) {
+    if (alpha == 1.0 && (dnorm <= P.newton_tol * ref || dnorm <= xres)) {
       converged = true;
       ++it;
       break;
