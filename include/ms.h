@@ -251,6 +251,30 @@ typedef struct {
   const float *in_mean, *in_std, *out_scale;
 } ms_mlp_desc;
 ms_status ms_set_warmstart(ms_ctx* c, const ms_mlp_desc* d);
+/* Install the network (NULL removes it).  Requires a basis; in_dim = 2 r,
+ * out_dim = r, r = 12 m.  Weights are copied.  The prediction is used by
+ * ms_step with warm_start = 1 once two coarse states are recorded (the
+ * history restarts at ms_set_state), and only if it lowers the energy;
+ * otherwise the step starts as without it.  Errors: MS_E_ORDER (no basis),
+ * MS_E_ARG (shapes, non-positive std), MS_E_NONFINITE. */
+
+/* The network on the GPU without a context (training and parity checks).
+ * params: the six arrays W0 [w][in], b0 [w], W1 [w][w], b1 [w],
+ * W2 [out][w], b2 [out] concatenated, FP32 host.  Products run on bf16
+ * matrix cores with FP32 accumulation.  Work runs on dev->hip_stream.
+ * ms_mlp_forward: Z [n][in] (already standardised) -> Y [n][out].
+ * ms_mlp_train: Adam (beta 0.9 / 0.999, eps 1e-8, bias-corrected, FP32
+ * master weights) on the mean squared error; step s uses the samples
+ * order[s * batch .. (s+1) * batch) of X [n_samples][in], T [n_samples][out];
+ * params are updated in place; losses [n_steps] (optional) receives each
+ * step's loss before its update and first_grads (optional, same layout as
+ * params) the gradient of the first step.  Errors: MS_E_ARG (shapes,
+ * indices out of range), MS_E_NOMEM, MS_E_DEVICE. */
+ms_status ms_mlp_forward(const ms_device* dev, int32_t in_dim, int32_t width, int32_t out_dim, const float* params,
+                         int64_t n, const float* Z, float* Y);
+ms_status ms_mlp_train(const ms_device* dev, int32_t in_dim, int32_t width, int32_t out_dim, float* params,
+                       int64_t n_samples, const float* X, const float* T, int32_t n_steps, int32_t batch,
+                       const int32_t* order, float lr, float* losses, float* first_grads);
 
 /* ---- kernel-level entry points (parity checks and measurements) ---------
  * ms_eval: at positions x [n][3] (host), with x~ = x^t + dt v^t from the

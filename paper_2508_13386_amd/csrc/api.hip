@@ -495,6 +495,7 @@ void ms_destroy(ms_ctx* c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
   destroy_batch(c);
+  destroy_mlp(c);
   destroy_graphs(c);
   for (auto& e : c->tev)
     if (e) (void)hipEventDestroy(e);

@@ -292,6 +292,7 @@ ms_status pcg_solve(ms_ctx* c, int prec, int pc, double eta_max, double eta_min,
 void launch_restrict(ms_ctx* c, const double* v, const double* weight, const double* scal);
 void launch_cg_update(ms_ctx* c, int prec, int parity);
 void destroy_batch(ms_ctx* c);
+void destroy_mlp(ms_ctx* c);
 ms_status time_loop_kernel(ms_ctx* c, int kernel, int prec, int reps, double* avg_us, double* bytes);
 void launch_cg_iteration(ms_ctx* c, int prec, int pc, int parity, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 void launch_precond(ms_ctx* c, int pc, int prec, const double* r, double* z);

@@ -93,7 +93,8 @@ ms_status plain_step(ms_ctx* c, double dt, const ms_solver_params& P, ms_step_st
   ms_status s;
   if (P.warm_start && c->mlp) {
     if ((s = warm_start(c, dt, &S.warm_start_used))) return restore(c, s);
-  } else if (P.predictor == 1) {
+  }
+  if (!S.warm_start_used && P.predictor == 1) {
     if ((s = inertial_start(c, h2))) return restore(c, s);
   }
   // round-off resolution of the positions (the step cannot be resolved below it)

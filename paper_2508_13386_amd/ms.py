@@ -105,6 +105,8 @@ def lib():
             "ms_energy_difference": [vp, dp, dp, d, d, dp],
             "ms_basis_compute": [i64, dp, i64, ip, dp, i64, ip, C.POINTER(ms_basis_params), C.POINTER(C.c_void_p)],
             "ms_basis_get": [vp, C.POINTER(i32), C.POINTER(i64), dp, ip, ip, dp, ip],
+            "ms_mlp_forward": [C.POINTER(ms_device), i32, i32, i32, vp, i64, vp, vp],
+            "ms_mlp_train": [C.POINTER(ms_device), i32, i32, i32, vp, i64, vp, vp, i32, i32, vp, C.c_float, vp, vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -288,7 +290,22 @@ class Context:
         self._check(self.L.ms_get_coarse(self.h, _ptr(q)))
         return q
 
-    def ms_set_warmstart(self, desc: ms_mlp_desc):
+    def ms_set_warmstart(self, params=None, in_mean=None, in_std=None, out_scale=None):
+        """Install the warm-start network (dict W0 b0 W1 b1 W2 b2, float32
+        row-major [out][in]) with its input standardisation and output scale;
+        params None removes it."""
+        if params is None:
+            self._check(self.L.ms_set_warmstart(self.h, None))
+            return
+        keep = {k: np.ascontiguousarray(params[k], dtype=np.float32) for k in MLP_KEYS}
+        keep["m"] = np.ascontiguousarray(in_mean, dtype=np.float32)
+        keep["s"] = np.ascontiguousarray(in_std, dtype=np.float32)
+        keep["o"] = np.ascontiguousarray(out_scale, dtype=np.float32)
+        fp = lambda a: a.ctypes.data_as(_FP)
+        w, i = keep["W0"].shape
+        o = keep["W2"].shape[0]
+        desc = ms_mlp_desc(i, w, o, fp(keep["W0"]), fp(keep["b0"]), fp(keep["W1"]), fp(keep["b1"]),
+                           fp(keep["W2"]), fp(keep["b2"]), fp(keep["m"]), fp(keep["s"]), fp(keep["o"]))
         self._check(self.L.ms_set_warmstart(self.h, C.byref(desc)))
 
     # -- kernel-level queries ---------------------------------------------------
@@ -361,6 +378,61 @@ def ms_basis_compute(rest, tets, E, dbc=(), params=None, **kw):
     finally:
         L.ms_basis_free(h)
     return dict(origins=o, vptr=vp, vhandle=vh, vphi=w, part=part, m=m.value)
+
+
+MLP_KEYS = ("W0", "b0", "W1", "b1", "W2", "b2")
+
+
+def mlp_pack(p):
+    return np.concatenate([np.asarray(p[k], dtype=np.float32).ravel() for k in MLP_KEYS])
+
+
+def mlp_unpack(flat, in_dim, width, out_dim):
+    shapes = {"W0": (width, in_dim), "b0": (width,), "W1": (width, width), "b1": (width,),
+              "W2": (out_dim, width), "b2": (out_dim,)}
+    out, k = {}, 0
+    for name in MLP_KEYS:
+        size = int(np.prod(shapes[name]))
+        out[name] = np.asarray(flat[k:k + size], dtype=np.float32).reshape(shapes[name]).copy()
+        k += size
+    return out
+
+
+def _mlp_dims(p):
+    w, i = np.asarray(p["W0"]).shape
+    return i, w, np.asarray(p["W2"]).shape[0]
+
+
+def ms_mlp_forward(dev, params, Z):
+    """Network outputs for Z [n][in] (standardised inputs) on the GPU."""
+    L = lib()
+    i, w, o = _mlp_dims(params)
+    flat = mlp_pack(params)
+    Z = np.ascontiguousarray(Z, dtype=np.float32)
+    Y = np.empty((len(Z), o), dtype=np.float32)
+    code = L.ms_mlp_forward(C.byref(dev.desc), i, w, o, _ptr(flat), len(Z), _ptr(Z), _ptr(Y))
+    if code != MS_OK:
+        raise MSError(code, "ms_mlp_forward")
+    return Y
+
+
+def ms_mlp_train(dev, params, X, T, order, lr, grads=False):
+    """Adam on the GPU over the minibatches order [n_steps][batch]; returns
+    (trained params, per-step losses, first-step gradients or None)."""
+    L = lib()
+    i, w, o = _mlp_dims(params)
+    flat = mlp_pack(params)
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    T = np.ascontiguousarray(T, dtype=np.float32)
+    order = np.ascontiguousarray(order, dtype=np.int32)
+    n_steps, batch = order.shape
+    losses = np.empty(n_steps, dtype=np.float32)
+    g = np.empty_like(flat) if grads else None
+    code = L.ms_mlp_train(C.byref(dev.desc), i, w, o, _ptr(flat), len(X), _ptr(X), _ptr(T), n_steps, batch,
+                          _ptr(order), C.c_float(lr), _ptr(losses), _ptr(g) if grads else None)
+    if code != MS_OK:
+        raise MSError(code, "ms_mlp_train")
+    return mlp_unpack(flat, i, w, o), losses, (mlp_unpack(g, i, w, o) if grads else None)
 
 
 def ms_batch_step(contexts, dt, params=None, **kw):

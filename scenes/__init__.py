@@ -268,3 +268,26 @@ def spd_bsr_pattern(N: int, seed: int = 0, permute: bool = False):
     diag = rows == cols
     vals[diag] += 40.0 * np.eye(3)
     return row_ptr, cols.astype(np.int32), vals
+
+
+def mlp_init(in_dim: int, width: int, out_dim: int, seed: int = 0):
+    """Seeded initial weights of the warm-start network (uniform in
+    +-1/sqrt(fan_in), row-major [out][in]) as float32, shared by the GPU
+    trainer and the oracle."""
+    rng = np.random.default_rng(seed)
+    out = {}
+    for name, (o, i) in (("0", (width, in_dim)), ("1", (width, width)), ("2", (out_dim, width))):
+        bound = 1.0 / math.sqrt(i)
+        out["W" + name] = rng.uniform(-bound, bound, size=(o, i)).astype(np.float32)
+        out["b" + name] = rng.uniform(-bound, bound, size=o).astype(np.float32)
+    return out
+
+
+def minibatch_order(n_samples: int, batch: int, n_steps: int, seed: int = 0):
+    """Sample indices of every training step (a fresh permutation per epoch),
+    shape [n_steps, batch], int32."""
+    rng = np.random.default_rng(seed)
+    idx = []
+    while len(idx) < n_steps * batch:
+        idx.extend(rng.permutation(n_samples).tolist())
+    return np.asarray(idx[:n_steps * batch], dtype=np.int32).reshape(n_steps, batch)

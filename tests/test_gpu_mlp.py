@@ -1,0 +1,99 @@
+"""GPU warm-start network (bf16 matrix cores, FP32 accumulation) against
+the FP64 oracle, and timesteps started from its prediction."""
+import numpy as np
+import pytest
+
+import scenes
+from oracle import fem, mlp, newton
+from tests.gpu_util import device, e_rel, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return device()
+
+
+def _abs_bound(p, Z):
+    """Propagated absolute sums |W2| 1.1 (|W1| 1.1 (|W0| |z| + |b0|) + |b1|) + |b2|:
+    bf16 operands with FP32 accumulation keep each layer's error below a
+    small multiple of 2^-8 of these sums (silu' <= 1.1)."""
+    a0 = np.abs(Z) @ np.abs(p["W0"]).T + np.abs(p["b0"])
+    a1 = 1.1 * a0 @ np.abs(p["W1"]).T + np.abs(p["b1"])
+    return 1.1 * a1 @ np.abs(p["W2"]).T + np.abs(p["b2"])
+
+
+@pytest.mark.parametrize("dims,n", [((40, 32, 20), 5), ((130, 70, 65), 37), ((1032, 256, 516), 3)])
+def test_mlp_forward_matches_oracle(dev, dims, n):
+    from paper_2508_13386_amd import ms
+    i, w, o = dims
+    p = scenes.mlp_init(i, w, o, seed=1)
+    Z = np.random.default_rng(2).standard_normal((n, i)).astype(np.float32)
+    Y = ms.ms_mlp_forward(dev, p, Z)
+    p64 = {k: v.astype(np.float64) for k, v in p.items()}
+    Yo, _ = mlp.forward(p64, Z.astype(np.float64))
+    err = np.abs(Y - Yo) / _abs_bound(p64, Z.astype(np.float64))
+    say("mlp forward", dims, n, "max err / bound-scale", err.max())
+    assert err.max() <= 3 * 2.0 ** -8
+
+
+def test_mlp_first_gradients_match_oracle(dev):
+    from paper_2508_13386_amd import ms
+    i, w, o = 72, 48, 36
+    p = scenes.mlp_init(i, w, o, seed=3)
+    rng = np.random.default_rng(4)
+    X = rng.standard_normal((100, i)).astype(np.float32)
+    T = np.tanh(X[:, :o]).astype(np.float32)
+    order = scenes.minibatch_order(100, 32, 1, seed=5)
+    _, losses, g = ms.ms_mlp_train(dev, p, X, T, order, lr=1e-3, grads=True)
+    p64 = {k: v.astype(np.float64) for k, v in p.items()}
+    idx = order[0]
+    Yo, cache = mlp.forward(p64, X[idx].astype(np.float64))
+    go = mlp.backward(p64, cache, Yo, T[idx].astype(np.float64))
+    assert losses[0] == pytest.approx(mlp.loss(Yo, T[idx]), rel=2e-2)
+    for k in go:
+        rel = np.linalg.norm(g[k] - go[k]) / np.linalg.norm(go[k])
+        say("grad", k, "rel", rel)
+        assert rel <= 5e-2
+
+
+def test_mlp_training_tracks_oracle(dev):
+    from paper_2508_13386_amd import ms
+    rng = np.random.default_rng(6)
+    X = rng.standard_normal((256, 24)).astype(np.float32)
+    T = np.tanh(0.5 * X[:, :12]).astype(np.float32)
+    p0 = scenes.mlp_init(24, 32, 12, seed=7)
+    order = scenes.minibatch_order(256, 32, 300, seed=8)
+    _, lg, _ = ms.ms_mlp_train(dev, p0, X, T, order, lr=3e-3)
+    _, lo = mlp.train(p0, X.astype(np.float64), T.astype(np.float64), order, lr=3e-3)
+    say("loss gpu", lg[0], lg[-1], "oracle", lo[0], lo[-1])
+    assert np.mean(lg[-20:]) < 0.2 * np.mean(lg[:5])
+    assert np.mean(lg[-20:]) <= 2.0 * np.mean(lo[-20:]) + 1e-4
+
+
+def test_warm_started_steps_match_oracle(dev):
+    """A network with zero weights predicts the constant-velocity coarse
+    state; the step it starts must still land on the oracle's minimiser."""
+    from paper_2508_13386_amd import ms
+    s = scenes.inclusion_block(8, seed=1, steps=4)
+    c = ms.context_from_scene(dev, s)
+    c.ms_build_basis(n_handles=8, seed=2)
+    r = 12 * c.ms_get_basis()["m"]
+    zero = {k: np.zeros_like(v) for k, v in scenes.mlp_init(2 * r, 16, r, seed=0).items()}
+    c.ms_set_warmstart(zero, np.zeros(2 * r), np.ones(2 * r), np.ones(r))
+    body = fem.Body(s["rest"], s["tets"], s["E"], s["nu"], s["rho"])
+    x, v = s["x0"].copy(), s["v0"].copy()
+    used = []
+    for k in range(1, 5):
+        xo, vo, _ = newton.newton_step(body, x, v, s["dt"], s["gravity"], s["dirichlet"], s["dbc_targets"](k))
+        c.ms_set_dirichlet(s["dirichlet"], s["dbc_targets"](k))
+        st = c.ms_step(s["dt"], warm_start=1)
+        xg, vg = c.ms_get_state()
+        err = e_rel(xg, xo, x)
+        used.append(st["warm_start_used"])
+        say("warm step", k, "e_rel", err, "used", st["warm_start_used"], "newton", st["newton_iters"])
+        assert err <= 1e-6
+        x, v = xg, vg  # continue from the GPU state: the coarse history is the GPU's
+    assert used[0] == 0 and sum(used[1:]) >= 1
+    c.close()
