@@ -46,8 +46,14 @@ def parse():
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="mixed")
     ap.add_argument("--pc", choices=["jacobi", "two_level", "additive"], default="additive")
     ap.add_argument("--handles", type=int, default=128)
-    ap.add_argument("--workload", choices=["block32", "batch64"], default="block32",
-                    help="block32: the heterogeneous block (default); batch64: 64 uneven scenes stepped together")
+    ap.add_argument("--eta-max", type=float, default=0.5, help="largest PCG forcing term (Eisenstat-Walker)")
+    ap.add_argument("--workload", choices=["block32", "batch64", "learned"], default="block32",
+                    help="block32: the heterogeneous block (default); batch64: 64 uneven scenes stepped together; "
+                         "learned: train the coarse warm start on trajectories and evaluate it on held-out seeds")
+    ap.add_argument("--train-seeds", type=int, default=40)
+    ap.add_argument("--eval-seeds", type=int, default=6)
+    ap.add_argument("--traj-grid", type=int, default=16)
+    ap.add_argument("--traj-steps", type=int, default=30)
     ap.add_argument("--no-reference", action="store_true", help="skip the plain FP64 block-Jacobi run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=200, help="back-to-back replays of the product kernel")
@@ -192,7 +198,7 @@ def batch_main(a):
     scs = scenes.batch_scenes(64, seed=0)
     dev = ms.TorchDevice(0)
     prec = ms.PREC_MIXED if a.precision == "mixed" else ms.PREC_FP64
-    params = ms.solver_defaults(precision=prec, forcing=1)
+    params = ms.solver_defaults(precision=prec, forcing=1, pcg_eta_max=a.eta_max)
     dt = scs[0]["dt"]
 
     def timed(step_all):
@@ -233,6 +239,114 @@ def batch_main(a):
     print(json.dumps(out), flush=True)
 
 
+def learned_main(a):
+    """Trajectories of the heterogeneous-block generator (per-seed inclusions,
+    10-step ramp then held) at traj_grid^3 with a 64-handle lattice basis;
+    the warm-start network is trained on the training seeds' coarse states
+    (GPU, bf16 matrix cores) and the timesteps of held-out seeds are run with
+    and without it.  Both runs solve every step to the plain-path tolerance;
+    the gain is in Newton / PCG iterations and time."""
+    import torch
+
+    import scenes
+    from paper_2508_13386_amd import ms
+    dev = ms.TorchDevice(0)
+    prec = ms.PREC_MIXED if a.precision == "mixed" else ms.PREC_FP64
+    base = dict(precision=prec, preconditioner=ms.PC_TWO_LEVEL_ADDITIVE, forcing=1, pcg_eta_max=a.eta_max,
+                max_newton=100)
+
+    def trajectory(seed, warm=None):
+        """Coarse states, step stats and states of one trajectory, or None if
+        a step fails to converge (reported and left out)."""
+        try:
+            return _trajectory(seed, warm)
+        except ms.MSError as e:
+            print(f"trajectory seed {seed} warm {warm is not None}: {e}", file=sys.stderr, flush=True)
+            return None
+
+    def _trajectory(seed, warm=None):
+        sc = scenes.learned_trajectory_scene(seed, N=a.traj_grid, steps=a.traj_steps)
+        c = ms.context_from_scene(dev, sc)
+        try:
+            c.ms_build_basis(n_handles=43, lattice_seeding=1)
+            r = 12 * c.ms_get_basis()["m"]
+            if warm is not None:
+                c.ms_set_warmstart(*warm)
+            qs = [c.ms_get_coarse(r)]
+            stats, xs = [], []
+            for k in range(1, a.traj_steps + 1):
+                c.ms_set_dirichlet(sc["dirichlet"], sc["dbc_targets"](k))
+                stats.append(c.ms_step(sc["dt"], ms.solver_defaults(warm_start=1 if warm else 0, **base)))
+                qs.append(c.ms_get_coarse(r))
+                xs.append(c.ms_get_state()[0])
+        finally:
+            c.close()
+        print(f"trajectory seed {seed} warm {warm is not None}: newton {sum(st['newton_iters'] for st in stats)}",
+              file=sys.stderr, flush=True)
+        return np.array(qs), stats, xs, r
+
+    t0 = time.perf_counter()
+    train = [t for t in (trajectory(sd) for sd in scenes.TRAIN_SEEDS[:a.train_seeds]) if t is not None]
+    gen_s = time.perf_counter() - t0
+    r = train[0][3]
+    train = [t for t in train if t[3] == r]
+    Xs, Ys = [], []
+    for qs, _, _, _ in train:
+        for k in range(1, len(qs) - 1):
+            Xs.append(np.concatenate([qs[k - 1], qs[k]]))
+            Ys.append(qs[k + 1] - (2 * qs[k] - qs[k - 1]))
+    X, Y = np.array(Xs), np.array(Ys)
+    # one scale per array (not per coordinate): coordinates that barely move
+    # (handles near the pinned base) would otherwise have round-off-level
+    # accelerations blown up to unit variance
+    mean = X.mean(axis=0)
+    std = np.full(X.shape[1], (X - mean).std() + 1e-30)
+    oscale = np.full(Y.shape[1], Y.std() + 1e-30)
+    Xn, Yn = ((X - mean) / std).astype(np.float32), (Y / oscale).astype(np.float32)
+    p0 = scenes.mlp_init(2 * r, 256, r, seed=0)
+    steps = 1500
+    order = scenes.minibatch_order(len(Xn), 128, steps, seed=1)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    params, losses, _ = ms.ms_mlp_train(dev, p0, Xn, Yn, order, lr=1e-3)
+    train_s = time.perf_counter() - t1
+    warm = (params, mean, std, oscale)
+    rows, skipped = [], []
+    for sd in scenes.HELDOUT_SEEDS[:a.eval_seeds]:
+        t0_, t1_ = trajectory(sd), trajectory(sd, warm)
+        if t0_ is None or t1_ is None:
+            skipped.append(dict(seed=sd, base_failed=t0_ is None, warm_failed=t1_ is None))
+            continue
+        _, s0, x0, _ = t0_
+        _, s1, x1, _ = t1_
+        e = max(float(np.linalg.norm(p - q) / max(np.linalg.norm(p), 1e-300)) for p, q in zip(x0, x1))
+        rows.append(dict(seed=sd, newton=[sum(st["newton_iters"] for st in s0), sum(st["newton_iters"] for st in s1)],
+                         pcg=[sum(st["pcg_iters"] for st in s0), sum(st["pcg_iters"] for st in s1)],
+                         ms=[sum(st["time_ms"] for st in s0), sum(st["time_ms"] for st in s1)],
+                         used=sum(st["warm_start_used"] for st in s1), max_state_rel_diff=e))
+    t_base = sum(rw["ms"][0] for rw in rows)
+    t_warm = sum(rw["ms"][1] for rw in rows)
+    out = {
+        "metric": "held-out timesteps/s with the learned coarse warm start",
+        "value": 1e3 * a.traj_steps * len(rows) / t_warm, "unit": "timesteps/s", "n_gpus": 1,
+        "steps": a.traj_steps * len(rows), "warmup": 0, "ms_per_step": t_warm / (a.traj_steps * len(rows)),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if a.precision == "fp64" else "f32+f64", "data": "synthetic",
+        "config": {"workload": f"heterogeneous block {a.traj_grid}^3, per-seed inclusions, {a.traj_steps} steps",
+                   "handles": r // 12, "train_seeds": len(train), "samples": int(len(Xn)),
+                   "network": f"{2 * r}-256-256-{r} SiLU, bf16 products", "parallelism": "single GPU"},
+        "training": {"steps": steps, "batch": 128, "lr": 1e-3, "loss_first": float(losses[0]),
+                     "loss_last": float(np.mean(losses[-50:])), "train_s": train_s, "data_gen_s": gen_s},
+        "reference_form": {"form": "same held-out steps without the warm start (inertial predictor)",
+                           "value": 1e3 * a.traj_steps * len(rows) / t_base, "unit": "timesteps/s",
+                           "speedup": t_base / t_warm},
+        "per_seed": rows,
+        "skipped": skipped,
+        "train_trajectories_failed": a.train_seeds - len(train),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -248,6 +362,9 @@ def main():
     if a.workload == "batch64":
         batch_main(a)
         return
+    if a.workload == "learned":
+        learned_main(a)
+        return
     import scenes
     from paper_2508_13386_amd import ms
 
@@ -256,7 +373,7 @@ def main():
     dev = ms.TorchDevice(0)
     pc = {"jacobi": ms.PC_BLOCK_JACOBI, "two_level": ms.PC_TWO_LEVEL, "additive": ms.PC_TWO_LEVEL_ADDITIVE}[a.pc]
     prec = ms.PREC_MIXED if a.precision == "mixed" else ms.PREC_FP64
-    params = ms.solver_defaults(precision=prec, preconditioner=pc, forcing=1)
+    params = ms.solver_defaults(precision=prec, preconditioner=pc, forcing=1, pcg_eta_max=a.eta_max)
     value, elapsed, stats, states, ctx, basis_s = run(dev, s, params, a.warmup, a.steps,
                                                       handles=a.handles if pc != ms.PC_BLOCK_JACOBI else 0)
     # the product kernel replayed back to back on the last Hessian (hot caches)
@@ -270,7 +387,7 @@ def main():
     # dispatches).
     k = a.warmup + a.steps + 1
     ctx.ms_set_dirichlet(s["dirichlet"], s["dbc_targets"](k))
-    tparams = ms.solver_defaults(precision=prec, preconditioner=pc, forcing=1, time_kernels=1)
+    tparams = ms.solver_defaults(precision=prec, preconditioner=pc, forcing=1, pcg_eta_max=a.eta_max, time_kernels=1)
     tstat = ctx.ms_step(s["dt"], tparams)
     k_us, k_bytes = ctx.ms_time_kernel(0, prec, 0)
     # slice height of the chosen layout, from the byte count of the product
@@ -286,7 +403,8 @@ def main():
 
     ref = None
     if not a.no_reference:
-        pref = ms.solver_defaults(precision=ms.PREC_FP64, preconditioner=ms.PC_BLOCK_JACOBI, forcing=1)
+        pref = ms.solver_defaults(precision=ms.PREC_FP64, preconditioner=ms.PC_BLOCK_JACOBI, forcing=1,
+                                  pcg_eta_max=a.eta_max)
         rv, _, rstats, rstates, rctx, _ = run(dev, s, pref, a.warmup, a.steps)
         rctx.close()
         xr, xg = rstates[-1], states[-1]

@@ -125,6 +125,8 @@ typedef struct {
   int32_t backtracks;         /* total line-search halvings                             */
   int32_t hessian_refreshes;  /* paper mode: lagged-Hessian recomputations              */
   int32_t warm_start_used;    /* 1 if the learned prediction was accepted               */
+  int32_t precision_escalations; /* mixed precision: 1 if the step finished with the FP64
+                                    Hessian after the Newton steps stopped shrinking      */
   double energy;              /* E at x^{t+1}                                            */
   double last_dnorm;          /* ||d||_2 of the last Newton step                         */
   double disp_norm;           /* ||x^{t+1} - x^t||_2                                     */

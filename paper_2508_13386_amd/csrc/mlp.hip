@@ -258,12 +258,13 @@ void destroy_mlp(ms_ctx* c) {
   c->mlp = nullptr;
 }
 
-// u-space warm start: called at step start with x = x^t (Dirichlet applied).
-ms_status warm_start(ms_ctx* c, double dt, int32_t* used) {
-  (void)dt;
+// Learned warm start, called at step start with x = x^t (Dirichlet
+// applied); falls back to the inertial predictor (if enabled) while no
+// prediction is available.
+ms_status warm_start(ms_ctx* c, double dt, bool inertial, int32_t* used) {
   *used = 0;
   Mlp* N = c->mlp;
-  if (!N || !c->has_basis || c->q_hist < 2) return MS_OK;
+  if (!N || !c->has_basis || c->q_hist < 2) return inertial ? inertial_start(c, dt * dt) : MS_OK;
   const int r = c->r;
   // z = ([q^{t-1}, q^t] - mean) / std, then the network, then
   // dq = (q^t - q^{t-1}) + out_scale * y  (= q_hat - q^t)
@@ -292,19 +293,46 @@ ms_status warm_start(ms_ctx* c, double dt, int32_t* used) {
   std::vector<float> y(N->out);
   MS_HIP(hipMemcpyAsync(y.data(), Y, N->out * sizeof(float), hipMemcpyDeviceToHost, c->stream));
   if ((s = sync(c))) return s;
+  // the network's correction of the constant-velocity coarse guess; the
+  // inertial predictor's coarse part is exactly that guess (q is linear in
+  // x and x~ = 2 x^t - x^{t-1}), so with the predictor on, the learned start
+  // is x~ + U (out_scale * y), else x^t + U (q^t - q^{t-1} + out_scale * y)
   std::vector<double> dq(r);
   for (int i = 0; i < r; ++i) {
-    dq[i] = (qc[i] - qp[i]) + double(scale[i]) * double(y[i]);
-    if (!std::isfinite(dq[i])) return MS_OK;  // no usable prediction: ordinary start
+    dq[i] = double(scale[i]) * double(y[i]) + (inertial ? 0.0 : qc[i] - qp[i]);
+    if (!std::isfinite(dq[i])) return inertial ? inertial_start(c, dt * dt) : MS_OK;  // no usable prediction
   }
   MS_HIP(hipMemcpyAsync(c->d_e, dq.data(), r * sizeof(double), hipMemcpyHostToDevice, c->stream));
-  launch_prolong_set_d(c);  // d = U dq, zero on pinned vertices
-  // accepted only if it lowers the energy (the move is made by try_move)
-  MS_HIP(hipMemcpyAsync(c->d_w, c->d_x, 3 * c->n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-  if ((s = try_move(c, dt * dt))) return s;
-  launch_dots(c, nullptr, nullptr, nullptr, nullptr, c->d_x, c->d_w);
-  if ((s = read_scal(c))) return s;
-  *used = c->h_scal[S_DOT2] > 0.0 ? 1 : 0;
+  const double h2 = dt * dt;
+  auto candidate = [&](double* dE, double* alpha) -> ms_status {
+    *alpha = 1.0;
+    ms_status st;
+    if (c->has_hs) {
+      launch_ccd(c, c->d_x, c->d_d);
+      if ((st = read_scal(c))) return st;
+      *alpha = std::fmin(1.0, c->h_scal[S_CCD]);
+    }
+    double err;
+    return energy_delta(c, c->d_x, c->d_d, *alpha, h2, dE, &err);
+  };
+  // candidates: the inertial predictor (if on) and the learned start; the
+  // lower-energy one is taken if it lowers E
+  double dE_i = INFINITY, a_i = 0.0, dE_l, a_l;
+  if (inertial) {
+    launch_predictor_dir(c);  // x~ - x, zero on pinned vertices
+    if ((s = candidate(&dE_i, &a_i))) return s;
+    MS_HIP(hipMemcpyAsync(c->d_p, c->d_d, 3 * c->n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    launch_prolong_add(c, c->d_d, nullptr);  // + U dq (zero on pinned vertices)
+  } else {
+    launch_prolong_set_d(c);  // U dq
+  }
+  if ((s = candidate(&dE_l, &a_l))) return s;
+  if (std::isfinite(dE_l) && dE_l < 0.0 && !(dE_i <= dE_l)) {
+    launch_axpy(c, c->d_x, c->d_d, a_l, 3 * c->n);
+    *used = 1;
+  } else if (std::isfinite(dE_i) && dE_i < 0.0) {
+    launch_axpy(c, c->d_x, c->d_p, a_i, 3 * c->n);
+  }
   return MS_OK;
 }
 

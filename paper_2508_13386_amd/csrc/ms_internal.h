@@ -319,7 +319,7 @@ void release_all(ms_ctx* c);
 ms_status time_cg_spmv(ms_ctx* c, int prec, int reps, double* avg_us, double* bytes);
 double cg_spmv_bytes(const ms_ctx* c, int prec);
 ms_status line_search(ms_ctx* c, double h2, double gd, int max_bt, double* alpha_out, int* nbt);
-ms_status warm_start(ms_ctx* c, double dt, int32_t* used);
+ms_status warm_start(ms_ctx* c, double dt, bool inertial, int32_t* used);
 ms_status inertial_start(ms_ctx* c, double h2);
 ms_status try_move(ms_ctx* c, double h2);
 void launch_predictor_dir(ms_ctx* c);

@@ -82,7 +82,7 @@ ms_status try_move(ms_ctx* c, double h2) {
 ms_status plain_step(ms_ctx* c, double dt, const ms_solver_params& P, ms_step_stats* st) {
   const double t0 = now_ms();
   const double h2 = dt * dt;
-  const int prec = P.precision == MS_PREC_MIXED ? MS_PREC_MIXED : MS_PREC_FP64;
+  int prec = P.precision == MS_PREC_MIXED ? MS_PREC_MIXED : MS_PREC_FP64;
   const int pc = (P.preconditioner >= 0 && P.preconditioner <= 2) ? P.preconditioner : MS_PC_BLOCK_JACOBI;
   if (two_level(pc) && !c->has_basis) return fail(c, MS_E_ORDER, "two-level preconditioner needs a basis");
   launch_predict(c, dt);
@@ -92,21 +92,21 @@ ms_status plain_step(ms_ctx* c, double dt, const ms_solver_params& P, ms_step_st
   S.min_alpha = 1.0;
   ms_status s;
   if (P.warm_start && c->mlp) {
-    if ((s = warm_start(c, dt, &S.warm_start_used))) return restore(c, s);
-  }
-  if (!S.warm_start_used && P.predictor == 1) {
+    if ((s = warm_start(c, dt, P.predictor == 1, &S.warm_start_used))) return restore(c, s);
+  } else if (P.predictor == 1) {
     if ((s = inertial_start(c, h2))) return restore(c, s);
   }
   // round-off resolution of the positions (the step cannot be resolved below it)
   launch_dots(c, nullptr, nullptr, c->d_x, c->d_x, nullptr, nullptr);
   if ((s = read_scal(c))) return restore(c, s);
   const double xres = 1e-13 * std::sqrt(c->h_scal[S_DOT1]);
-  bool endgame = false, converged = false, first = true;
-  double dnorm = 0.0, disp = 0.0;
-  int it = 0;
+  bool endgame = false, converged = false, first = true, escalated = false;
+  double dnorm = 0.0, disp = 0.0, best = INFINITY;
+  int it = 0, stall = 0;
   for (; it < P.max_newton; ++it) {
     const bool project = !(P.exact_endgame && endgame);
-    const bool refresh = it == 0 || (P.coarse_every > 0 && it % P.coarse_every == 0);
+    const bool refresh = it == 0 || escalated || (P.coarse_every > 0 && it % P.coarse_every == 0);
+    escalated = false;
     if ((s = assemble(c, c->d_x, h2, prec, project, true, pc, refresh))) return restore(c, s);
     int iters = 0, code = 0;
     if ((s = pcg_solve(c, prec, pc, P.pcg_eta_max, P.pcg_eta_min, first, P.max_pcg, &iters, &code, P.forcing)))
@@ -156,6 +156,19 @@ ms_status plain_step(ms_ctx* c, double dt, const ms_solver_params& P, ms_step_st
       break;
     }
     if (dnorm <= P.endgame_ratio * ref) endgame = true;
+    // Mixed precision: once the Newton step stops shrinking (the FP32
+    // Hessian limits the contraction on ill-conditioned systems), finish
+    // the step with the FP64 Hessian.
+    if (dnorm < 0.5 * best) {
+      best = dnorm;
+      stall = 0;
+    } else if (++stall >= 3 && prec == MS_PREC_MIXED) {
+      prec = MS_PREC_FP64;
+      escalated = true;
+      stall = 0;
+      ++S.precision_escalations;
+      if (c->verbose) std::fprintf(stderr, "[ms] it %d: continuing in FP64\n", it);
+    }
   }
   if (!converged) return restore(c, fail(c, MS_E_NOCONV, "Newton did not converge"));
   launch_velocity(c, 1.0 / dt);
