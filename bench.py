@@ -45,11 +45,20 @@ def parse():
     ap.add_argument("--grid", type=int, default=32)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="mixed")
     ap.add_argument("--pc", choices=["jacobi", "two_level", "additive"], default="additive")
-    ap.add_argument("--handles", type=int, default=128)
-    ap.add_argument("--eta-max", type=float, default=0.5, help="largest PCG forcing term (Eisenstat-Walker)")
-    ap.add_argument("--workload", choices=["block32", "batch64", "learned"], default="block32",
+    ap.add_argument("--handles", type=int, default=192)
+    ap.add_argument("--oversample", type=float, default=1.0, help="k-means++ seed oversampling of the basis build")
+    ap.add_argument("--eta-max", type=float, default=0.1, help="largest PCG forcing term (Eisenstat-Walker)")
+    ap.add_argument("--coarse-every", type=int, default=1,
+                    help="rebuild U^T H U and its inverse every this many Newton iterations (0: once per step)")
+    ap.add_argument("--endgame-fp64", type=int, default=1, help="mixed precision: FP64 Hessian in the Newton endgame")
+    ap.add_argument("--coarse-move", type=float, default=0.2,
+                    help="> 0: rebuild U^T H U once the iterate has moved by this fraction of the step's "
+                         "displacement since the last rebuild (replaces --coarse-every)")
+    ap.add_argument("--workload", choices=["block32", "batch64", "learned", "spmv_sweep"], default="block32",
                     help="block32: the heterogeneous block (default); batch64: 64 uneven scenes stepped together; "
-                         "learned: train the coarse warm start on trajectories and evaluate it on held-out seeds")
+                         "learned: train the coarse warm start on trajectories and evaluate it on held-out seeds; "
+                         "spmv_sweep: the PCG product kernel on the heterogeneous block at --sweep grid sizes")
+    ap.add_argument("--sweep", default="32,64,96,128", help="grid sizes of the spmv_sweep workload")
     ap.add_argument("--train-seeds", type=int, default=40)
     ap.add_argument("--eval-seeds", type=int, default=6)
     ap.add_argument("--traj-grid", type=int, default=16)
@@ -156,7 +165,7 @@ def copy_probe(mib):
     print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n, "copies": 5}), flush=True)
 
 
-def run(dev, s, params, warmup, steps, basis=None, handles=0, timed=True):
+def run(dev, s, params, warmup, steps, basis=None, handles=0, timed=True, oversample=1.0):
     """Runs warmup + steps timesteps; returns (timesteps/s, per-step stats,
     states after each timed step, context, basis seconds)."""
     import torch
@@ -166,7 +175,7 @@ def run(dev, s, params, warmup, steps, basis=None, handles=0, timed=True):
     basis_s = None
     if handles:
         t0 = time.perf_counter()
-        ctx.ms_build_basis(n_handles=handles, oversample=1.0)
+        ctx.ms_build_basis(n_handles=handles, oversample=oversample)
         basis_s = time.perf_counter() - t0
     stats, states = [], []
     for k in range(1, warmup + 1):
@@ -347,6 +356,41 @@ def learned_main(a):
     print(json.dumps(out), flush=True)
 
 
+def spmv_sweep_main(a):
+    """The PCG product kernel (k_cg_spmv, fused with its dot partials) on the
+    Hessian of the heterogeneous block at growing grid sizes: one Newton
+    iteration of the first timestep assembles H, then the kernel is replayed
+    back to back on it (--kernel-reps launches) in FP64 and in mixed storage.
+    Beyond the last-level cache the launch is bound by HBM bandwidth."""
+    import scenes
+    from paper_2508_13386_amd import ms
+    dev = ms.TorchDevice(0)
+    reps = max(1, a.kernel_reps)
+    for res in [int(v) for v in a.sweep.split(",") if v]:
+        t0 = time.perf_counter()
+        s = scenes.inclusion_block(res, seed=0, steps=1)
+        gen_s = time.perf_counter() - t0
+        ctx = ms.context_from_scene(dev, s)
+        ctx.ms_set_dirichlet(s["dirichlet"], s["dbc_targets"](1))
+        x0, v0 = ctx.ms_get_state()
+        for prec, name in ((ms.PREC_FP64, "fp64"), (ms.PREC_MIXED, "mixed")):
+            ctx.ms_set_state(x0, v0)
+            params = ms.solver_defaults(precision=prec, preconditioner=ms.PC_BLOCK_JACOBI, max_newton=1, max_pcg=4)
+            try:
+                ctx.ms_step(s["dt"], params)
+            except ms.MSError as e:
+                if e.code != ms.MS_E_NOCONV:
+                    raise
+            us, nbytes = ctx.ms_time_kernel(0, prec, reps)
+            gbs = nbytes / us * 1e-3
+            print(json.dumps({"workload": "spmv_sweep", "grid": res, "vertices": len(s["rest"]),
+                              "tets": len(s["tets"]), "storage": name, "kernel": "k_cg_spmv",
+                              "algorithmic_bytes": nbytes, "avg_launch_us": us, "launches": reps,
+                              "achieved_GBs": gbs, "frac_of_8TBs": gbs / HBM_PEAK_GBS,
+                              "scene_gen_s": round(gen_s, 2)}), flush=True)
+        ctx.close()
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -365,6 +409,9 @@ def main():
     if a.workload == "learned":
         learned_main(a)
         return
+    if a.workload == "spmv_sweep":
+        spmv_sweep_main(a)
+        return
     import scenes
     from paper_2508_13386_amd import ms
 
@@ -373,28 +420,37 @@ def main():
     dev = ms.TorchDevice(0)
     pc = {"jacobi": ms.PC_BLOCK_JACOBI, "two_level": ms.PC_TWO_LEVEL, "additive": ms.PC_TWO_LEVEL_ADDITIVE}[a.pc]
     prec = ms.PREC_MIXED if a.precision == "mixed" else ms.PREC_FP64
-    params = ms.solver_defaults(precision=prec, preconditioner=pc, forcing=1, pcg_eta_max=a.eta_max)
+    params = ms.solver_defaults(precision=prec, preconditioner=pc, forcing=1, pcg_eta_max=a.eta_max,
+                                coarse_every=a.coarse_every, coarse_move=a.coarse_move,
+                                mixed_endgame_fp64=a.endgame_fp64)
     value, elapsed, stats, states, ctx, basis_s = run(dev, s, params, a.warmup, a.steps,
-                                                      handles=a.handles if pc != ms.PC_BLOCK_JACOBI else 0)
-    # the product kernel replayed back to back on the last Hessian (hot caches)
-    r_us, _ = ctx.ms_time_kernel(0, prec, a.kernel_reps)
+                                                      handles=a.handles if pc != ms.PC_BLOCK_JACOBI else 0,
+                                                      oversample=a.oversample)
     # roofline of the dominant kernel, the PCG product fused with its dots:
     # one more timestep (outside the timed region) runs with every product
     # launch bracketed by HIP events on the library's stream, inside the real
     # PCG loop; the average over those launches is the kernel's duration.
     # These are the last product launches of the run (a profile can pick
     # them out as the kernel's last timed_step_pcg_iters + timed_step_solves
-    # dispatches).
+    # dispatches).  In mixed precision with the FP64 endgame both product
+    # instantiations run; the one that ran more PCG iterations in the timed
+    # region is reported.
+    fp64_share = sum(st["pcg_iters_fp64"] for st in stats) / max(1, sum(st["pcg_iters"] for st in stats))
+    kprec = ms.PREC_FP64 if fp64_share >= 0.5 else ms.PREC_MIXED
+    # the kernel replayed back to back on the last Hessian (hot caches)
+    r_us, _ = ctx.ms_time_kernel(0, kprec, a.kernel_reps)
     k = a.warmup + a.steps + 1
     ctx.ms_set_dirichlet(s["dirichlet"], s["dbc_targets"](k))
-    tparams = ms.solver_defaults(precision=prec, preconditioner=pc, forcing=1, pcg_eta_max=a.eta_max, time_kernels=1)
+    tparams = ms.solver_defaults(precision=prec, preconditioner=pc, forcing=1, pcg_eta_max=a.eta_max,
+                                 coarse_every=a.coarse_every, coarse_move=a.coarse_move,
+                                 mixed_endgame_fp64=a.endgame_fp64, time_kernels=1)
     tstat = ctx.ms_step(s["dt"], tparams)
-    k_us, k_bytes = ctx.ms_time_kernel(0, prec, 0)
+    k_us, k_bytes = ctx.ms_time_kernel(0, kprec, 0)
     # slice height of the chosen layout, from the byte count of the product
     # (4 bytes per slice offset; the rest is fixed by nnzb and n)
     _, col = ctx.ms_get_pattern()
     n = len(s["rest"])
-    vb = 8 if prec == ms.PREC_FP64 else 4
+    vb = 8 if kprec == ms.PREC_FP64 else 4
     nslices = int(round((k_bytes - len(col) * (9 * vb + 4) - 73 * n) / 4)) - 1
     S = next(c for c in (16, 32, 64) if -(-n // c) == nslices)
     kernel_name = f"k_cg_spmv<{'double' if vb == 8 else 'float'}, {S}>"
@@ -431,18 +487,24 @@ def main():
                                f"nu=0.49, top driven 0.1 m over 10 steps, dt=1/60",
                    "n_verts": int(len(s["rest"])), "n_tets": int(len(s["tets"])),
                    "precision": a.precision, "preconditioner": a.pc,
-                   "handles": a.handles if pc != ms.PC_BLOCK_JACOBI else None,
+                   "handles": a.handles if pc != ms.PC_BLOCK_JACOBI else None, "pcg_eta_max": a.eta_max,
+                   "coarse_every": a.coarse_every, "coarse_move": a.coarse_move, "endgame_fp64": a.endgame_fp64,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kernel_name),
                      "kernel": kernel_name + " (PCG product w = H u fused with its three dots, sliced BSR3)",
                      "bytes_per_launch": k_bytes, "avg_launch_us": k_us,
                      "timed_step_pcg_iters": int(tstat["pcg_iters"]),
+                     "timed_step_pcg_iters_fp64": int(tstat["pcg_iters_fp64"]),
+                     "fp64_share_of_pcg_iters": fp64_share,
                      "timed_step_solves": int(tstat["newton_iters"]),
                      "replay_avg_launch_us": r_us,
                      "replay_frac": k_bytes / (r_us * 1e-6) / 1e9 / HBM_PEAK_GBS},
         "solver": {"newton_iters": [st["newton_iters"] for st in stats],
                    "pcg_iters": [st["pcg_iters"] for st in stats],
+                   "pcg_iters_fp64": [st["pcg_iters_fp64"] for st in stats],
+                   "coarse_rebuilds": [st["hessian_refreshes"] for st in stats],
+                   "precision_escalations": [st["precision_escalations"] for st in stats],
                    "basis_build_s": basis_s},
         "reference_form": ref,
     }

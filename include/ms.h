@@ -106,15 +106,24 @@ typedef struct {
   int32_t forcing;         /* 0: eta = sqrt(||g||/||g_0||); 1: Eisenstat-Walker choice 2,
                               eta_k = 0.9 (||g_k||/||g_k-1||)^2 with safeguard          */
   double endgame_ratio;    /* exact (unprojected) Hessian once ||d|| <= ratio * ||x - x^t|| */
-  int32_t coarse_every;    /* two-level: rebuild U^T H U and its factor at the first Newton
-                              iteration of a step and then every coarse_every iterations
-                              (0: once per step; the preconditioner may lag H)          */
+  int32_t coarse_every;    /* additive two-level: rebuild U^T H U and its factor at the
+                              first Newton iteration of a step and then every coarse_every
+                              iterations (0: once per step; the preconditioner may lag
+                              H).  The smoothed form rebuilds at every iteration.       */
   int32_t predictor;       /* initial Newton iterate: 0 x^t; 1 the inertial predictor
                               x^t + h v^t (truncated by the contact filter, Dirichlet
                               vertices at their targets), kept only if it lowers E     */
   int32_t time_kernels;    /* 1: bracket every PCG product launch of this step with HIP
                               events (PCG runs without graphs); ms_time_kernel with
                               reps = 0 then reports their average duration             */
+  double coarse_move;      /* > 0, additive two-level: after the first Newton iteration,
+                              rebuild U^T H U and its factor only once the iterate has
+                              moved by more than coarse_move * max(||x - x^t||,
+                              abs_floor) since the last rebuild (replaces coarse_every) */
+  int32_t mixed_max_newton; /* mixed precision: continue the timestep in FP64 after this
+                              many Newton iterations without convergence (0: never)    */
+  int32_t mixed_endgame_fp64; /* mixed precision: 1 = assemble and solve in FP64 once
+                              ||d|| <= endgame_ratio * ||x - x^t|| (the tight solves)   */
 } ms_solver_params;
 
 /* Statistics of the last ms_step. */
@@ -123,10 +132,12 @@ typedef struct {
   int32_t pcg_iters;          /* total over the step                                    */
   int32_t max_pcg_iters;      /* largest single solve                                   */
   int32_t backtracks;         /* total line-search halvings                             */
-  int32_t hessian_refreshes;  /* paper mode: lagged-Hessian recomputations              */
+  int32_t hessian_refreshes;  /* paper mode: lagged-Hessian recomputations; plain mode
+                                 with a basis: rebuilds of U^T H U and its factor      */
   int32_t warm_start_used;    /* 1 if the learned prediction was accepted               */
-  int32_t precision_escalations; /* mixed precision: 1 if the step finished with the FP64
-                                    Hessian after the Newton steps stopped shrinking      */
+  int32_t precision_escalations; /* mixed precision: 1 if the step was continued in FP64
+                                    after mixed_max_newton iterations                    */
+  int32_t pcg_iters_fp64;     /* plain mode: PCG iterations run with the FP64 Hessian     */
   double energy;              /* E at x^{t+1}                                            */
   double last_dnorm;          /* ||d||_2 of the last Newton step                         */
   double disp_norm;           /* ||x^{t+1} - x^t||_2                                     */

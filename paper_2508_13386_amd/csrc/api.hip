@@ -232,6 +232,9 @@ void ms_solver_defaults(ms_solver_params* p) {
   p->endgame_ratio = 1e-3;
   p->coarse_every = 1;
   p->predictor = 1;
+  p->coarse_move = 0.0;
+  p->mixed_max_newton = 20;
+  p->mixed_endgame_fp64 = 0;
 }
 
 void ms_basis_defaults(ms_basis_params* p) {
@@ -487,6 +490,8 @@ ms_status ms_step(ms_ctx* c, double dt, const ms_solver_params* pin, ms_step_sta
     P = *pin;
   else
     ms_solver_defaults(&P);
+  if (!(P.coarse_move >= 0.0) || P.mixed_max_newton < 0)
+    return fail(c, MS_E_ARG, "coarse_move and mixed_max_newton must not be negative");
   if (P.mode == MS_MODE_PAPER) return paper_step(c, dt, P, st);
   return plain_step(c, dt, P, st);
 }

@@ -18,6 +18,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <type_traits>
 
 #include "ms_internal.h"
 #include "reduce.h"
@@ -98,11 +99,14 @@ __global__ void __launch_bounds__(256) k_restrict(const int4* __restrict__ chunk
 }
 
 // e = A c for a dense row-major r x r matrix A (FP64, or its FP32 copy in
-// mixed precision; leading dimension ld a multiple of 4) with c given by the
-// restriction partials: every block first forms c in LDS (c_(12 i + q) = sum
-// of handle i's partials q, in chunk order), then one wave per row, 8 rows
-// per 512-thread block.
+// mixed precision; leading dimension ld a multiple of 4, rows readable up to
+// ld) with c given by the restriction partials: every block first forms c in
+// LDS (c_(12 i + q) = sum of handle i's partials q, in chunk order), then one
+// wave per row, 8 rows per 512-thread block.  The first kGemvPre 16-byte
+// pieces of each lane's share of the row are loaded before the flag test
+// and the formation of c, so their latency overlaps both.
 constexpr int kGemvRows = 8;
+constexpr int kGemvPre = 8;
 template <typename AT>
 __global__ void __launch_bounds__(64 * kGemvRows) k_coarse_gemv(int r, int ld, const AT* __restrict__ A,
                                                       const int2* __restrict__ hinfo,
@@ -114,12 +118,13 @@ __global__ void __launch_bounds__(64 * kGemvRows) k_coarse_gemv(int r, int ld, c
   const int row = blockIdx.x * kGemvRows + wave;
   const AT* a = A + int64_t(row < r ? row : 0) * ld;
   constexpr int VW = 16 / sizeof(AT);  // elements per 16-byte load
-  // the first columns of the row are loaded before the flag is tested
-  AT a0[VW];
-  {
-    const int j = VW * lane;
+  constexpr int STRIDE = 64 * VW;
+  using V16 = typename std::conditional<sizeof(AT) == 4, float4, double2>::type;
+  V16 pre[kGemvPre];
 #pragma unroll
-    for (int q = 0; q < VW; ++q) a0[q] = j + q < r ? a[j + q] : AT(0);
+  for (int p = 0; p < kGemvPre; ++p) {
+    const int j = VW * lane + STRIDE * p;
+    pre[p] = j < ld ? *reinterpret_cast<const V16*>(a + j) : V16{};
   }
   if (done != 0.0) return;  // the flag is the same for the whole grid
   for (int idx = t; idx < r; idx += blockDim.x) {
@@ -132,13 +137,15 @@ __global__ void __launch_bounds__(64 * kGemvRows) k_coarse_gemv(int r, int ld, c
   __syncthreads();
   if (row >= r) return;
   double s = 0.0;
-  {
-    const int j = VW * lane;
+#pragma unroll
+  for (int p = 0; p < kGemvPre; ++p) {
+    const int j = VW * lane + STRIDE * p;
+    const AT* pv = reinterpret_cast<const AT*>(&pre[p]);
 #pragma unroll
     for (int q = 0; q < VW; ++q)
-      if (j + q < r) s += double(a0[q]) * sc[j + q];
+      if (j + q < r) s += double(pv[q]) * sc[j + q];
   }
-  for (int j = VW * lane + 64 * VW; j < r; j += 64 * VW) {
+  for (int j = VW * lane + STRIDE * kGemvPre; j < r; j += STRIDE) {
 #pragma unroll
     for (int q = 0; q < VW; ++q)
       if (j + q < r) s += double(a[j + q]) * sc[j + q];

@@ -7,7 +7,7 @@
 //
 // Panel k (tile row/column k of the current matrix A):
 //   k_gj_diag    D = inv(A_kk): in-place Gauss-Jordan of one tile by one
-//                wave; a pivot below 1e-12 of the original diagonal is
+//                block; a pivot below 1e-12 of the original diagonal is
 //                replaced by that diagonal (keeps the result SPD when U has
 //                null directions, e.g. a handle with degenerate support)
 //   k_gj_col     W_ik = A_ik D and V_kj = D A_kj for every i, j != k
@@ -28,53 +28,69 @@ __device__ __forceinline__ void load_tile(double (*s)[NB + 1], const double* __r
   }
 }
 
-// Value of `v` held by lane L (compile-time lane), broadcast to the wave.
-template <int L>
-__device__ __forceinline__ double lane_value(double v) {
-  const unsigned long long bits = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane(int(bits & 0xffffffffu), L);
-  const int hi = __builtin_amdgcn_readlane(int(bits >> 32), L);
-  return __longlong_as_double((static_cast<unsigned long long>(unsigned(hi)) << 32) | unsigned(lo));
-}
-
-// One Gauss-Jordan step with pivot P on the register-resident column `col`
-// of lane j; column P (owned by lane P) is broadcast with lane reads.  Steps
-// are instantiated recursively so that every index into `col` is a
-// compile-time constant and the column stays in registers.
-template <int P>
-__device__ __forceinline__ void gj_step(double (&col)[NB], const double* d0, int j, int* nreg) {
-  if constexpr (P < NB) {
-    double piv = lane_value<P>(col[P]);
-    if (!(piv > 1e-12 * d0[P]) || !isfinite(piv)) {
-      piv = d0[P] > 0 ? d0[P] : 1.0;
-      if (j == 0) atomicAdd(nreg, 1);
+// Gauss-Jordan inverse of tile (k,k) by one block of 256 threads: thread
+// (a, b) keeps the 4 x 4 sub-block of rows 4a.. and columns 4b.. in
+// registers.  At pivot P the owners of column P and of row P publish them in
+// LDS; every thread then updates its entries with the same operations per
+// entry as a column-by-column elimination.  A pivot below 1e-12 of the
+// original diagonal is replaced by that diagonal.
+__global__ void __launch_bounds__(256) k_gj_diag(int rp, int k, const double* __restrict__ A,
+                                                 double* __restrict__ Dk, const double* __restrict__ diag0,
+                                                 int* __restrict__ nreg) {
+  __shared__ double s_col[NB], s_row[NB], s_d0[NB];
+  const int t = threadIdx.x, a = t / 16, b = t % 16;
+  double m[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) m[u][v] = A[int64_t(k * NB + 4 * a + u) * rp + k * NB + 4 * b + v];
+  if (t < NB) s_d0[t] = diag0[k * NB + t];
+  for (int P = 0; P < NB; ++P) {
+    const int pq = P / 4, pr = P % 4;
+    if (b == pq)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        double v = m[u][0];
+#pragma unroll
+        for (int w = 1; w < 4; ++w)
+          if (pr == w) v = m[u][w];
+        s_col[4 * a + u] = v;
+      }
+    if (a == pq)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        double x = m[0][v];
+#pragma unroll
+        for (int w = 1; w < 4; ++w)
+          if (pr == w) x = m[w][v];
+        s_row[4 * b + v] = x;
+      }
+    __syncthreads();
+    double piv = s_col[P];
+    const double d0 = s_d0[P];
+    if (!(piv > 1e-12 * d0) || !isfinite(piv)) {
+      piv = d0 > 0 ? d0 : 1.0;
+      if (t == 0) atomicAdd(nreg, 1);
     }
     const double ip = 1.0 / piv;
-    const double rowp = (j == P) ? ip : col[P] * ip;  // new row P, my column
+    double fi[4], rowp[4];
 #pragma unroll
-    for (int i = 0; i < NB; ++i) {
-      if (i == P) continue;
-      const double fi = lane_value<P>(col[i]);
-      col[i] = (j == P) ? -fi * ip : col[i] - fi * rowp;
-    }
-    col[P] = rowp;
-    gj_step<P + 1>(col, d0, j, nreg);
+    for (int u = 0; u < 4; ++u) fi[u] = s_col[4 * a + u];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) rowp[v] = (4 * b + v == P) ? ip : s_row[4 * b + v] * ip;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 4 * a + u, j = 4 * b + v;
+        m[u][v] = (i == P) ? rowp[v] : ((j == P) ? -fi[u] * ip : m[u][v] - fi[u] * rowp[v]);
+      }
+    __syncthreads();
   }
-}
-
-// Gauss-Jordan inverse of tile (k,k) by one wave: lane j keeps column j in
-// registers and every lane updates its own column at each step.  A pivot
-// below 1e-12 of the original diagonal is replaced by that diagonal.
-__global__ void __launch_bounds__(64) k_gj_diag(int rp, int k, const double* __restrict__ A,
-                                                double* __restrict__ Dk, const double* __restrict__ diag0,
-                                                int* __restrict__ nreg) {
-  const int j = threadIdx.x;
-  double col[NB];
 #pragma unroll
-  for (int i = 0; i < NB; ++i) col[i] = A[int64_t(k * NB + i) * rp + k * NB + j];
-  gj_step<0>(col, diag0 + k * NB, j, nreg);
+  for (int u = 0; u < 4; ++u)
 #pragma unroll
-  for (int i = 0; i < NB; ++i) Dk[i * NB + j] = col[i];
+    for (int v = 0; v < 4; ++v) Dk[(4 * a + u) * NB + 4 * b + v] = m[u][v];
 }
 
 // 64 x 64 x 64 tile product from LDS: acc += A B (thread: 4 x 4 outputs).
@@ -206,7 +222,7 @@ ms_status coarse_factor(ms_ctx* c) {
   k_diag_max<<<1, 256, 0, c->stream>>>(r, c->d_Ac, c->d_diag0 + rp);
   k_pad_copy<<<256, 256, 0, c->stream>>>(r, rp, c->d_Ac, c->d_Ainv, c->d_diag0, c->d_diag0 + rp);
   for (int k = 0; k < nt; ++k) {
-    k_gj_diag<<<1, 64, 0, c->stream>>>(rp, k, c->d_Ainv, c->d_Linvd, c->d_diag0, c->d_nreg);
+    k_gj_diag<<<1, 256, 0, c->stream>>>(rp, k, c->d_Ainv, c->d_Linvd, c->d_diag0, c->d_nreg);
     if (nt > 1) {
       k_gj_col<<<dim3(unsigned(nt - 1), 2), 256, 0, c->stream>>>(rp, k, c->d_Ainv, c->d_Linvd, c->d_Y, c->d_Lc);
       k_gj_update<<<dim3(unsigned(nt - 1), unsigned(nt - 1)), 256, 0, c->stream>>>(rp, k, c->d_Ainv, c->d_Y);

@@ -101,18 +101,31 @@ ms_status plain_step(ms_ctx* c, double dt, const ms_solver_params& P, ms_step_st
   if ((s = read_scal(c))) return restore(c, s);
   const double xres = 1e-13 * std::sqrt(c->h_scal[S_DOT1]);
   bool endgame = false, converged = false, first = true, escalated = false;
-  double dnorm = 0.0, disp = 0.0, best = INFINITY;
-  int it = 0, stall = 0;
+  double dnorm = 0.0, disp = 0.0, moved = 0.0;
+  int it = 0;
   for (; it < P.max_newton; ++it) {
     const bool project = !(P.exact_endgame && endgame);
-    const bool refresh = it == 0 || escalated || (P.coarse_every > 0 && it % P.coarse_every == 0);
+    // the smoothed (deflation) form needs the Galerkin operator of the
+    // Hessian it is applied with; the additive form only needs an SPD one
+    bool refresh = it == 0 || escalated || pc == MS_PC_TWO_LEVEL;
+    if (P.coarse_move > 0.0)
+      refresh = refresh || moved > P.coarse_move * std::max(disp, P.abs_floor);
+    else
+      refresh = refresh || (P.coarse_every > 0 && it % P.coarse_every == 0);
+    if (refresh) {
+      moved = 0.0;
+      if (two_level(pc)) ++S.hessian_refreshes;
+    }
     escalated = false;
-    if ((s = assemble(c, c->d_x, h2, prec, project, true, pc, refresh))) return restore(c, s);
+    // mixed precision: the tight solves of the endgame use the FP64 Hessian
+    const int prec_it = (prec == MS_PREC_MIXED && endgame && P.mixed_endgame_fp64) ? MS_PREC_FP64 : prec;
+    if ((s = assemble(c, c->d_x, h2, prec_it, project, true, pc, refresh))) return restore(c, s);
     int iters = 0, code = 0;
-    if ((s = pcg_solve(c, prec, pc, P.pcg_eta_max, P.pcg_eta_min, first, P.max_pcg, &iters, &code, P.forcing)))
+    if ((s = pcg_solve(c, prec_it, pc, P.pcg_eta_max, P.pcg_eta_min, first, P.max_pcg, &iters, &code, P.forcing)))
       return restore(c, s);
     first = false;
     S.pcg_iters += iters;
+    if (prec_it == MS_PREC_FP64) S.pcg_iters_fp64 += iters;
     S.max_pcg_iters = std::max(S.max_pcg_iters, iters);
     if (!std::isfinite(c->h_scal[S_RHO0])) return restore(c, fail(c, MS_E_NONFINITE, "non-finite gradient"));
     if (code == 3 && !project) {  // indefinite exact Hessian: redo with the projection
@@ -139,6 +152,7 @@ ms_status plain_step(ms_ctx* c, double dt, const ms_solver_params& P, ms_step_st
     int nbt = 0;
     if ((s = line_search(c, h2, gd, P.max_backtracks, &alpha, &nbt))) return restore(c, s);
     launch_axpy(c, c->d_x, c->d_d, alpha, 3 * c->n);
+    moved += alpha * dnorm;
     S.backtracks += nbt;
     S.min_alpha = std::min(S.min_alpha, alpha);
     launch_dots(c, nullptr, nullptr, nullptr, nullptr, c->d_x, c->d_xt);
@@ -156,16 +170,12 @@ ms_status plain_step(ms_ctx* c, double dt, const ms_solver_params& P, ms_step_st
       break;
     }
     if (dnorm <= P.endgame_ratio * ref) endgame = true;
-    // Mixed precision: once the Newton step stops shrinking (the FP32
-    // Hessian limits the contraction on ill-conditioned systems), finish
-    // the step with the FP64 Hessian.
-    if (dnorm < 0.5 * best) {
-      best = dnorm;
-      stall = 0;
-    } else if (++stall >= 3 && prec == MS_PREC_MIXED) {
+    // Mixed precision: a timestep that has not converged after
+    // mixed_max_newton iterations (the FP32 Hessian can limit the
+    // contraction on ill-conditioned systems) is finished in FP64.
+    if (prec == MS_PREC_MIXED && P.mixed_max_newton > 0 && it + 1 >= P.mixed_max_newton) {
       prec = MS_PREC_FP64;
       escalated = true;
-      stall = 0;
       ++S.precision_escalations;
       if (c->verbose) std::fprintf(stderr, "[ms] it %d: continuing in FP64\n", it);
     }

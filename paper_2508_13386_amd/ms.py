@@ -38,13 +38,15 @@ class ms_solver_params(C.Structure):
                 ("warm_start", C.c_int32), ("paper_eps", C.c_double), ("subspace_rtol", C.c_double),
                 ("refine_iters", C.c_int32), ("lag_window", C.c_int32), ("lag_threshold", C.c_double),
                 ("lag_min_gap", C.c_int32), ("forcing", C.c_int32), ("endgame_ratio", C.c_double),
-                ("coarse_every", C.c_int32), ("predictor", C.c_int32), ("time_kernels", C.c_int32)]
+                ("coarse_every", C.c_int32), ("predictor", C.c_int32), ("time_kernels", C.c_int32),
+                ("coarse_move", C.c_double), ("mixed_max_newton", C.c_int32),
+                ("mixed_endgame_fp64", C.c_int32)]
 
 
 class ms_step_stats(C.Structure):
     _fields_ = [("newton_iters", C.c_int32), ("pcg_iters", C.c_int32), ("max_pcg_iters", C.c_int32),
                 ("backtracks", C.c_int32), ("hessian_refreshes", C.c_int32), ("warm_start_used", C.c_int32),
-                ("precision_escalations", C.c_int32), ("energy", C.c_double), ("last_dnorm", C.c_double), ("disp_norm", C.c_double),
+                ("precision_escalations", C.c_int32), ("pcg_iters_fp64", C.c_int32), ("energy", C.c_double), ("last_dnorm", C.c_double), ("disp_norm", C.c_double),
                 ("min_alpha", C.c_double), ("time_ms", C.c_double)]
 
     def asdict(self):

@@ -165,3 +165,38 @@ def test_two_level_steps_match_oracle(dev):
     # the material-aware coarse space cuts the PCG work on the stiff-inclusion block
     assert sum(its_tl) <= 1.05 * sum(its_bj)  # never worse on a coarse space this small
     c.close()
+
+
+@pytest.mark.parametrize("pc_name,opts", [
+    ("additive", dict(coarse_move=0.2)),
+    ("additive", dict(coarse_every=3)),
+    ("smoothed", dict(coarse_move=0.2)),
+    ("additive", dict(coarse_move=0.2, mixed_max_newton=1)),
+])
+def test_mixed_policies_match_oracle(dev, pc_name, opts):
+    """Mixed precision with the FP64 endgame, Eisenstat-Walker forcing and a
+    coarse operator that may lag the Hessian (additive form; the smoothed
+    form rebuilds it every iteration), and the forced FP64 continuation:
+    every step still lands on the oracle's minimiser."""
+    from paper_2508_13386_amd import ms
+    pc = ms.PC_TWO_LEVEL_ADDITIVE if pc_name == "additive" else ms.PC_TWO_LEVEL
+    s, c = _setup(dev, N=8, m=10)
+    body = fem.Body(s["rest"], s["tets"], s["E"], s["nu"], s["rho"])
+    x, v = s["x0"].copy(), s["v0"].copy()
+    for k in range(1, 4):
+        xo, vo, _ = newton.newton_step(body, x, v, s["dt"], s["gravity"], s["dirichlet"], s["dbc_targets"](k))
+        c.ms_set_dirichlet(s["dirichlet"], s["dbc_targets"](k))
+        c.ms_set_state(x, v)
+        st = c.ms_step(s["dt"], precision=ms.PREC_MIXED, preconditioner=pc, forcing=1, pcg_eta_max=0.1,
+                       mixed_endgame_fp64=1, **opts)
+        xg, _ = c.ms_get_state()
+        err = e_rel(xg, xo, x)
+        say("step", k, pc_name, opts, "e_rel", err, "pcg", st["pcg_iters"], "newton", st["newton_iters"],
+            "refreshes", st["hessian_refreshes"], "escalations", st["precision_escalations"])
+        assert err <= 1e-6
+        if opts.get("mixed_max_newton") == 1:
+            assert st["precision_escalations"] == (1 if st["newton_iters"] > 1 else 0)
+        else:
+            assert st["precision_escalations"] == 0
+        x, v = xo, vo
+    c.close()
