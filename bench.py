@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--coarse-every", type=int, default=1,
                     help="rebuild U^T H U and its inverse every this many Newton iterations (0: once per step)")
     ap.add_argument("--endgame-fp64", type=int, default=1, help="mixed precision: FP64 Hessian in the Newton endgame")
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip the per-step error check against tightly converged FP64 steps")
     ap.add_argument("--coarse-move", type=float, default=0.2,
                     help="> 0: rebuild U^T H U once the iterate has moved by this fraction of the step's "
                          "displacement since the last rebuild (replaces --coarse-every)")
@@ -101,8 +103,8 @@ def cpu_baseline():
 def measured_traffic(kernel_name):
     """HBM bytes per launch of the product kernel from the committed counter
     summary (FETCH_SIZE x copy factor + WRITE_SIZE x copy factor), or None
-    when the summary is missing, was taken for another kernel instance, or
-    the kernel source has changed since."""
+    when the summary is missing, holds no figure for this kernel instance,
+    or the kernel source has changed since the counters were taken."""
     import hashlib
     try:
         text = open(TRAFFIC_PROFILE).read()
@@ -112,12 +114,12 @@ def measured_traffic(kernel_name):
     for line in text.splitlines():
         if line.startswith("- ") and ": " in line:
             k, v = line[2:].split(": ", 1)
-            fields[k.strip()] = v.strip().strip("`")
+            fields[k.strip().strip("`")] = v.strip().strip("`")
     src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
-    if fields.get("kernel_source_sha256") != src or fields.get("kernel") != kernel_name:
+    if fields.get("kernel_source_sha256") != src:
         return None
     try:
-        return float(fields["traffic_bytes_per_launch"])
+        return float(fields["traffic_bytes_per_launch " + kernel_name])
     except (KeyError, ValueError):
         return None
 
@@ -195,6 +197,36 @@ def run(dev, s, params, warmup, steps, basis=None, handles=0, timed=True, oversa
     return steps / elapsed, elapsed, stats, states, ctx, basis_s
 
 
+def step_errors(dev, s, ctx, params, warmup, steps):
+    """Per-step error of the benchmarked form: the timed steps are replayed
+    (deterministic, untimed) from the same start, and each one is compared
+    with a tightly converged FP64 step (block-Jacobi PCG, ||d|| <= 1e-11
+    ||x - x^t||, no a-posteriori stop) taken from the same state:
+    e_rel = ||x_form - x_tight|| / ||x_tight - x^t||."""
+    from paper_2508_13386_amd import ms
+    tight = ms.context_from_scene(dev, s)
+    tparams = ms.solver_defaults(precision=ms.PREC_FP64, preconditioner=ms.PC_BLOCK_JACOBI, forcing=0,
+                                 newton_tol=1e-11, max_newton=100)
+    ctx.ms_set_state(s["x0"], s["v0"])
+    errs = []
+    for k in range(1, warmup + steps + 1):
+        ctx.ms_set_dirichlet(s["dirichlet"], s["dbc_targets"](k))
+        x0, v0 = ctx.ms_get_state()
+        ctx.ms_step(s["dt"], params)
+        x1, _ = ctx.ms_get_state()
+        if k <= warmup:
+            continue
+        tight.ms_set_dirichlet(s["dirichlet"], s["dbc_targets"](k))
+        tight.ms_set_state(x0, v0)
+        tight.ms_step(s["dt"], tparams)
+        xt, _ = tight.ms_get_state()
+        errs.append(float(np.linalg.norm(x1 - xt) / np.linalg.norm(xt - x0)))
+    tight.close()
+    return {"check": "each timed step vs the same step solved by FP64 block-Jacobi Newton-PCG to "
+                     "||d|| <= 1e-11 ||x - x^t|| from the same state", "e_rel_per_step": errs,
+            "e_rel_max": max(errs), "bound": 1e-6}
+
+
 def batch_main(a):
     """64 uneven scenes (cubes / ellipsoids, 1e3-5e4 tets each, E log-uniform
     in [1e5, 1e9], bottom layer pinned, gravity) advanced by ms_batch_step;
@@ -244,6 +276,7 @@ def batch_main(a):
         "solver": {"max_newton_iters": [max(st["newton_iters"] for st in step) for step in stats],
                    "max_pcg_iters": [max(st["pcg_iters"] for st in step) for step in stats]},
         "reference_form": ref,
+        "accuracy": accuracy,
     }
     print(json.dumps(out), flush=True)
 
@@ -430,11 +463,12 @@ def main():
     # one more timestep (outside the timed region) runs with every product
     # launch bracketed by HIP events on the library's stream, inside the real
     # PCG loop; the average over those launches is the kernel's duration.
-    # These are the last product launches of the run (a profile can pick
-    # them out as the kernel's last timed_step_pcg_iters + timed_step_solves
-    # dispatches).  In mixed precision with the FP64 endgame both product
-    # instantiations run; the one that ran more PCG iterations in the timed
-    # region is reported.
+    # These are the last product launches of the run.  In mixed precision
+    # with the FP64 endgame both product instantiations run; the one that
+    # ran more PCG iterations in the timed region is reported (a profile
+    # picks its event-timed launches out as its last timed_step_pcg_iters_fp64
+    # + timed_step_solves_fp64 dispatches for the FP64 instantiation, and the
+    # remaining iterations and solves for the FP32 one).
     fp64_share = sum(st["pcg_iters_fp64"] for st in stats) / max(1, sum(st["pcg_iters"] for st in stats))
     kprec = ms.PREC_FP64 if fp64_share >= 0.5 else ms.PREC_MIXED
     # the kernel replayed back to back on the last Hessian (hot caches)
@@ -455,6 +489,7 @@ def main():
     S = next(c for c in (16, 32, 64) if -(-n // c) == nslices)
     kernel_name = f"k_cg_spmv<{'double' if vb == 8 else 'float'}, {S}>"
     achieved = k_bytes / (k_us * 1e-6) / 1e9
+    accuracy = None if a.no_accuracy else step_errors(dev, s, ctx, params, a.warmup, a.steps)
     ctx.close()
 
     ref = None
@@ -496,6 +531,7 @@ def main():
                      "bytes_per_launch": k_bytes, "avg_launch_us": k_us,
                      "timed_step_pcg_iters": int(tstat["pcg_iters"]),
                      "timed_step_pcg_iters_fp64": int(tstat["pcg_iters_fp64"]),
+                     "timed_step_solves_fp64": int(tstat["pcg_solves_fp64"]),
                      "fp64_share_of_pcg_iters": fp64_share,
                      "timed_step_solves": int(tstat["newton_iters"]),
                      "replay_avg_launch_us": r_us,
@@ -507,6 +543,7 @@ def main():
                    "precision_escalations": [st["precision_escalations"] for st in stats],
                    "basis_build_s": basis_s},
         "reference_form": ref,
+        "accuracy": accuracy,
     }
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()

@@ -138,6 +138,7 @@ typedef struct {
   int32_t precision_escalations; /* mixed precision: 1 if the step was continued in FP64
                                     after mixed_max_newton iterations                    */
   int32_t pcg_iters_fp64;     /* plain mode: PCG iterations run with the FP64 Hessian     */
+  int32_t pcg_solves_fp64;    /* plain mode: PCG solves run with the FP64 Hessian         */
   double energy;              /* E at x^{t+1}                                            */
   double last_dnorm;          /* ||d||_2 of the last Newton step                         */
   double disp_norm;           /* ||x^{t+1} - x^t||_2                                     */

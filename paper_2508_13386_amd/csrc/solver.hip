@@ -125,7 +125,10 @@ ms_status plain_step(ms_ctx* c, double dt, const ms_solver_params& P, ms_step_st
       return restore(c, s);
     first = false;
     S.pcg_iters += iters;
-    if (prec_it == MS_PREC_FP64) S.pcg_iters_fp64 += iters;
+    if (prec_it == MS_PREC_FP64) {
+      S.pcg_iters_fp64 += iters;
+      ++S.pcg_solves_fp64;
+    }
     S.max_pcg_iters = std::max(S.max_pcg_iters, iters);
     if (!std::isfinite(c->h_scal[S_RHO0])) return restore(c, fail(c, MS_E_NONFINITE, "non-finite gradient"));
     if (code == 3 && !project) {  // indefinite exact Hessian: redo with the projection

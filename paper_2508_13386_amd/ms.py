@@ -46,7 +46,8 @@ class ms_solver_params(C.Structure):
 class ms_step_stats(C.Structure):
     _fields_ = [("newton_iters", C.c_int32), ("pcg_iters", C.c_int32), ("max_pcg_iters", C.c_int32),
                 ("backtracks", C.c_int32), ("hessian_refreshes", C.c_int32), ("warm_start_used", C.c_int32),
-                ("precision_escalations", C.c_int32), ("pcg_iters_fp64", C.c_int32), ("energy", C.c_double), ("last_dnorm", C.c_double), ("disp_norm", C.c_double),
+                ("precision_escalations", C.c_int32), ("pcg_iters_fp64", C.c_int32),
+                ("pcg_solves_fp64", C.c_int32), ("energy", C.c_double), ("last_dnorm", C.c_double), ("disp_norm", C.c_double),
                 ("min_alpha", C.c_double), ("time_ms", C.c_double)]
 
     def asdict(self):

@@ -176,7 +176,7 @@ def test_two_level_steps_match_oracle(dev):
 def test_mixed_policies_match_oracle(dev, pc_name, opts):
     """Mixed precision with the FP64 endgame, Eisenstat-Walker forcing and a
     coarse operator that may lag the Hessian (additive form; the smoothed
-    form rebuilds it every iteration), and the forced FP64 continuation:
+    form rebuilds it every iteration) and the forced FP64 continuation:
     every step still lands on the oracle's minimiser."""
     from paper_2508_13386_amd import ms
     pc = ms.PC_TWO_LEVEL_ADDITIVE if pc_name == "additive" else ms.PC_TWO_LEVEL
