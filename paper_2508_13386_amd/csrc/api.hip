@@ -109,6 +109,16 @@ static void destroy_graphs(ms_ctx* c) {
       }
 }
 
+void set_coarse_f32(ms_ctx* c, bool on) {
+  if (c->coarse_f32 == on) return;
+  for (auto& g : c->cg_graph[MS_PREC_FP64])
+    if (g) {
+      (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
+  c->coarse_f32 = on;
+}
+
 // Runs PCG on H d = -g with the Hessian and preconditioner already built.
 // Returns the device "done" code in *code (1 converged, 2 iteration cap,
 // 3 loss of positive definiteness).
@@ -469,6 +479,7 @@ ms_status ms_apply_preconditioner(ms_ctx* c, int32_t kind, int32_t prec, const d
   if (!c || !r || !z) return MS_E_ARG;
   if (!c->eval_valid) return fail(c, MS_E_ORDER, "call ms_eval first");
   if (prec != c->eval_prec) return fail(c, MS_E_ARG, "precision differs from the last ms_eval");
+  set_coarse_f32(c, false);
   if (kind < 0 || kind > 2) return fail(c, MS_E_ARG, "bad preconditioner kind");
   if (two_level(kind) && !c->has_basis) return fail(c, MS_E_ORDER, "no basis");
   const int64_t n3 = 3 * c->n;

@@ -106,7 +106,7 @@ __global__ void __launch_bounds__(256) k_restrict(const int4* __restrict__ chunk
 // pieces of each lane's share of the row are loaded before the flag test
 // and the formation of c, so their latency overlaps both.
 constexpr int kGemvRows = 8;
-constexpr int kGemvPre = 8;
+constexpr int kGemvPre = 10;
 template <typename AT>
 __global__ void __launch_bounds__(64 * kGemvRows) k_coarse_gemv(int r, int ld, const AT* __restrict__ A,
                                                       const int2* __restrict__ hinfo,
@@ -631,12 +631,13 @@ ms_status launch_galerkin(ms_ctx* c, int prec) {
   return MS_OK;
 }
 
-// e = A^-1 c in the precision of the mode (FP32 inverse in mixed precision).
+// e = A^-1 c with the FP32 inverse in mixed-precision steps (also in their
+// FP64 iterations), else the FP64 inverse.
 void launch_coarse_gemv(ms_ctx* c, int prec, const double* scal) {
   Basis& D = c->basis;
   const unsigned nb = nblocks(c->r, kGemvRows);
   const size_t lds = size_t(c->r) * sizeof(double);
-  if (prec == MS_PREC_MIXED)
+  if (prec == MS_PREC_MIXED || c->coarse_f32)
     k_coarse_gemv<float><<<nb, 64 * kGemvRows, lds, c->stream>>>(c->r, c->rp, c->d_Ainv32, D.d_hinfo, D.d_rpart,
                                                                  c->d_e, scal);
   else

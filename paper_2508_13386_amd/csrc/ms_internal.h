@@ -153,6 +153,10 @@ struct ms_ctx {
   int nblk_vert = 0;          // blocks of the per-vertex kernels
   // graphs of fixed-size PCG chunks (per precision x preconditioner)
   hipGraphExec_t cg_graph[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
+  // mixed-precision steps: the PCG iterations that run with the FP64
+  // Hessian also apply the FP32 coarse inverse (the FP64 graphs are captured
+  // under the current value; set_coarse_f32 drops them when it changes)
+  bool coarse_f32 = false;
   int cg_chunk = 16;
   bool use_graphs = true;
   bool own_stream = false;
@@ -287,8 +291,7 @@ constexpr int kUpdBlock = 256;  // vertices per PCG update block
 void launch_coarse_gemv(ms_ctx* c, int prec, const double* scal);
 void launch_prolong_add(ms_ctx* c, double* target, const double* scal);
 void launch_diag_barrier(ms_ctx* c, int prec, void* vals, const double* x, double h2, double sign);
-ms_status pcg_solve(ms_ctx* c, int prec, int pc, double eta_max, double eta_min, bool first, int max_it, int* iters,
-                    int* code, int forcing);
+void set_coarse_f32(ms_ctx* c, bool on);
 void launch_restrict(ms_ctx* c, const double* v, const double* weight, const double* scal);
 void launch_cg_update(ms_ctx* c, int prec, int parity);
 void destroy_batch(ms_ctx* c);
