@@ -47,6 +47,7 @@ def parse():
     ap.add_argument("--pc", choices=["jacobi", "two_level", "additive"], default="additive")
     ap.add_argument("--handles", type=int, default=192)
     ap.add_argument("--oversample", type=float, default=1.0, help="k-means++ seed oversampling of the basis build")
+    ap.add_argument("--lattice", type=int, default=0, help="1: basis seeds on a fixed lattice (no pruning)")
     ap.add_argument("--eta-max", type=float, default=0.1, help="largest PCG forcing term (Eisenstat-Walker)")
     ap.add_argument("--coarse-every", type=int, default=1,
                     help="rebuild U^T H U and its inverse every this many Newton iterations (0: once per step)")
@@ -56,10 +57,11 @@ def parse():
     ap.add_argument("--coarse-move", type=float, default=0.2,
                     help="> 0: rebuild U^T H U once the iterate has moved by this fraction of the step's "
                          "displacement since the last rebuild (replaces --coarse-every)")
-    ap.add_argument("--workload", choices=["block32", "batch64", "learned", "spmv_sweep"], default="block32",
+    ap.add_argument("--workload", choices=["block32", "batch64", "learned", "spmv_sweep", "paper"], default="block32",
                     help="block32: the heterogeneous block (default); batch64: 64 uneven scenes stepped together; "
                          "learned: train the coarse warm start on trajectories and evaluate it on held-out seeds; "
-                         "spmv_sweep: the PCG product kernel on the heterogeneous block at --sweep grid sizes")
+                         "spmv_sweep: the PCG product kernel on the heterogeneous block at --sweep grid sizes; "
+                         "paper: the paper's three-level step (Alg. 1/2) and its error against the exact step")
     ap.add_argument("--sweep", default="32,64,96,128", help="grid sizes of the spmv_sweep workload")
     ap.add_argument("--train-seeds", type=int, default=40)
     ap.add_argument("--eval-seeds", type=int, default=6)
@@ -167,7 +169,7 @@ def copy_probe(mib):
     print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n, "copies": 5}), flush=True)
 
 
-def run(dev, s, params, warmup, steps, basis=None, handles=0, timed=True, oversample=1.0):
+def run(dev, s, params, warmup, steps, basis=None, handles=0, timed=True, oversample=1.0, lattice=0):
     """Runs warmup + steps timesteps; returns (timesteps/s, per-step stats,
     states after each timed step, context, basis seconds)."""
     import torch
@@ -177,7 +179,7 @@ def run(dev, s, params, warmup, steps, basis=None, handles=0, timed=True, oversa
     basis_s = None
     if handles:
         t0 = time.perf_counter()
-        ctx.ms_build_basis(n_handles=handles, oversample=oversample)
+        ctx.ms_build_basis(n_handles=handles, oversample=oversample, lattice_seeding=lattice)
         basis_s = time.perf_counter() - t0
     stats, states = [], []
     for k in range(1, warmup + 1):
@@ -389,6 +391,78 @@ def learned_main(a):
     print(json.dumps(out), flush=True)
 
 
+def paper_main(a):
+    """The paper's three-level timestep (affine and sparse subspace levels,
+    lagged-Hessian refinement, subspace-decrement stop) on the heterogeneous
+    block and on the contact scene.  Each timed step starts from the paper
+    trajectory's state; from the same state the exact step (plain mixed
+    two-level Newton-PCG to the plain-path tolerance) is solved untimed, and
+    the difference is reported as the paper measures it (per-vertex
+    displacement difference over the bounding-box diagonal) and as e_rel."""
+    import torch
+
+    import scenes
+    from paper_2508_13386_amd import ms
+    dev = ms.TorchDevice(0)
+    prec = ms.PREC_MIXED if a.precision == "mixed" else ms.PREC_FP64
+    exact = ms.solver_defaults(precision=prec, preconditioner=ms.PC_TWO_LEVEL_ADDITIVE, forcing=1,
+                               pcg_eta_max=a.eta_max, coarse_move=a.coarse_move, mixed_endgame_fp64=a.endgame_fp64)
+    pparams = ms.solver_defaults(mode=ms.MODE_PAPER, precision=prec, refine_iters=0, max_newton=100)
+    cases = [("cube %d^3, per-tet E log-uniform in [1e5, 1e8], bottom pinned, gravity" % a.grid,
+              scenes.plain_cube(a.grid, seed=0, steps=a.warmup + a.steps), a.handles),
+             ("gyroid-lattice sphere at 32^3 falling onto a rigid half-space",
+              scenes.gyroid_sphere(res=32), a.handles),
+             ("heterogeneous block %d^3, 20 inclusions E=1e10 in E=1e5" % a.grid,
+              scenes.inclusion_block(a.grid, seed=0, steps=a.warmup + a.steps), a.handles)]
+    for name, s, m in cases:
+        c = ms.context_from_scene(dev, s)
+        c.ms_build_basis(n_handles=m, oversample=a.oversample)
+        bbox = float(np.linalg.norm(s["rest"].max(axis=0) - s["rest"].min(axis=0)))
+        times, etimes, errs, ebox, iters = [], [], [], [], []
+        failure = None
+        x, v = s["x0"].copy(), s["v0"].copy()
+        for k in range(1, a.warmup + a.steps + 1):
+            if len(s["dirichlet"]):
+                c.ms_set_dirichlet(s["dirichlet"], s["dbc_targets"](k))
+            c.ms_set_state(x, v)
+            dev.stream.synchronize()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            try:
+                st = c.ms_step(s["dt"], pparams)
+            except ms.MSError as e:
+                failure = f"step {k}: {e}"
+                break
+            dev.stream.synchronize()
+            t1 = time.perf_counter()
+            xp, vp = c.ms_get_state()
+            c.ms_set_state(x, v)
+            dev.stream.synchronize()
+            t2 = time.perf_counter()
+            c.ms_step(s["dt"], exact)
+            dev.stream.synchronize()
+            t3 = time.perf_counter()
+            xe, _ = c.ms_get_state()
+            if k > a.warmup:
+                times.append(t1 - t0)
+                etimes.append(t3 - t2)
+                errs.append(float(np.linalg.norm(xp - xe) / np.linalg.norm(xe - x)))
+                ebox.append(float(np.linalg.norm(xp - xe, axis=1).max() / bbox))
+                iters.append((st["newton_iters"], st["pcg_iters"]))
+            x, v = xp, vp
+        c.close()
+        print(json.dumps({"workload": "paper", "scene": name, "n_verts": len(s["rest"]), "n_tets": len(s["tets"]),
+                          "handles": m, "precision": a.precision,
+                          "timesteps_per_s": len(times) / sum(times) if times else None,
+                          "ms_per_step": 1e3 * sum(times) / len(times) if times else None, "steps": len(times),
+                          "failure": failure,
+                          "exact_step_timesteps_per_s": len(etimes) / sum(etimes) if etimes else None,
+                          "newton_and_pcg_iters": iters, "e_rel_vs_exact_per_step": errs,
+                          "max_vertex_error_over_bbox_per_step": ebox,
+                          "note": "error of the paper's approximate step against the exact minimiser from the "
+                                  "same state (the paper reports about 1e-2)"}), flush=True)
+
+
 def spmv_sweep_main(a):
     """The PCG product kernel (k_cg_spmv, fused with its dot partials) on the
     Hessian of the heterogeneous block at growing grid sizes: one Newton
@@ -445,6 +519,9 @@ def main():
     if a.workload == "spmv_sweep":
         spmv_sweep_main(a)
         return
+    if a.workload == "paper":
+        paper_main(a)
+        return
     import scenes
     from paper_2508_13386_amd import ms
 
@@ -458,7 +535,7 @@ def main():
                                 mixed_endgame_fp64=a.endgame_fp64)
     value, elapsed, stats, states, ctx, basis_s = run(dev, s, params, a.warmup, a.steps,
                                                       handles=a.handles if pc != ms.PC_BLOCK_JACOBI else 0,
-                                                      oversample=a.oversample)
+                                                      oversample=a.oversample, lattice=a.lattice)
     # roofline of the dominant kernel, the PCG product fused with its dots:
     # one more timestep (outside the timed region) runs with every product
     # launch bracketed by HIP events on the library's stream, inside the real
