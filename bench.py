@@ -74,6 +74,7 @@ def parse():
                     help="only summarise a rocprofv3 kernel_trace.csv: per kernel, the mean duration over all "
                          "dispatches and over those that did work (longer than --work-us)")
     ap.add_argument("--work-us", type=float, default=4.0)
+    ap.add_argument("--by-grid", action="store_true", help="with --trace-summary: split kernels by grid size")
     ap.add_argument("--tail", nargs=2, metavar=("NAME", "N"),
                     help="with --trace-summary: also split the dispatches of kernels whose name contains NAME "
                          "into their last N and the rest")
@@ -126,16 +127,19 @@ def measured_traffic(kernel_name):
         return None
 
 
-def trace_summary(path, work_us, tail=None):
-    """Per-kernel dispatch statistics of a rocprofv3 kernel trace.  Kernels of
-    the PCG loop that start after the solve has converged return at once;
-    'working' dispatches are those longer than work_us."""
+def trace_summary(path, work_us, tail=None, by_grid=False):
+    """Per-kernel dispatch statistics of a rocprofv3 kernel trace (per kernel
+    and grid size with by_grid).  Kernels of the PCG loop that start after
+    the solve has converged return at once; 'working' dispatches are those
+    longer than work_us."""
     import csv
     acc = {}
     with open(path) as f:
         for row in csv.DictReader(f):
             d = (int(row["End_Timestamp"]) - int(row["Start_Timestamp"])) * 1e-3
-            a = acc.setdefault(row["Kernel_Name"], [0, 0.0, 0, 0.0])
+            grid = row.get("Grid_Size", row.get("Grid_Size_X", "?"))
+            key = row["Kernel_Name"][:90] + (f" grid {grid}" if by_grid else "")
+            a = acc.setdefault(key, [0, 0.0, 0, 0.0])
             a[0] += 1
             a[1] += d
             if d > work_us:
@@ -143,7 +147,7 @@ def trace_summary(path, work_us, tail=None):
                 a[3] += d
     rows = sorted(acc.items(), key=lambda kv: -kv[1][1])
     for name, (n, tot, nw, totw) in rows[:25]:
-        print(json.dumps({"kernel": name[:90], "dispatches": n, "mean_us": tot / n, "working": nw,
+        print(json.dumps({"kernel": name, "dispatches": n, "mean_us": tot / n, "working": nw,
                           "working_mean_us": (totw / nw) if nw else None, "total_ms": tot * 1e-3}))
     if tail:
         key, last = tail[0], int(tail[1])
@@ -508,7 +512,7 @@ def main():
         copy_probe(a.copy_probe)
         return
     if a.trace_summary:
-        trace_summary(a.trace_summary, a.work_us, a.tail)
+        trace_summary(a.trace_summary, a.work_us, a.tail, a.by_grid)
         return
     if a.workload == "batch64":
         batch_main(a)
