@@ -44,7 +44,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--grid", type=int, default=32)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="mixed")
-    ap.add_argument("--pc", choices=["jacobi", "two_level", "additive"], default="additive")
+    ap.add_argument("--pc", choices=["jacobi", "two_level", "additive", "vcycle"], default="additive")
     ap.add_argument("--handles", type=int, default=192)
     ap.add_argument("--oversample", type=float, default=1.0, help="k-means++ seed oversampling of the basis build")
     ap.add_argument("--lattice", type=int, default=0, help="1: basis seeds on a fixed lattice (no pruning)")
@@ -532,7 +532,8 @@ def main():
     s = scenes.inclusion_block(a.grid, seed=0, steps=a.warmup + a.steps)
     x_start = s["x0"]
     dev = ms.TorchDevice(0)
-    pc = {"jacobi": ms.PC_BLOCK_JACOBI, "two_level": ms.PC_TWO_LEVEL, "additive": ms.PC_TWO_LEVEL_ADDITIVE}[a.pc]
+    pc = {"jacobi": ms.PC_BLOCK_JACOBI, "two_level": ms.PC_TWO_LEVEL, "additive": ms.PC_TWO_LEVEL_ADDITIVE,
+          "vcycle": ms.PC_TWO_LEVEL_VCYCLE}[a.pc]
     prec = ms.PREC_MIXED if a.precision == "mixed" else ms.PREC_FP64
     params = ms.solver_defaults(precision=prec, preconditioner=pc, forcing=1, pcg_eta_max=a.eta_max,
                                 coarse_every=a.coarse_every, coarse_move=a.coarse_move,

@@ -71,8 +71,19 @@ typedef enum { MS_PREC_FP64 = 0, MS_PREC_MIXED = 1 } ms_precision;
  *                              correction; PCG starts from d_0 = Q(-g), which
  *                              makes the iteration a deflated / balancing
  *                              two-level method)
- *   MS_PC_TWO_LEVEL_ADDITIVE   z = S r + Q r */
-typedef enum { MS_PC_BLOCK_JACOBI = 0, MS_PC_TWO_LEVEL = 1, MS_PC_TWO_LEVEL_ADDITIVE = 2 } ms_preconditioner;
+ *   MS_PC_TWO_LEVEL_ADDITIVE   z = S r + Q r
+ *   MS_PC_TWO_LEVEL_VCYCLE     symmetric V(1,1): z1 = L r, z2 = z1 + Q (r - H z1),
+ *                              z = z2 + L (r - H z2), with L the l1-scaled 3x3
+ *                              block-Jacobi inverse (diagonal block of H plus, on
+ *                              its diagonal, the absolute row sums of the row's
+ *                              other blocks at free vertices), which keeps the
+ *                              V-cycle SPD for any SPD coarse matrix */
+typedef enum {
+  MS_PC_BLOCK_JACOBI = 0,
+  MS_PC_TWO_LEVEL = 1,
+  MS_PC_TWO_LEVEL_ADDITIVE = 2,
+  MS_PC_TWO_LEVEL_VCYCLE = 3
+} ms_preconditioner;
 typedef enum { MS_MODE_PLAIN = 0, MS_MODE_PAPER = 1 } ms_mode;
 
 /* Parameters of one timestep solve.  ms_solver_defaults() fills them. */
@@ -106,17 +117,18 @@ typedef struct {
   int32_t forcing;         /* 0: eta = sqrt(||g||/||g_0||); 1: Eisenstat-Walker choice 2,
                               eta_k = 0.9 (||g_k||/||g_k-1||)^2 with safeguard          */
   double endgame_ratio;    /* exact (unprojected) Hessian once ||d|| <= ratio * ||x - x^t|| */
-  int32_t coarse_every;    /* additive two-level: rebuild U^T H U and its factor at the
-                              first Newton iteration of a step and then every coarse_every
-                              iterations (0: once per step; the preconditioner may lag
-                              H).  The smoothed form rebuilds at every iteration.       */
+  int32_t coarse_every;    /* additive and V-cycle two-level: rebuild U^T H U and its
+                              factor at the first Newton iteration of a step and then
+                              every coarse_every iterations (0: once per step; the
+                              preconditioner may lag H).  The smoothed form rebuilds
+                              at every iteration.                                      */
   int32_t predictor;       /* initial Newton iterate: 0 x^t; 1 the inertial predictor
                               x^t + h v^t (truncated by the contact filter, Dirichlet
                               vertices at their targets), kept only if it lowers E     */
   int32_t time_kernels;    /* 1: bracket every PCG product launch of this step with HIP
                               events (PCG runs without graphs); ms_time_kernel with
                               reps = 0 then reports their average duration             */
-  double coarse_move;      /* > 0, additive two-level: after the first Newton iteration,
+  double coarse_move;      /* > 0, additive / V-cycle: after the first Newton iteration,
                               rebuild U^T H U and its factor only once the iterate has
                               moved by more than coarse_move * max(||x - x^t||,
                               abs_floor) since the last rebuild (replaces coarse_every) */

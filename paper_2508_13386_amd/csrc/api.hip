@@ -181,7 +181,10 @@ ms_status assemble(ms_ctx* c, const double* x, double h2, int prec, bool project
   launch_gather_grad(c, x, h2, c->d_g);
   launch_gather_hess(c, x, h2, prec);
   if (need_pc) {
-    launch_block_jacobi(c, prec);
+    if (pc == MS_PC_TWO_LEVEL_VCYCLE)
+      launch_block_jacobi_l1(c, prec);
+    else
+      launch_block_jacobi(c, prec);
     if (two_level(pc) && (refresh_coarse || !c->coarse_valid)) {
       ms_status s = launch_galerkin(c, prec);
       if (s) return s;
@@ -480,14 +483,18 @@ ms_status ms_apply_preconditioner(ms_ctx* c, int32_t kind, int32_t prec, const d
   if (!c->eval_valid) return fail(c, MS_E_ORDER, "call ms_eval first");
   if (prec != c->eval_prec) return fail(c, MS_E_ARG, "precision differs from the last ms_eval");
   set_coarse_f32(c, false);
-  if (kind < 0 || kind > 2) return fail(c, MS_E_ARG, "bad preconditioner kind");
+  if (kind < 0 || kind > 3) return fail(c, MS_E_ARG, "bad preconditioner kind");
   if (two_level(kind) && !c->has_basis) return fail(c, MS_E_ORDER, "no basis");
   const int64_t n3 = 3 * c->n;
   std::vector<double> mr(r, r + n3);
   for (auto& v : mr) v = -v;
   MS_HIP(hipMemcpyAsync(c->d_g, mr.data(), n3 * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  // the V-cycle smooths with the l1-scaled inverses; ms_eval left the plain
+  // block-Jacobi ones, restored afterwards
+  if (kind == MS_PC_TWO_LEVEL_VCYCLE) launch_block_jacobi_l1(c, prec);
   launch_cg_init(c, prec, 0.0, 0.0, true, 0, 0);
   launch_precond_apply(c, prec, kind);
+  if (kind == MS_PC_TWO_LEVEL_VCYCLE) launch_block_jacobi(c, prec);
   MS_HIP(hipMemcpyAsync(z, c->d_u, n3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   return sync(c);
 }

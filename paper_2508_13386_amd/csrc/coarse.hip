@@ -605,7 +605,7 @@ ms_status install_basis(ms_ctx* c, Basis&& B) {
   c->has_basis = true;
   c->coarse_valid = 0;
   for (auto& row : c->cg_graph)
-    for (int pc = 1; pc < 3; ++pc)
+    for (int pc = 1; pc < 4; ++pc)
       if (row[pc]) {
         (void)hipGraphExecDestroy(row[pc]);
         row[pc] = nullptr;
@@ -672,6 +672,11 @@ void launch_precond_apply(ms_ctx* c, int prec, int pc) {
   } else if (pc == MS_PC_TWO_LEVEL) {
     launch_spmv_resid(c, prec, false);  // w = r - H u
     launch_coarse_correction(c, prec, true);
+  } else if (pc == MS_PC_TWO_LEVEL_VCYCLE) {  // u = L r on entry
+    launch_spmv_resid(c, prec, false);        // w = r - H u
+    launch_coarse_correction(c, prec, true);  // u += Q w
+    launch_spmv_resid(c, prec, false);        // w = r - H u
+    launch_bj_add(c, prec);                   // u += L w
   }
 }
 

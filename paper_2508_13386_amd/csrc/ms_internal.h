@@ -152,7 +152,7 @@ struct ms_ctx {
   unsigned* d_counter = nullptr;
   int nblk_vert = 0;          // blocks of the per-vertex kernels
   // graphs of fixed-size PCG chunks (per precision x preconditioner)
-  hipGraphExec_t cg_graph[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
+  hipGraphExec_t cg_graph[2][4] = {{nullptr, nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr, nullptr}};
   // mixed-precision steps: the PCG iterations that run with the FP64
   // Hessian also apply the FP32 coarse inverse (the FP64 graphs are captured
   // under the current value; set_coarse_f32 drops them when it changes)
@@ -286,12 +286,16 @@ void launch_coarse_start(ms_ctx* c, int prec);
 void launch_spmv_resid(ms_ctx* c, int prec, bool from_d);
 void launch_bj(ms_ctx* c, int prec);
 void launch_prolong_set_d(ms_ctx* c);
-inline bool two_level(int pc) { return pc == MS_PC_TWO_LEVEL || pc == MS_PC_TWO_LEVEL_ADDITIVE; }
+inline bool two_level(int pc) {
+  return pc == MS_PC_TWO_LEVEL || pc == MS_PC_TWO_LEVEL_ADDITIVE || pc == MS_PC_TWO_LEVEL_VCYCLE;
+}
 constexpr int kUpdBlock = 256;  // vertices per PCG update block
 void launch_coarse_gemv(ms_ctx* c, int prec, const double* scal);
 void launch_prolong_add(ms_ctx* c, double* target, const double* scal);
 void launch_diag_barrier(ms_ctx* c, int prec, void* vals, const double* x, double h2, double sign);
 void set_coarse_f32(ms_ctx* c, bool on);
+void launch_block_jacobi_l1(ms_ctx* c, int prec);
+void launch_bj_add(ms_ctx* c, int prec);
 void launch_restrict(ms_ctx* c, const double* v, const double* weight, const double* scal);
 void launch_cg_update(ms_ctx* c, int prec, int parity);
 void destroy_batch(ms_ctx* c);

@@ -84,7 +84,7 @@ ms_status plain_step(ms_ctx* c, double dt, const ms_solver_params& P, ms_step_st
   const double h2 = dt * dt;
   int prec = P.precision == MS_PREC_MIXED ? MS_PREC_MIXED : MS_PREC_FP64;
   set_coarse_f32(c, prec == MS_PREC_MIXED);
-  const int pc = (P.preconditioner >= 0 && P.preconditioner <= 2) ? P.preconditioner : MS_PC_BLOCK_JACOBI;
+  const int pc = (P.preconditioner >= 0 && P.preconditioner <= 3) ? P.preconditioner : MS_PC_BLOCK_JACOBI;
   if (two_level(pc) && !c->has_basis) return fail(c, MS_E_ORDER, "two-level preconditioner needs a basis");
   launch_predict(c, dt);
   launch_apply_dbc(c, int64_t(c->h_dbc.size()));

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libms.so")
 MS_OK, MS_E_ARG, MS_E_MESH, MS_E_ORDER, MS_E_DEVICE, MS_E_NOMEM, MS_E_NOCONV, MS_E_LINESEARCH, MS_E_NONFINITE = \
     0, -1, -2, -3, -4, -5, -6, -7, -8
 PREC_FP64, PREC_MIXED = 0, 1
-PC_BLOCK_JACOBI, PC_TWO_LEVEL, PC_TWO_LEVEL_ADDITIVE = 0, 1, 2
+PC_BLOCK_JACOBI, PC_TWO_LEVEL, PC_TWO_LEVEL_ADDITIVE, PC_TWO_LEVEL_VCYCLE = 0, 1, 2, 3
 MODE_PLAIN, MODE_PAPER = 0, 1
 
 _ALLOC = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)

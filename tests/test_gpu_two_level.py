@@ -84,6 +84,40 @@ def test_two_level_apply_matches_dense(dev):
     zref = Sr + Q(t)
     z = c.ms_apply_preconditioner(ms.PC_TWO_LEVEL, r)
     assert np.abs(z - zref).max() <= 1e-9 * np.abs(zref).max()
+    # symmetric V(1,1) with the l1-scaled block-Jacobi smoother L:
+    # z1 = L r, z2 = z1 + Q (r - H z1), z = z2 + L (r - H z2)
+    V = np.asarray(Hb, dtype=np.float64).reshape(-1, 3, 3)
+    L = np.zeros((len(x), 3, 3))
+    for i in range(len(x)):
+        if pinned[i]:
+            continue
+        D, l1 = None, np.zeros(3)
+        for k in range(rp[i], rp[i + 1]):
+            if col[k] == i:
+                D = V[k].copy()
+            elif not pinned[col[k]]:
+                l1 += np.abs(V[k]).sum(axis=1)
+        L[i] = np.linalg.inv(D + np.diag(l1))
+    Hm = lambda y: linops.bsr_matvec(rp, col, Hb, y)
+
+    def vcycle(v):
+        z1 = np.einsum("vij,vj->vi", L, v)
+        t1 = v - Hm(z1)
+        t1[pinned] = 0.0
+        z2 = z1 + Q(t1)
+        t2 = v - Hm(z2)
+        t2[pinned] = 0.0
+        return z2 + np.einsum("vij,vj->vi", L, t2)
+
+    zv = c.ms_apply_preconditioner(ms.PC_TWO_LEVEL_VCYCLE, r)
+    zref = vcycle(r)
+    assert np.abs(zv - zref).max() <= 1e-9 * np.abs(zref).max()
+    zv2 = c.ms_apply_preconditioner(ms.PC_TWO_LEVEL_VCYCLE, r2)
+    assert abs((zv * r2).sum() - (zv2 * r).sum()) <= 1e-10 * abs((zv * r2).sum())
+    assert (zv * r).sum() > 0
+    # the plain block-Jacobi inverses are back after a V-cycle application
+    zbj = c.ms_apply_preconditioner(ms.PC_BLOCK_JACOBI, r)
+    assert np.abs(zbj - Sr).max() <= 1e-12 * np.abs(Sr).max()
     c.close()
 
 
@@ -153,7 +187,8 @@ def test_two_level_steps_match_oracle(dev):
     for k in range(1, 4):
         xo, vo, _ = newton.newton_step(body, x, v, s["dt"], s["gravity"], s["dirichlet"], s["dbc_targets"](k))
         c.ms_set_dirichlet(s["dirichlet"], s["dbc_targets"](k))
-        for pc, its in ((ms.PC_TWO_LEVEL, its_tl), (ms.PC_TWO_LEVEL_ADDITIVE, []), (ms.PC_BLOCK_JACOBI, its_bj)):
+        for pc, its in ((ms.PC_TWO_LEVEL, its_tl), (ms.PC_TWO_LEVEL_ADDITIVE, []), (ms.PC_TWO_LEVEL_VCYCLE, []),
+                        (ms.PC_BLOCK_JACOBI, its_bj)):
             c.ms_set_state(x, v)
             st = c.ms_step(s["dt"], preconditioner=pc)
             xg, _ = c.ms_get_state()
@@ -172,6 +207,7 @@ def test_two_level_steps_match_oracle(dev):
     ("additive", dict(coarse_every=3)),
     ("smoothed", dict(coarse_move=0.2)),
     ("additive", dict(coarse_move=0.2, mixed_max_newton=1)),
+    ("vcycle", dict(coarse_move=0.2)),
 ])
 def test_mixed_policies_match_oracle(dev, pc_name, opts):
     """Mixed precision with the FP64 endgame, Eisenstat-Walker forcing and a
@@ -179,7 +215,8 @@ def test_mixed_policies_match_oracle(dev, pc_name, opts):
     form rebuilds it every iteration) and the forced FP64 continuation:
     every step still lands on the oracle's minimiser."""
     from paper_2508_13386_amd import ms
-    pc = ms.PC_TWO_LEVEL_ADDITIVE if pc_name == "additive" else ms.PC_TWO_LEVEL
+    pc = {"additive": ms.PC_TWO_LEVEL_ADDITIVE, "smoothed": ms.PC_TWO_LEVEL,
+          "vcycle": ms.PC_TWO_LEVEL_VCYCLE}[pc_name]
     s, c = _setup(dev, N=8, m=10)
     body = fem.Body(s["rest"], s["tets"], s["E"], s["nu"], s["rho"])
     x, v = s["x0"].copy(), s["v0"].copy()
