@@ -43,6 +43,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=8)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--grid", type=int, default=32)
+    ap.add_argument("--scene", choices=["block", "gyroid"], default="block",
+                    help="block: the heterogeneous block (--grid); gyroid: the contact scene, a gyroid-lattice "
+                         "sphere voxelized at --grid^3 falling at 5 m/s onto a rigid half-space")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="mixed")
     ap.add_argument("--pc", choices=["jacobi", "two_level", "additive", "vcycle"], default="additive")
     ap.add_argument("--handles", type=int, default=192)
@@ -83,31 +86,37 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline():
-    """The CPU oracle (FP64 Newton + SuperLU) on a bounded sample: one
-    timestep of the same generator at 16^3 (24,576 tets), one thread."""
+def cpu_baseline(scene="block", grid=32, n_tets=None):
+    """The CPU oracle (FP64 Newton + SuperLU, half-space barrier and CCD
+    filter for the contact scene) on a bounded sample: one timestep of the
+    same generator at a lower resolution (half the grid; 3/8 of it for the
+    contact scene, whose oracle step is costlier), one thread, scaled to the
+    workload by its tet count (linear scaling: a lower bound on the oracle's
+    cost, whose sparse solve grows faster)."""
     from threadpoolctl import threadpool_limits
 
     import scenes
     from oracle import fem, newton
-    s = scenes.inclusion_block(16, seed=0, steps=1)
+    g = max(4, (3 * grid) // 8 if scene == "gyroid" else grid // 2)
+    s = scenes.gyroid_sphere(res=g) if scene == "gyroid" else scenes.inclusion_block(g, seed=0, steps=1)
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
         body = fem.Body(s["rest"], s["tets"], s["E"], s["nu"], s["rho"])
-        newton.newton_step(body, s["x0"], s["v0"], s["dt"], s["gravity"], s["dirichlet"], s["dbc_targets"](1))
+        newton.newton_step(body, s["x0"], s["v0"], s["dt"], s["gravity"], s["dirichlet"], s["dbc_targets"](1),
+                           halfspace=s["halfspace"])
         dt = time.perf_counter() - t0
-    # scaled to the 32^3 workload by its 8x tet count (linear scaling: a
-    # lower bound on the oracle's cost, whose sparse solve grows faster)
-    return dict(value=1.0 / (dt * 8.0), unit="timesteps/s", cores=1, kind="oracle",
-                sample=f"one timestep of the same generator at 16^3 (24,576 tets) took {dt:.1f} s on 1 thread; "
-                       f"value = 1/(8 x that), linear tet-count scaling to the 32^3 workload")
+    ratio = (n_tets or 8 * len(s["tets"])) / len(s["tets"])
+    return dict(value=1.0 / (dt * ratio), unit="timesteps/s", cores=1, kind="oracle",
+                sample=f"one timestep of the same generator at {g}^3 ({len(s['tets']):,} tets) took {dt:.1f} s on "
+                       f"1 thread; value = 1/({ratio:.2f} x that), linear tet-count scaling to the workload")
 
 
-def measured_traffic(kernel_name):
+def measured_traffic(kernel_name, workload):
     """HBM bytes per launch of the product kernel from the committed counter
     summary (FETCH_SIZE x copy factor + WRITE_SIZE x copy factor), or None
-    when the summary is missing, holds no figure for this kernel instance,
-    or the kernel source has changed since the counters were taken."""
+    when the summary is missing, was taken on another workload, holds no
+    figure for this kernel instance, or the kernel source has changed since
+    the counters were taken."""
     import hashlib
     try:
         text = open(TRAFFIC_PROFILE).read()
@@ -119,7 +128,7 @@ def measured_traffic(kernel_name):
             k, v = line[2:].split(": ", 1)
             fields[k.strip().strip("`")] = v.strip().strip("`")
     src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
-    if fields.get("kernel_source_sha256") != src:
+    if fields.get("kernel_source_sha256") != src or fields.get("workload") != workload:
         return None
     try:
         return float(fields["traffic_bytes_per_launch " + kernel_name])
@@ -529,7 +538,14 @@ def main():
     import scenes
     from paper_2508_13386_amd import ms
 
-    s = scenes.inclusion_block(a.grid, seed=0, steps=a.warmup + a.steps)
+    if a.scene == "gyroid":
+        s = scenes.gyroid_sphere(res=a.grid)
+        wname = (f"gyroid-lattice sphere voxelized at {a.grid}^3 (E=1e7, nu=0.45) falling at 5 m/s onto a rigid "
+                 f"half-space, IPC barrier d_hat=1e-3, dt=1/100")
+    else:
+        s = scenes.inclusion_block(a.grid, seed=0, steps=a.warmup + a.steps)
+        wname = (f"heterogeneous block {a.grid}^3 hexes x 6 tets, 20 inclusions E=1e10 in E=1e5, "
+                 f"nu=0.49, top driven 0.1 m over 10 steps, dt=1/60")
     x_start = s["x0"]
     dev = ms.TorchDevice(0)
     pc = {"jacobi": ms.PC_BLOCK_JACOBI, "two_level": ms.PC_TWO_LEVEL, "additive": ms.PC_TWO_LEVEL_ADDITIVE,
@@ -600,15 +616,14 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if a.precision == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"heterogeneous block {a.grid}^3 hexes x 6 tets, 20 inclusions E=1e10 in E=1e5, "
-                               f"nu=0.49, top driven 0.1 m over 10 steps, dt=1/60",
+        "config": {"workload": wname,
                    "n_verts": int(len(s["rest"])), "n_tets": int(len(s["tets"])),
                    "precision": a.precision, "preconditioner": a.pc,
                    "handles": a.handles if pc != ms.PC_BLOCK_JACOBI else None, "pcg_eta_max": a.eta_max,
                    "coarse_every": a.coarse_every, "coarse_move": a.coarse_move, "endgame_fp64": a.endgame_fp64,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kernel_name),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kernel_name, f"{a.scene}{a.grid}"),
                      "kernel": kernel_name + " (PCG product w = H u fused with its three dots, sliced BSR3)",
                      "bytes_per_launch": k_bytes, "avg_launch_us": k_us,
                      "timed_step_pcg_iters": int(tstat["pcg_iters"]),
@@ -628,7 +643,7 @@ def main():
         "accuracy": accuracy,
     }
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline()
+        out["cpu_baseline"] = cpu_baseline(a.scene, a.grid, len(s["tets"]))
     print(json.dumps(out), flush=True)
 
 
