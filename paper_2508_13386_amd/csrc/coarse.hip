@@ -102,10 +102,10 @@ __global__ void __launch_bounds__(256) k_restrict(const int4* __restrict__ chunk
 // mixed precision; leading dimension ld a multiple of 4, rows readable up to
 // ld) with c given by the restriction partials: every block first forms c in
 // LDS (c_(12 i + q) = sum of handle i's partials q, in chunk order), then one
-// wave per row, 8 rows per 512-thread block.  The first kGemvPre 16-byte
+// wave per row, 16 rows per 1024-thread block.  The first kGemvPre 16-byte
 // pieces of each lane's share of the row are loaded before the flag test
 // and the formation of c, so their latency overlaps both.
-constexpr int kGemvRows = 8;
+constexpr int kGemvRows = 16;
 constexpr int kGemvPre = 10;
 template <typename AT>
 __global__ void __launch_bounds__(64 * kGemvRows) k_coarse_gemv(int r, int ld, const AT* __restrict__ A,
