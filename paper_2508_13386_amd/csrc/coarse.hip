@@ -34,16 +34,19 @@ __global__ void k_sub(int64_t len, const double* __restrict__ a, const double* _
   if (i < len) out[i] = a[i] - b[i];
 }
 
-// Restriction partials of c = U^T (weight .* v).  One block of 256 threads
-// per chunk of at most kRChunk entries of one handle's vertex list (entries
-// in handle order: vertex hv[e] and weights hw[e] = W_vi, so the weight
-// loads are contiguous); each thread takes four entries with every load
-// issued before any is used (clamped index, zero scale past the chunk end).
+// Restriction partials of c = U^T (weight .* v).  One block of kRThreads
+// threads per chunk of at most kRChunk entries of one handle's vertex list
+// (entries in handle order: vertex hv[e] and weights hw[e] = W_vi, so the
+// weight loads are contiguous); each thread takes kREnt entries with every
+// load issued before any is used (clamped index, zero scale past the chunk
+// end).
 // The chunk's 12 sums are reduced in a fixed order and stored as a partial;
 // the coarse GEMV adds a handle's partials in chunk order (no inter-block
 // communication, hence no device-scope fences).
 constexpr int kRChunk = 1024;
-__global__ void __launch_bounds__(256) k_restrict(const int4* __restrict__ chunk_info, const int32_t* __restrict__ hv,
+constexpr int kRThreads = 64;
+constexpr int kREnt = kRChunk / kRThreads;
+__global__ void __launch_bounds__(kRThreads) k_restrict(const int4* __restrict__ chunk_info, const int32_t* __restrict__ hv,
                                                   const double* __restrict__ hw, const double* __restrict__ v,
                                                   const double* __restrict__ weight, double* __restrict__ part,
                                                   const double* __restrict__ scal) {
@@ -51,11 +54,11 @@ __global__ void __launch_bounds__(256) k_restrict(const int4* __restrict__ chunk
   const int4 info = chunk_info[ch];  // {handle, first entry, end entry, unused}
   const double done = scal ? scal[S_DONE] : 0.0;
   const int e0 = info.y, e1 = info.z;
-  int vv[4];
-  double w[4][4], sc[4];
+  int vv[kREnt];
+  double w[kREnt][4], sc[kREnt];
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int e = e0 + t + 256 * u;
+  for (int u = 0; u < kREnt; ++u) {
+    const int e = e0 + t + kRThreads * u;
     const bool ok = e < e1;
     const int ec = ok ? e : 0;
     vv[u] = hv[ec];
@@ -68,19 +71,19 @@ __global__ void __launch_bounds__(256) k_restrict(const int4* __restrict__ chunk
     sc[u] = ok ? 1.0 : 0.0;
   }
   if (done != 0.0) return;  // the flag is the same for the whole grid
-  double rv[4][3];
+  double rv[kREnt][3];
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
+  for (int u = 0; u < kREnt; ++u)
 #pragma unroll
     for (int a = 0; a < 3; ++a) rv[u][a] = v[3 * int64_t(vv[u]) + a];
   if (weight)
 #pragma unroll
-    for (int u = 0; u < 4; ++u) sc[u] *= weight[vv[u]];
+    for (int u = 0; u < kREnt; ++u) sc[u] *= weight[vv[u]];
   double acc[12];
 #pragma unroll
   for (int q = 0; q < 12; ++q) acc[q] = 0.0;
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
+  for (int u = 0; u < kREnt; ++u)
 #pragma unroll
     for (int l = 0; l < 4; ++l) {
       const double wl = sc[u] * w[u][l];
@@ -654,7 +657,7 @@ void launch_prolong_add(ms_ctx* c, double* target, const double* scal) {
 // Restriction partials of U^T (weight .* v) into d_rpart.
 void launch_restrict(ms_ctx* c, const double* v, const double* weight, const double* scal) {
   Basis& D = c->basis;
-  k_restrict<<<unsigned(D.nrchunks), 256, 0, c->stream>>>(D.d_chunk_info, D.d_hv, D.d_hw, v, weight, D.d_rpart,
+  k_restrict<<<unsigned(D.nrchunks), kRThreads, 0, c->stream>>>(D.d_chunk_info, D.d_hv, D.d_hw, v, weight, D.d_rpart,
                                                           scal);
 }
 
