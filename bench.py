@@ -66,6 +66,8 @@ def parse():
                          "spmv_sweep: the PCG product kernel on the heterogeneous block at --sweep grid sizes; "
                          "paper: the paper's three-level step (Alg. 1/2) and its error against the exact step")
     ap.add_argument("--sweep", default="32,64,96,128", help="grid sizes of the spmv_sweep workload")
+    ap.add_argument("--order", choices=["natural", "random", "rcm"], default="natural",
+                    help="vertex numbering of the spmv_sweep meshes")
     ap.add_argument("--train-seeds", type=int, default=40)
     ap.add_argument("--eval-seeds", type=int, default=6)
     ap.add_argument("--traj-grid", type=int, default=16)
@@ -190,7 +192,9 @@ def run(dev, s, params, warmup, steps, basis=None, handles=0, timed=True, oversa
     from paper_2508_13386_amd import ms
     ctx = ms.context_from_scene(dev, s)
     basis_s = None
-    if handles:
+    if basis is not None:
+        ctx.ms_set_basis(basis["origins"], basis["vptr"], basis["vhandle"], basis["vphi"])
+    elif handles:
         t0 = time.perf_counter()
         ctx.ms_build_basis(n_handles=handles, oversample=oversample, lattice_seeding=lattice)
         basis_s = time.perf_counter() - t0
@@ -489,6 +493,8 @@ def spmv_sweep_main(a):
     for res in [int(v) for v in a.sweep.split(",") if v]:
         t0 = time.perf_counter()
         s = scenes.inclusion_block(res, seed=0, steps=1)
+        if a.order != "natural":
+            s = scenes.permute_vertices(s, scenes.vertex_order(s["rest"], s["tets"], a.order, seed=1))
         gen_s = time.perf_counter() - t0
         ctx = ms.context_from_scene(dev, s)
         ctx.ms_set_dirichlet(s["dirichlet"], s["dbc_targets"](1))
@@ -503,7 +509,7 @@ def spmv_sweep_main(a):
                     raise
             us, nbytes = ctx.ms_time_kernel(0, prec, reps)
             gbs = nbytes / us * 1e-3
-            print(json.dumps({"workload": "spmv_sweep", "grid": res, "vertices": len(s["rest"]),
+            print(json.dumps({"workload": "spmv_sweep", "grid": res, "order": a.order, "vertices": len(s["rest"]),
                               "tets": len(s["tets"]), "storage": name, "kernel": "k_cg_spmv",
                               "algorithmic_bytes": nbytes, "avg_launch_us": us, "launches": reps,
                               "achieved_GBs": gbs, "frac_of_8TBs": gbs / HBM_PEAK_GBS,
@@ -588,6 +594,7 @@ def main():
     kernel_name = f"k_cg_spmv<{'double' if vb == 8 else 'float'}, {S}>"
     achieved = k_bytes / (k_us * 1e-6) / 1e9
     accuracy = None if a.no_accuracy else step_errors(dev, s, ctx, params, a.warmup, a.steps)
+    basis = ctx.ms_get_basis() if pc != ms.PC_BLOCK_JACOBI else None
     ctx.close()
 
     ref = None
@@ -602,6 +609,18 @@ def main():
                "speedup": value / rv, "e_rel_final_state_vs_this_form": e_rel,
                "pcg_iters": [st["pcg_iters"] for st in rstats],
                "newton_iters": [st["newton_iters"] for st in rstats]}
+        if basis is not None and prec == ms.PREC_MIXED:
+            # the same preconditioner and policy in FP64 throughout, on the
+            # same basis: isolates what the mixed-precision form gains
+            p64 = ms.solver_defaults(precision=ms.PREC_FP64, preconditioner=pc, forcing=1, pcg_eta_max=a.eta_max,
+                                     coarse_every=a.coarse_every, coarse_move=a.coarse_move)
+            fv, _, fstats, fstates, fctx, _ = run(dev, s, p64, a.warmup, a.steps, basis=basis)
+            fctx.close()
+            ref["fp64_same_preconditioner"] = {
+                "value": fv, "speedup_of_mixed": value / fv,
+                "e_rel_final_state_vs_this_form": float(np.linalg.norm(xg - fstates[-1]) /
+                                                        np.linalg.norm(fstates[-1] - x_start)),
+                "pcg_iters": [st["pcg_iters"] for st in fstats]}
 
     out = {
         "metric": METRIC,

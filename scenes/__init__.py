@@ -291,3 +291,40 @@ def minibatch_order(n_samples: int, batch: int, n_steps: int, seed: int = 0):
     while len(idx) < n_steps * batch:
         idx.extend(rng.permutation(n_samples).tolist())
     return np.asarray(idx[:n_steps * batch], dtype=np.int32).reshape(n_steps, batch)
+
+
+def vertex_order(rest: np.ndarray, tets: np.ndarray, kind: str, seed: int = 0) -> np.ndarray:
+    """A vertex numbering for SpMV measurements: 'natural' (the generator's),
+    'random' (a seeded permutation, the unstructured-mesh stand-in) or 'rcm'
+    (reverse Cuthill-McKee on the tet edge graph).  Returns perm with new
+    vertex i = old vertex perm[i]."""
+    n = len(rest)
+    if kind == "natural":
+        return np.arange(n)
+    if kind == "random":
+        return np.random.default_rng(seed).permutation(n)
+    if kind == "rcm":
+        import scipy.sparse as sp
+        from scipy.sparse.csgraph import reverse_cuthill_mckee
+        a = tets[:, [0, 0, 0, 1, 1, 2]].ravel()
+        b = tets[:, [1, 2, 3, 2, 3, 3]].ravel()
+        A = sp.coo_matrix((np.ones(len(a)), (a, b)), shape=(n, n))
+        A = (A + A.T).tocsr()
+        return np.asarray(reverse_cuthill_mckee(A, symmetric_mode=True))
+    raise ValueError(kind)
+
+
+def permute_vertices(s: dict, perm: np.ndarray) -> dict:
+    """The same scene with its vertices renumbered (new vertex i = old vertex
+    perm[i]); Dirichlet targets keep the order of the Dirichlet list."""
+    perm = np.asarray(perm)
+    inv = np.empty_like(perm)
+    inv[perm] = np.arange(len(perm))
+    out = dict(s)
+    out["rest"] = s["rest"][perm]
+    out["x0"] = s["x0"][perm]
+    out["v0"] = s["v0"][perm]
+    out["tets"] = inv[s["tets"]].astype(np.int32)
+    out["dirichlet"] = inv[s["dirichlet"]].astype(np.int32)
+    return out
+

@@ -57,3 +57,14 @@ def test_batch_sizes():
     for s in bs:
         assert (_signed_vol(s["rest"], s["tets"]) > 0).all()
         assert len(s["dirichlet"]) >= 3
+
+
+@pytest.mark.parametrize("kind", ["random", "rcm"])
+def test_vertex_renumbering_keeps_the_mesh(kind):
+    s = scenes.inclusion_block(6, seed=2, steps=1)
+    perm = scenes.vertex_order(s["rest"], s["tets"], kind, seed=1)
+    assert sorted(perm.tolist()) == list(range(len(s["rest"])))
+    t = scenes.permute_vertices(s, perm)
+    assert np.array_equal(t["rest"][t["tets"]], s["rest"][s["tets"]])
+    assert np.array_equal(t["rest"][t["dirichlet"]], s["rest"][s["dirichlet"]])
+    assert np.array_equal(t["dbc_targets"](3), s["dbc_targets"](3))
