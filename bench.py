@@ -314,18 +314,20 @@ def learned_main(a):
     dev = ms.TorchDevice(0)
     prec = ms.PREC_MIXED if a.precision == "mixed" else ms.PREC_FP64
     base = dict(precision=prec, preconditioner=ms.PC_TWO_LEVEL_ADDITIVE, forcing=1, pcg_eta_max=a.eta_max,
-                max_newton=100)
+                max_newton=100, coarse_move=a.coarse_move, mixed_endgame_fp64=a.endgame_fp64)
+    plain64 = dict(precision=ms.PREC_FP64, preconditioner=ms.PC_BLOCK_JACOBI, forcing=1, pcg_eta_max=a.eta_max,
+                   max_newton=100)
 
-    def trajectory(seed, warm=None):
+    def trajectory(seed, warm=None, form=None):
         """Coarse states, step stats and states of one trajectory, or None if
         a step fails to converge (reported and left out)."""
         try:
-            return _trajectory(seed, warm)
+            return _trajectory(seed, warm, form or base)
         except ms.MSError as e:
             print(f"trajectory seed {seed} warm {warm is not None}: {e}", file=sys.stderr, flush=True)
             return None
 
-    def _trajectory(seed, warm=None):
+    def _trajectory(seed, warm, form):
         sc = scenes.learned_trajectory_scene(seed, N=a.traj_grid, steps=a.traj_steps)
         c = ms.context_from_scene(dev, sc)
         try:
@@ -337,7 +339,7 @@ def learned_main(a):
             stats, xs = [], []
             for k in range(1, a.traj_steps + 1):
                 c.ms_set_dirichlet(sc["dirichlet"], sc["dbc_targets"](k))
-                stats.append(c.ms_step(sc["dt"], ms.solver_defaults(warm_start=1 if warm else 0, **base)))
+                stats.append(c.ms_step(sc["dt"], ms.solver_defaults(warm_start=1 if warm else 0, **form)))
                 qs.append(c.ms_get_coarse(r))
                 xs.append(c.ms_get_state()[0])
         finally:
@@ -374,19 +376,24 @@ def learned_main(a):
     warm = (params, mean, std, oscale)
     rows, skipped = [], []
     for sd in scenes.HELDOUT_SEEDS[:a.eval_seeds]:
-        t0_, t1_ = trajectory(sd), trajectory(sd, warm)
-        if t0_ is None or t1_ is None:
-            skipped.append(dict(seed=sd, base_failed=t0_ is None, warm_failed=t1_ is None))
+        t0_, t1_, t2_ = trajectory(sd), trajectory(sd, warm), trajectory(sd, form=plain64)
+        if t0_ is None or t1_ is None or t2_ is None:
+            skipped.append(dict(seed=sd, base_failed=t0_ is None, warm_failed=t1_ is None, plain_failed=t2_ is None))
             continue
         _, s0, x0, _ = t0_
         _, s1, x1, _ = t1_
+        _, s2, x2, _ = t2_
         e = max(float(np.linalg.norm(p - q) / max(np.linalg.norm(p), 1e-300)) for p, q in zip(x0, x1))
+        e2 = max(float(np.linalg.norm(p - q) / max(np.linalg.norm(p), 1e-300)) for p, q in zip(x2, x1))
         rows.append(dict(seed=sd, newton=[sum(st["newton_iters"] for st in s0), sum(st["newton_iters"] for st in s1)],
                          pcg=[sum(st["pcg_iters"] for st in s0), sum(st["pcg_iters"] for st in s1)],
                          ms=[sum(st["time_ms"] for st in s0), sum(st["time_ms"] for st in s1)],
-                         used=sum(st["warm_start_used"] for st in s1), max_state_rel_diff=e))
+                         plain_fp64_ms=sum(st["time_ms"] for st in s2),
+                         used=sum(st["warm_start_used"] for st in s1), max_state_rel_diff=e,
+                         max_state_rel_diff_vs_plain_fp64=e2))
     t_base = sum(rw["ms"][0] for rw in rows)
     t_warm = sum(rw["ms"][1] for rw in rows)
+    t_plain = sum(rw["plain_fp64_ms"] for rw in rows)
     out = {
         "metric": "held-out timesteps/s with the learned coarse warm start",
         "value": 1e3 * a.traj_steps * len(rows) / t_warm, "unit": "timesteps/s", "n_gpus": 1,
@@ -401,6 +408,9 @@ def learned_main(a):
         "reference_form": {"form": "same held-out steps without the warm start (inertial predictor)",
                            "value": 1e3 * a.traj_steps * len(rows) / t_base, "unit": "timesteps/s",
                            "speedup": t_base / t_warm},
+        "plain_fp64_form": {"form": "same held-out steps, plain FP64 Newton-PCG with 3x3 block-Jacobi",
+                            "value": 1e3 * a.traj_steps * len(rows) / t_plain, "unit": "timesteps/s",
+                            "speedup_of_learned_mixed": t_plain / t_warm},
         "per_seed": rows,
         "skipped": skipped,
         "train_trajectories_failed": a.train_seeds - len(train),

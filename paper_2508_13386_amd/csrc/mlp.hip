@@ -315,24 +315,36 @@ ms_status warm_start(ms_ctx* c, double dt, bool inertial, int32_t* used) {
     double err;
     return energy_delta(c, c->d_x, c->d_d, *alpha, h2, dE, &err);
   };
-  // candidates: the inertial predictor (if on) and the learned start; the
-  // lower-energy one is taken if it lowers E
-  double dE_i = INFINITY, a_i = 0.0, dE_l, a_l;
+  // candidates: the inertial predictor x~ (if on) and x~ + beta U dq for
+  // beta = 1, 1/2, 1/4 (from x^t without the predictor); the lowest-energy
+  // one is taken if it lowers E
+  const size_t nb = 3 * c->n * sizeof(double);
+  double best = INFINITY, best_a = 0.0, best_beta = -1.0;
   if (inertial) {
     launch_predictor_dir(c);  // x~ - x, zero on pinned vertices
+    double dE_i, a_i;
     if ((s = candidate(&dE_i, &a_i))) return s;
-    MS_HIP(hipMemcpyAsync(c->d_p, c->d_d, 3 * c->n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-    launch_prolong_add(c, c->d_d, nullptr);  // + U dq (zero on pinned vertices)
+    if (std::isfinite(dE_i) && dE_i < 0.0) best = dE_i, best_a = a_i, best_beta = 0.0;
+    MS_HIP(hipMemcpyAsync(c->d_p, c->d_d, nb, hipMemcpyDeviceToDevice, c->stream));
   } else {
-    launch_prolong_set_d(c);  // U dq
+    launch_fill(c, c->d_p, 0.0, 3 * c->n);
   }
-  if ((s = candidate(&dE_l, &a_l))) return s;
-  if (std::isfinite(dE_l) && dE_l < 0.0 && !(dE_i <= dE_l)) {
-    launch_axpy(c, c->d_x, c->d_d, a_l, 3 * c->n);
+  launch_prolong_set_d(c);  // U dq (zero on pinned vertices), kept in w
+  MS_HIP(hipMemcpyAsync(c->d_w, c->d_d, nb, hipMemcpyDeviceToDevice, c->stream));
+  for (const double beta : {1.0, 0.5, 0.25}) {
+    MS_HIP(hipMemcpyAsync(c->d_d, c->d_p, nb, hipMemcpyDeviceToDevice, c->stream));
+    launch_axpy(c, c->d_d, c->d_w, beta, 3 * c->n);
+    double dE_l, a_l;
+    if ((s = candidate(&dE_l, &a_l))) return s;
+    if (std::isfinite(dE_l) && dE_l < 0.0 && dE_l < best) best = dE_l, best_a = a_l, best_beta = beta;
+  }
+  if (best_beta < 0.0) return MS_OK;  // no candidate lowers E: start at x^t
+  MS_HIP(hipMemcpyAsync(c->d_d, c->d_p, nb, hipMemcpyDeviceToDevice, c->stream));
+  if (best_beta > 0.0) {
+    launch_axpy(c, c->d_d, c->d_w, best_beta, 3 * c->n);
     *used = 1;
-  } else if (std::isfinite(dE_i) && dE_i < 0.0) {
-    launch_axpy(c, c->d_x, c->d_p, a_i, 3 * c->n);
   }
+  launch_axpy(c, c->d_x, c->d_d, best_a, 3 * c->n);
   return MS_OK;
 }
 
