@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--coarse-every", type=int, default=1,
                     help="rebuild U^T H U and its inverse every this many Newton iterations (0: once per step)")
     ap.add_argument("--endgame-fp64", type=int, default=1, help="mixed precision: FP64 Hessian in the Newton endgame")
+    ap.add_argument("--endgame-ratio", type=float, default=1e-3,
+                    help="endgame once ||d|| <= ratio * ||x - x^t|| (exact Hessian; FP64 with --endgame-fp64)")
     ap.add_argument("--no-accuracy", action="store_true",
                     help="skip the per-step error check against tightly converged FP64 steps")
     ap.add_argument("--coarse-move", type=float, default=0.2,
@@ -569,7 +571,7 @@ def main():
     prec = ms.PREC_MIXED if a.precision == "mixed" else ms.PREC_FP64
     params = ms.solver_defaults(precision=prec, preconditioner=pc, forcing=1, pcg_eta_max=a.eta_max,
                                 coarse_every=a.coarse_every, coarse_move=a.coarse_move,
-                                mixed_endgame_fp64=a.endgame_fp64)
+                                mixed_endgame_fp64=a.endgame_fp64, endgame_ratio=a.endgame_ratio)
     value, elapsed, stats, states, ctx, basis_s = run(dev, s, params, a.warmup, a.steps,
                                                       handles=a.handles if pc != ms.PC_BLOCK_JACOBI else 0,
                                                       oversample=a.oversample, lattice=a.lattice)
@@ -591,7 +593,7 @@ def main():
     ctx.ms_set_dirichlet(s["dirichlet"], s["dbc_targets"](k))
     tparams = ms.solver_defaults(precision=prec, preconditioner=pc, forcing=1, pcg_eta_max=a.eta_max,
                                  coarse_every=a.coarse_every, coarse_move=a.coarse_move,
-                                 mixed_endgame_fp64=a.endgame_fp64, time_kernels=1)
+                                 mixed_endgame_fp64=a.endgame_fp64, endgame_ratio=a.endgame_ratio, time_kernels=1)
     tstat = ctx.ms_step(s["dt"], tparams)
     k_us, k_bytes = ctx.ms_time_kernel(0, kprec, 0)
     # slice height of the chosen layout, from the byte count of the product
@@ -650,6 +652,7 @@ def main():
                    "precision": a.precision, "preconditioner": a.pc,
                    "handles": a.handles if pc != ms.PC_BLOCK_JACOBI else None, "pcg_eta_max": a.eta_max,
                    "coarse_every": a.coarse_every, "coarse_move": a.coarse_move, "endgame_fp64": a.endgame_fp64,
+                   "endgame_ratio": a.endgame_ratio,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kernel_name, f"{a.scene}{a.grid}"),
