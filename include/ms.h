@@ -353,7 +353,8 @@ ms_status ms_time_kernel(ms_ctx* c, int32_t kernel, int32_t prec, int32_t reps, 
 /* ---- standalone sliced-BSR3 matrix for SpMV measurements ----------------
  * A block-sparse matrix with 3x3 blocks given in BSR form (host row_ptr
  * [n+1], col [nnzb], vals [nnzb][3][3] doubles) is converted into the
- * library's device layout (64-row slices, component-major planes) in FP64
+ * library's device layout (slices of 16, 32 or 64 rows: MS_SLICE, else the
+ * fastest on this pattern; component-major planes) in FP64
  * (dtype 0) or FP32 (dtype 1).  ms_mat_spmv computes y = A x for DEVICE
  * vectors x, y of 3n elements of that dtype on the matrix's stream. */
 typedef struct ms_mat ms_mat;
