@@ -52,6 +52,7 @@ def parse():
     ap.add_argument("--oversample", type=float, default=1.0, help="k-means++ seed oversampling of the basis build")
     ap.add_argument("--lattice", type=int, default=0, help="1: basis seeds on a fixed lattice (no pruning)")
     ap.add_argument("--eta-max", type=float, default=0.1, help="largest PCG forcing term (Eisenstat-Walker)")
+    ap.add_argument("--eta-min", type=float, default=1e-4, help="smallest PCG forcing term")
     ap.add_argument("--coarse-every", type=int, default=1,
                     help="rebuild U^T H U and its inverse every this many Newton iterations (0: once per step)")
     ap.add_argument("--endgame-fp64", type=int, default=1, help="mixed precision: FP64 Hessian in the Newton endgame")
@@ -570,7 +571,7 @@ def main():
           "vcycle": ms.PC_TWO_LEVEL_VCYCLE}[a.pc]
     prec = ms.PREC_MIXED if a.precision == "mixed" else ms.PREC_FP64
     params = ms.solver_defaults(precision=prec, preconditioner=pc, forcing=1, pcg_eta_max=a.eta_max,
-                                coarse_every=a.coarse_every, coarse_move=a.coarse_move,
+                                pcg_eta_min=a.eta_min, coarse_every=a.coarse_every, coarse_move=a.coarse_move,
                                 mixed_endgame_fp64=a.endgame_fp64, endgame_ratio=a.endgame_ratio)
     value, elapsed, stats, states, ctx, basis_s = run(dev, s, params, a.warmup, a.steps,
                                                       handles=a.handles if pc != ms.PC_BLOCK_JACOBI else 0,
@@ -592,7 +593,7 @@ def main():
     k = a.warmup + a.steps + 1
     ctx.ms_set_dirichlet(s["dirichlet"], s["dbc_targets"](k))
     tparams = ms.solver_defaults(precision=prec, preconditioner=pc, forcing=1, pcg_eta_max=a.eta_max,
-                                 coarse_every=a.coarse_every, coarse_move=a.coarse_move,
+                                 pcg_eta_min=a.eta_min, coarse_every=a.coarse_every, coarse_move=a.coarse_move,
                                  mixed_endgame_fp64=a.endgame_fp64, endgame_ratio=a.endgame_ratio, time_kernels=1)
     tstat = ctx.ms_step(s["dt"], tparams)
     k_us, k_bytes = ctx.ms_time_kernel(0, kprec, 0)
@@ -652,7 +653,7 @@ def main():
                    "precision": a.precision, "preconditioner": a.pc,
                    "handles": a.handles if pc != ms.PC_BLOCK_JACOBI else None, "pcg_eta_max": a.eta_max,
                    "coarse_every": a.coarse_every, "coarse_move": a.coarse_move, "endgame_fp64": a.endgame_fp64,
-                   "endgame_ratio": a.endgame_ratio,
+                   "endgame_ratio": a.endgame_ratio, "pcg_eta_min": a.eta_min,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kernel_name, f"{a.scene}{a.grid}"),

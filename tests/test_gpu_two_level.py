@@ -208,6 +208,7 @@ def test_two_level_steps_match_oracle(dev):
     ("smoothed", dict(coarse_move=0.2)),
     ("additive", dict(coarse_move=0.2, mixed_max_newton=1)),
     ("vcycle", dict(coarse_move=0.2)),
+    ("additive", dict(coarse_move=0.2, pcg_eta_min=1e-4)),
 ])
 def test_mixed_policies_match_oracle(dev, pc_name, opts):
     """Mixed precision with the FP64 endgame, Eisenstat-Walker forcing and a
