@@ -317,9 +317,9 @@ def learned_main(a):
     dev = ms.TorchDevice(0)
     prec = ms.PREC_MIXED if a.precision == "mixed" else ms.PREC_FP64
     base = dict(precision=prec, preconditioner=ms.PC_TWO_LEVEL_ADDITIVE, forcing=1, pcg_eta_max=a.eta_max,
-                max_newton=100, coarse_move=a.coarse_move, mixed_endgame_fp64=a.endgame_fp64)
+                pcg_eta_min=a.eta_min, max_newton=100, coarse_move=a.coarse_move, mixed_endgame_fp64=a.endgame_fp64)
     plain64 = dict(precision=ms.PREC_FP64, preconditioner=ms.PC_BLOCK_JACOBI, forcing=1, pcg_eta_max=a.eta_max,
-                   max_newton=100)
+                   pcg_eta_min=a.eta_min, max_newton=100)
 
     def trajectory(seed, warm=None, form=None):
         """Coarse states, step stats and states of one trajectory, or None if
@@ -436,7 +436,8 @@ def paper_main(a):
     dev = ms.TorchDevice(0)
     prec = ms.PREC_MIXED if a.precision == "mixed" else ms.PREC_FP64
     exact = ms.solver_defaults(precision=prec, preconditioner=ms.PC_TWO_LEVEL_ADDITIVE, forcing=1,
-                               pcg_eta_max=a.eta_max, coarse_move=a.coarse_move, mixed_endgame_fp64=a.endgame_fp64)
+                               pcg_eta_max=a.eta_max, pcg_eta_min=a.eta_min, coarse_move=a.coarse_move,
+                               mixed_endgame_fp64=a.endgame_fp64)
     pparams = ms.solver_defaults(mode=ms.MODE_PAPER, precision=prec, refine_iters=0, max_newton=100)
     cases = [("cube %d^3, per-tet E log-uniform in [1e5, 1e8], bottom pinned, gravity" % a.grid,
               scenes.plain_cube(a.grid, seed=0, steps=a.warmup + a.steps), a.handles),
@@ -613,7 +614,7 @@ def main():
     ref = None
     if not a.no_reference:
         pref = ms.solver_defaults(precision=ms.PREC_FP64, preconditioner=ms.PC_BLOCK_JACOBI, forcing=1,
-                                  pcg_eta_max=a.eta_max)
+                                  pcg_eta_max=a.eta_max, pcg_eta_min=a.eta_min)
         rv, _, rstats, rstates, rctx, _ = run(dev, s, pref, a.warmup, a.steps)
         rctx.close()
         xr, xg = rstates[-1], states[-1]
@@ -626,7 +627,7 @@ def main():
             # the same preconditioner and policy in FP64 throughout, on the
             # same basis: isolates what the mixed-precision form gains
             p64 = ms.solver_defaults(precision=ms.PREC_FP64, preconditioner=pc, forcing=1, pcg_eta_max=a.eta_max,
-                                     coarse_every=a.coarse_every, coarse_move=a.coarse_move)
+                                     pcg_eta_min=a.eta_min, coarse_every=a.coarse_every, coarse_move=a.coarse_move)
             fv, _, fstats, fstates, fctx, _ = run(dev, s, p64, a.warmup, a.steps, basis=basis)
             fctx.close()
             ref["fp64_same_preconditioner"] = {
