@@ -407,7 +407,10 @@ def learned_main(a):
                    "handles": r // 12, "train_seeds": len(train), "samples": int(len(Xn)),
                    "network": f"{2 * r}-256-256-{r} SiLU, bf16 products", "parallelism": "single GPU"},
         "training": {"steps": steps, "batch": 128, "lr": 1e-3, "loss_first": float(losses[0]),
-                     "loss_last": float(np.mean(losses[-50:])), "train_s": train_s, "data_gen_s": gen_s},
+                     "loss_last": float(np.mean(losses[-50:])), "train_s": train_s, "data_gen_s": gen_s,
+                     # matrix-core work: forward 2 flops per weight and sample, backward twice that
+                     "gemm_tflops": 6.0 * 128 * steps * (2 * r * 256 + 256 * 256 + 256 * r) / train_s * 1e-12,
+                     "bf16_dense_peak_tflops": 2500.0},
         "reference_form": {"form": "same held-out steps without the warm start (inertial predictor)",
                            "value": 1e3 * a.traj_steps * len(rows) / t_base, "unit": "timesteps/s",
                            "speedup": t_base / t_warm},
