@@ -14,7 +14,13 @@ Readings where the paper is silent (each also listed in the design notes):
   * Gravity enters as the potential -sum_v m_v g . x_v inside the h^2 term.
   * B is the IPC log barrier b(d) = -(d - dhat)^2 ln(d / dhat) for 0 < d < dhat
     (Li et al. 2020) on the signed distance d_v = n . x_v - c of every vertex
-    to a rigid half-space, scaled by a stiffness kappa.  D = 0 (no friction).
+    to a rigid half-space, scaled by a stiffness kappa.
+  * D is lagged Coulomb friction against the half-space in the IPC form (the
+    paper's D(x) term; off unless the half-space has mu > 0):
+        D(x) = sum_v mu lambda_v f0(|u_v|),  u_v = P (x_v - x_v^t),  P = I - n n^T,
+    with the normal force lambda_v = kappa |b'(d_v(x^t))| frozen at the start
+    of the step and the smoothed magnitude f0(y) = y for y >= eps_v h, else
+    -y^3 / (3 (eps_v h)^2) + y^2 / (eps_v h) + eps_v h / 3 (C1 at eps_v h).
   * The element Hessian is made PSD by clamping the negative eigenvalues of
     the 9x9 deformation-gradient Hessian (the usual IPC practice); this
     changes Newton iterates only, not the minimiser.
@@ -146,10 +152,41 @@ def barrier_d2(d, dhat):
 
 
 # ----------------------------------------------------------------------------
+# Smoothed friction magnitude f0 and its derivatives in y = |u| (eh = eps_v h).
+# ----------------------------------------------------------------------------
+def friction_f0(y, eh):
+    y = np.asarray(y, dtype=np.float64)
+    out = y.copy()
+    m = y < eh
+    ym = y[m]
+    out[m] = -ym ** 3 / (3.0 * eh * eh) + ym * ym / eh + eh / 3.0
+    return out
+
+
+def friction_f1(y, eh):
+    """f0'(y): 1 beyond eh, -y^2/eh^2 + 2y/eh below (0 at rest)."""
+    y = np.asarray(y, dtype=np.float64)
+    out = np.ones_like(y)
+    m = y < eh
+    ym = y[m]
+    out[m] = -ym * ym / (eh * eh) + 2.0 * ym / eh
+    return out
+
+
+def friction_f2(y, eh):
+    """f0''(y)."""
+    y = np.asarray(y, dtype=np.float64)
+    out = np.zeros_like(y)
+    m = y < eh
+    out[m] = -2.0 * y[m] / (eh * eh) + 2.0 / eh
+    return out
+
+
+# ----------------------------------------------------------------------------
 # The incremental potential of one implicit Euler step.
 # ----------------------------------------------------------------------------
 class StepProblem:
-    """E(x) of one implicit Euler step (Eq. IP with alpha = 1, D = 0)."""
+    """E(x) of one implicit Euler step (Eq. IP with alpha = 1)."""
 
     def __init__(self, body: Body, x_t, v_t, h, gravity, halfspace=None):
         self.b = body
@@ -158,6 +195,13 @@ class StepProblem:
         self.xtilde = self.x_t + self.h * np.asarray(v_t, dtype=np.float64)
         self.gravity = np.asarray(gravity, dtype=np.float64)
         self.hs = halfspace
+        # lagged friction: mu lambda_v from the contact forces at x^t
+        self.fric = None
+        if halfspace is not None and float(halfspace.get("mu", 0.0)) > 0.0:
+            lam = float(halfspace["kappa"]) * np.abs(barrier_d1(self._dist(self.x_t), float(halfspace["dhat"])))
+            nrm = np.asarray(halfspace["normal"], dtype=np.float64)
+            self.fric = dict(mulam=float(halfspace["mu"]) * lam, eh=float(halfspace["eps_v"]) * self.h,
+                             P=np.eye(3) - np.outer(nrm, nrm))
 
     # -- parts ---------------------------------------------------------------
     def _dist(self, x):
@@ -174,11 +218,15 @@ class StepProblem:
         Bv = 0.0
         if self.hs is not None:
             Bv = float(self.hs["kappa"]) * float(barrier(self._dist(x), float(self.hs["dhat"])).sum())
-        return dict(K=K, Psi=h2 * Psi, G=h2 * G, B=h2 * Bv)
+        Dv = 0.0
+        if self.fric is not None:
+            y = np.linalg.norm((x - self.x_t) @ self.fric["P"], axis=1)
+            Dv = float((self.fric["mulam"] * friction_f0(y, self.fric["eh"])).sum())
+        return dict(K=K, Psi=h2 * Psi, G=h2 * G, B=h2 * Bv, D=h2 * Dv)
 
     def energy(self, x):
         p = self.energy_parts(x)
-        return p["K"] + p["Psi"] + p["G"] + p["B"]
+        return p["K"] + p["Psi"] + p["G"] + p["B"] + p["D"]
 
     def energy_scale(self, x):
         p = self.energy_parts(x)
@@ -198,6 +246,12 @@ class StepProblem:
             n = np.asarray(self.hs["normal"], dtype=np.float64)
             d1 = barrier_d1(self._dist(x), float(self.hs["dhat"]))
             g += h2 * float(self.hs["kappa"]) * d1[:, None] * n[None, :]
+        if self.fric is not None:
+            u = (x - self.x_t) @ self.fric["P"]
+            y = np.linalg.norm(u, axis=1)
+            f1 = friction_f1(y, self.fric["eh"])
+            c1 = np.where(y > 0, f1 / np.where(y > 0, y, 1.0), 2.0 / self.fric["eh"])  # f1(y)/y, 2/eh at 0
+            g += h2 * (self.fric["mulam"] * c1)[:, None] * u
         return g
 
     def element_hessians(self, x, project=True):
@@ -232,7 +286,21 @@ class StepProblem:
             d2 = barrier_d2(self._dist(x), float(self.hs["dhat"]))
             blk = h2 * float(self.hs["kappa"]) * d2[:, None, None] * np.outer(nrm, nrm)[None]
             H = H + _block_diag3(blk)
+        if self.fric is not None:
+            H = H + _block_diag3(h2 * self.friction_blocks(x))
         return H.tocsr()
+
+    def friction_blocks(self, x):
+        """Per-vertex 3x3 Hessian of D: mu lambda [f1/y P + (f0'' - f1/y) u u^T / y^2]
+        (positive semi-definite for this f0; the limit 2/eh P at rest)."""
+        P, eh = self.fric["P"], self.fric["eh"]
+        u = (x - self.x_t) @ P
+        y = np.linalg.norm(u, axis=1)
+        ys = np.where(y > 0, y, 1.0)
+        c1 = np.where(y > 0, friction_f1(y, eh) / ys, 2.0 / eh)
+        c2 = np.where(y > 0, (friction_f2(y, eh) - c1) / (ys * ys), 0.0)
+        blk = c1[:, None, None] * P[None] + c2[:, None, None] * np.einsum("vi,vj->vij", u, u)
+        return self.fric["mulam"][:, None, None] * blk
 
 
 def _block_diag3(blk):

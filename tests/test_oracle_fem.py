@@ -163,3 +163,82 @@ def test_lumped_mass_total():
     T = len(tets)
     body = fem.Body(rest, tets, np.ones(T), np.full(T, 0.3), np.full(T, 1000.0))
     assert body.mass.sum() == pytest.approx(1000.0, rel=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# friction (lagged IPC form against the half-space)
+# ---------------------------------------------------------------------------
+def test_friction_magnitude_closed_forms():
+    eh = 2e-3
+    y = np.array([0.0, 0.3 * eh, eh * (1 - 1e-12), eh, 3 * eh])
+    f0, f1, f2 = fem.friction_f0(y, eh), fem.friction_f1(y, eh), fem.friction_f2(y, eh)
+    assert f0[0] == pytest.approx(eh / 3.0, rel=1e-15) and f1[0] == 0.0 and f2[0] == pytest.approx(2.0 / eh)
+    # C1 at eh (values and slopes from both sides), Coulomb magnitude beyond
+    assert f0[2] == pytest.approx(eh, rel=1e-9) and f0[3] == eh and f0[4] == 3 * eh
+    assert f1[2] == pytest.approx(1.0, rel=1e-9) and f1[3] == 1.0 and f1[4] == 1.0
+    assert abs(f2[2]) <= 1e-6 / eh and f2[4] == 0.0
+    # f1 = f0' and f2 = f1' by central differences on both branches
+    for yy in (0.2 * eh, 0.7 * eh, 2.5 * eh):
+        s = 1e-6 * eh
+        assert fem.friction_f1(yy, eh) == pytest.approx(
+            (fem.friction_f0(yy + s, eh) - fem.friction_f0(yy - s, eh)) / (2 * s), rel=1e-7, abs=1e-9)
+        assert fem.friction_f2(yy, eh) == pytest.approx(
+            (fem.friction_f1(yy + s, eh) - fem.friction_f1(yy - s, eh)) / (2 * s), rel=1e-6, abs=1e-6 / eh)
+
+
+def _tiny_friction(seed=3):
+    prob, x = _tiny(seed=seed)
+    # plane within dhat of the lowest vertices of x^t, so they carry a lagged normal force
+    hs = dict(prob.hs, offset=prob.x_t[:, 2].min() - 3e-3, mu=0.4, eps_v=0.05)
+    prob = fem.StepProblem(prob.b, prob.x_t, (prob.xtilde - prob.x_t) / prob.h, prob.h, prob.gravity, hs)
+    eh = hs["eps_v"] * prob.h
+    # tangential displacements from x^t on both sides of eps_v h
+    rng = np.random.default_rng(seed + 1)
+    u = rng.standard_normal(x.shape) * np.array([1.0, 1.0, 0.0])
+    scale = np.where(np.arange(len(x)) % 2 == 0, 0.4 * eh, 4.0 * eh)
+    x = prob.x_t + u / np.linalg.norm(u, axis=1)[:, None] * scale[:, None] + np.array([0, 0, 1e-4])
+    assert (prob.fric["mulam"] > 0).sum() >= 2  # some vertices carry a normal force
+    return prob, x
+
+
+def test_friction_gradient_and_hessian_match_central_differences():
+    prob, x = _tiny_friction()
+    g = prob.gradient(x).ravel()
+    H = prob.hessian(x, project=False).toarray()
+    eps = 1e-9
+    fd_g = np.zeros_like(g)
+    fd_H = np.zeros_like(H)
+    for k in range(len(g)):
+        e = np.zeros(len(g))
+        e[k] = eps
+        xp, xm = x + e.reshape(x.shape), x - e.reshape(x.shape)
+        fd_g[k] = (prob.energy(xp) - prob.energy(xm)) / (2 * eps)
+        fd_H[:, k] = (prob.gradient(xp).ravel() - prob.gradient(xm).ravel()) / (2 * eps)
+    assert np.linalg.norm(fd_g - g) <= 1e-6 * np.linalg.norm(g)
+    assert np.abs(fd_H - H).max() <= 1e-5 * np.abs(H).max()
+    # the friction blocks alone are symmetric positive semi-definite
+    for blk in prob.friction_blocks(x):
+        assert np.allclose(blk, blk.T, atol=1e-12 * np.abs(blk).max() + 1e-300)
+        assert np.linalg.eigvalsh(blk).min() >= -1e-9 * max(np.abs(blk).max(), 1e-300)
+
+
+def test_friction_decelerates_a_sliding_body_by_mu_g_h():
+    """Coulomb's law: a stiff cube resting on the plane (normal force = its
+    weight) and sliding tangentially loses mu * M * g * h of tangential
+    momentum in one implicit step, whatever the barrier's constants."""
+    from oracle import newton
+    rest, tets, _, _ = scenes.kuhn_cube(2, size=0.1)
+    T = len(tets)
+    body = fem.Body(rest, tets, np.full(T, 1e9), np.full(T, 0.3), np.full(T, 1000.0))
+    g = np.array([0.0, 0.0, -9.81])
+    hs = dict(normal=np.array([0.0, 0.0, 1.0]), offset=-5e-4, dhat=1e-3, kappa=1e5)
+    # static equilibrium on the plane: one step so long that inertia vanishes
+    x_eq, _, _ = newton.newton_step(body, rest, np.zeros_like(rest), 30.0, g, halfspace=hs)
+    M = body.mass.sum()
+    mu, h, v0 = 0.3, 0.01, np.array([1.0, 0.5, 0.0])
+    hsf = dict(hs, mu=mu, eps_v=1e-4)
+    v_t = np.tile(v0, (len(rest), 1))
+    x1, v1, _ = newton.newton_step(body, x_eq, v_t, h, g, halfspace=hsf)
+    dp = (body.mass[:, None] * (v1 - v_t)).sum(axis=0)
+    expect = -h * mu * M * 9.81 * v0 / np.linalg.norm(v0)
+    assert np.abs(dp[:2] - expect[:2]).max() <= 1e-4 * np.linalg.norm(expect)
