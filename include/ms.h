@@ -213,6 +213,16 @@ ms_status ms_set_dirichlet(ms_ctx* c, int64_t n, const int32_t* verts, const dou
  * be unit length (it is normalised).  At most one half-space. */
 ms_status ms_add_halfspace(ms_ctx* c, const double normal[3], double offset, double dhat, double kappa);
 
+/* Lagged Coulomb friction against the half-space (the D term of the
+ * incremental potential, Sec. 3.1; IPC's smoothed form): per vertex
+ * mu lambda_v f0(|P (x_v - x_v^t)|) with P the tangent projector of the
+ * plane, lambda_v = kappa |b'(d_v(x^t))| the barrier's normal force at the
+ * start of the step and f0 the C1 smoothing of |u| below eps_v h (eps_v in
+ * m/s).  mu = 0 turns friction off.  Plain mode only (paper mode returns
+ * MS_E_ARG).  Errors: MS_E_ORDER without a half-space, MS_E_ARG for
+ * mu < 0 or eps_v <= 0. */
+ms_status ms_set_friction(ms_ctx* c, double mu, double eps_v);
+
 /* Set positions x [n][3] and velocities v [n][3].  With a half-space every
  * vertex must lie strictly inside it.  Errors: MS_E_NONFINITE, MS_E_ARG. */
 ms_status ms_set_state(ms_ctx* c, const double* x, const double* v);

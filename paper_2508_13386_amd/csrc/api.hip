@@ -388,6 +388,16 @@ ms_status ms_add_halfspace(ms_ctx* c, const double nrm[3], double off, double dh
   return MS_OK;
 }
 
+ms_status ms_set_friction(ms_ctx* c, double mu, double eps_v) {
+  if (!c) return MS_E_ARG;
+  if (!c->has_hs) return fail(c, MS_E_ORDER, "add a half-space first");
+  if (!(mu >= 0.0) || !std::isfinite(mu) || !(eps_v > 0.0) || !std::isfinite(eps_v))
+    return fail(c, MS_E_ARG, "need mu >= 0 and eps_v > 0");
+  c->hs_mu = mu;
+  c->hs_epsv = eps_v;
+  return MS_OK;
+}
+
 ms_status ms_set_state(ms_ctx* c, const double* x, const double* v) {
   if (!c) return MS_E_ARG;
   if (c->stage < 2) return fail(c, MS_E_ORDER, "upload mesh and material first");

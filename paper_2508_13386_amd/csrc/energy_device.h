@@ -82,6 +82,13 @@ __device__ __forceinline__ void vertex_energy_delta(int64_t i, const double* __r
     barrier_terms(dist + ddist, hs.dhat, bn, bn1, bn2);
     e[3] = h2 * hs.kappa * (bn - b);
     e[4] += h2 * hs.kappa * (fabs(bn) + fabs(b));
+    if (hs.mu > 0.0) {  // lagged friction: D_v(x + alpha d) - D_v(x)
+      const double y0[3] = {x[3 * i], x[3 * i + 1], x[3 * i + 2]};
+      const double y1[3] = {y0[0] + dv[0], y0[1] + dv[1], y0[2] + dv[2]};
+      const double f0 = friction_energy(hs, i, y0), f1 = friction_energy(hs, i, y1);
+      e[3] += h2 * (f1 - f0);
+      e[4] += h2 * (fabs(f1) + fabs(f0));
+    }
   }
   }
 

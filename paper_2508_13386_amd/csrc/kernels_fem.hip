@@ -247,6 +247,14 @@ __global__ void k_gather_grad(int64_t n, const int32_t* __restrict__ vt_ptr, con
     r0 += f * hs.n[0];
     r1 += f * hs.n[1];
     r2 += f * hs.n[2];
+    if (hs.mu > 0.0) {
+      const double y[3] = {x0, x1, x2};
+      double gf[3], Hf[9];
+      friction_terms(hs, v, y, gf, Hf);
+      r0 += h2 * gf[0];
+      r1 += h2 * gf[1];
+      r2 += h2 * gf[2];
+    }
   }
   g[3 * v] = r0;
   g[3 * v + 1] = r1;
@@ -301,6 +309,13 @@ __global__ void __launch_bounds__(64) k_gather_hess(int64_t n, int S, const int3
         for (int i = 0; i < 3; ++i)
 #pragma unroll
           for (int j = 0; j < 3; ++j) acc[3 * i + j] += f * hs.n[i] * hs.n[j];
+        if (hs.mu > 0.0) {
+          const double y[3] = {x[3 * row], x[3 * row + 1], x[3 * row + 2]};
+          double gf[3], Hf[9];
+          friction_terms(hs, row, y, gf, Hf);
+#pragma unroll
+          for (int q = 0; q < 9; ++q) acc[q] += h2 * Hf[q];
+        }
       }
     }
   }
@@ -309,7 +324,8 @@ __global__ void __launch_bounds__(64) k_gather_hess(int64_t n, int S, const int3
   for (int c = 0; c < 9; ++c) out[S * c] = VT(acc[c]);
 }
 
-// Energy parts at y = x + alpha d: {K, h^2 Psi, h^2 G, h^2 B}; threads cover
+// Energy parts at y = x + alpha d: {K, h^2 Psi, h^2 G, h^2 (B + D)} with D
+// the lagged friction (zero unless mu > 0); threads cover
 // max(T, n) indices, doing one tet and one vertex each.
 __global__ void __launch_bounds__(256) k_energy(int64_t T, int64_t n, const int32_t* __restrict__ tets,
                                                 const double* __restrict__ Dminv, const double* __restrict__ vol,
@@ -359,6 +375,7 @@ __global__ void __launch_bounds__(256) k_energy(int64_t T, int64_t n, const int3
       double b, b1, b2;
       barrier_terms(hs.n[0] * y[0] + hs.n[1] * y[1] + hs.n[2] * y[2] - hs.off, hs.dhat, b, b1, b2);
       e[3] = h2 * hs.kappa * b;
+      if (hs.mu > 0.0) e[3] += h2 * friction_energy(hs, i, y);
     }
   }
   if (grid_sum<4>(e, part, counter) && threadIdx.x == 0)
@@ -373,7 +390,7 @@ __global__ void __launch_bounds__(256) k_energy(int64_t T, int64_t n, const int3
 //             dIc = 2 F:delta + |delta|^2,
 //             dJ  = cof(F):delta + F:cof(delta) + det(delta)  (exact for 3x3),
 //             dPsi = mu/2 dIc - mu dJ + lam/2 dJ (dJ + 2 (J - 1))
-//   barrier   per vertex b(d') - b(d)
+//   barrier   per vertex b(d') - b(d); lagged friction D_v(y') - D_v(y)
 // out[4] = sum of the magnitudes of the terms above, the scale of the
 // round-off in the total.  Threads cover max(T, n) indices, one tet and one vertex each.
 __global__ void __launch_bounds__(256) k_energy_delta(int64_t T, int64_t n, const int32_t* __restrict__ tets,
@@ -470,6 +487,7 @@ static inline unsigned nblocks(int64_t n, int b) { return unsigned((n + b - 1) /
 
 
 void launch_predict(ms_ctx* c, double dt) {
+  c->step_h = dt;  // the friction smoothing length eps_v h uses it
   k_predict<<<nblocks(3 * c->n, 256), 256, 0, c->stream>>>(3 * c->n, c->d_x, c->d_v, dt, c->d_xt, c->d_xtilde);
 }
 void launch_apply_dbc(ms_ctx* c, int64_t nd) {

@@ -121,6 +121,8 @@ struct ms_ctx {
   double gravity[3] = {0, 0, 0};
   bool has_hs = false;
   double hs_n[3] = {0, 0, 1}, hs_off = 0, hs_dhat = 1e-3, hs_kappa = 0;
+  double hs_mu = 0.0, hs_epsv = 1e-3;  // lagged friction against the half-space
+  double step_h = 0.0;                 // timestep of the current step / evaluation
   // Dirichlet
   std::vector<int32_t> h_dbc;
   std::vector<double> h_dbc_tgt;

@@ -213,6 +213,7 @@ struct LagSwap {
 ms_status paper_step(ms_ctx* c, double dt, const ms_solver_params& P, ms_step_stats* st) {
   const double t0 = now_ms();
   if (!c->has_basis) return fail(c, MS_E_ORDER, "paper mode needs a basis");
+  if (c->has_hs && c->hs_mu > 0.0) return fail(c, MS_E_ARG, "paper mode does not support friction");
   set_coarse_f32(c, false);
   const double h2 = dt * dt;
   const int prec = P.precision == MS_PREC_MIXED ? MS_PREC_MIXED : MS_PREC_FP64;

@@ -88,6 +88,7 @@ def lib():
             "ms_set_gravity": [vp, dp],
             "ms_set_dirichlet": [vp, i64, ip, dp],
             "ms_add_halfspace": [vp, dp, d, d, d],
+            "ms_set_friction": [vp, d, d],
             "ms_set_state": [vp, dp, dp],
             "ms_get_state": [vp, dp, dp],
             "ms_build_basis": [vp, C.POINTER(ms_basis_params)],
@@ -249,6 +250,9 @@ class Context:
     def ms_add_halfspace(self, normal, offset, dhat, kappa):
         nrm = _f64(normal)
         self._check(self.L.ms_add_halfspace(self.h, _ptr(nrm), float(offset), float(dhat), float(kappa)))
+
+    def ms_set_friction(self, mu, eps_v=1e-3):
+        self._check(self.L.ms_set_friction(self.h, float(mu), float(eps_v)))
 
     def ms_set_state(self, x, v):
         x, v = _f64(x), _f64(v)
@@ -497,5 +501,7 @@ def context_from_scene(dev: TorchDevice, s, step: int = 1):
     if s["halfspace"] is not None:
         hs = s["halfspace"]
         c.ms_add_halfspace(hs["normal"], hs["offset"], hs["dhat"], hs["kappa"])
+        if float(hs.get("mu", 0.0)) > 0.0:
+            c.ms_set_friction(hs["mu"], hs.get("eps_v", 1e-3))
     c.ms_set_state(s["x0"], s["v0"])
     return c

@@ -198,6 +198,31 @@ def gyroid_sphere(res: int = 64, period: int = 8, thresh: float = 0.3, E: float 
                 x0=rest.copy(), v0=v0, dt=dt, steps=steps)
 
 
+def sliding_cube(N: int = 6, size: float = 0.2, E: float = 1e6, nu: float = 0.4, rho: float = 1000.0,
+                 mu: float = 0.5, eps_v: float = 1e-3, velocity=(1.0, 0.5, 0.0), dhat: float = 1e-3,
+                 dt: float = 1.0 / 100.0, steps: int = 10):
+    """Friction scene: a Kuhn N^3 cube of edge `size` resting on a rigid slab
+    z = 0 (bottom layer at dhat / 2, inside the barrier's range) and sliding
+    with the given tangential velocity; gravity; lagged Coulomb friction
+    coefficient mu with smoothing velocity eps_v.  The barrier stiffness is
+    chosen so that the bottom layer's barrier forces at dhat / 2 carry the
+    cube's weight (the slide starts close to vertical equilibrium)."""
+    rest, tets, _, _ = kuhn_cube(N, size)
+    rest = rest.copy()
+    rest[:, 2] += 0.5 * dhat
+    T = len(tets)
+    v0 = np.tile(np.asarray(velocity, dtype=np.float64), (len(rest), 1))
+    d, e = 0.5 * dhat, -0.5 * dhat
+    b1 = abs(-2.0 * e * math.log(d / dhat) - e * e / d)  # |b'(dhat / 2)|
+    kappa = rho * size ** 3 * abs(GRAVITY[2]) / ((N + 1) ** 2 * b1)
+    return dict(name=f"sliding_cube_{N}", rest=rest, tets=tets, E=np.full(T, E), nu=np.full(T, nu),
+                rho=np.full(T, rho), gravity=GRAVITY.copy(), dirichlet=_empty_dbc(),
+                dbc_targets=lambda k: np.zeros((0, 3)),
+                halfspace=dict(normal=np.array([0.0, 0.0, 1.0]), offset=0.0, dhat=dhat, kappa=kappa, mu=mu,
+                               eps_v=eps_v),
+                x0=rest.copy(), v0=v0, dt=dt, steps=steps)
+
+
 def batch_scenes(n_scenes: int = 64, seed: int = 0, t_lo: float = 1e3, t_hi: float = 5e4,
                  e_lo: float = 1e5, e_hi: float = 1e9, nu: float = 0.45, rho: float = 1000.0,
                  dt: float = 1.0 / 60.0, steps: int = 10):

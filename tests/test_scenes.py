@@ -68,3 +68,15 @@ def test_vertex_renumbering_keeps_the_mesh(kind):
     assert np.array_equal(t["rest"][t["tets"]], s["rest"][s["tets"]])
     assert np.array_equal(t["rest"][t["dirichlet"]], s["rest"][s["dirichlet"]])
     assert np.array_equal(t["dbc_targets"](3), s["dbc_targets"](3))
+
+
+def test_sliding_cube_starts_in_vertical_balance():
+    s = scenes.sliding_cube(4)
+    hs = s["halfspace"]
+    z = s["rest"][:, 2]
+    bottom = np.isclose(z, z.min())
+    assert bottom.sum() == 25 and z.min() == pytest.approx(0.5 * hs["dhat"])
+    from oracle import fem
+    lam = hs["kappa"] * np.abs(fem.barrier_d1(z[bottom], hs["dhat"]))
+    weight = 1000.0 * 0.2 ** 3 * 9.81
+    assert lam.sum() == pytest.approx(weight, rel=1e-12)
