@@ -43,9 +43,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=8)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--grid", type=int, default=32)
-    ap.add_argument("--scene", choices=["block", "gyroid"], default="block",
+    ap.add_argument("--scene", choices=["block", "gyroid", "sliding"], default="block",
                     help="block: the heterogeneous block (--grid); gyroid: the contact scene, a gyroid-lattice "
-                         "sphere voxelized at --grid^3 falling at 5 m/s onto a rigid half-space")
+                         "sphere voxelized at --grid^3 falling at 5 m/s onto a rigid half-space; sliding: a "
+                         "--grid^3 cube sliding on the half-space with lagged friction (mu = 0.5)")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="mixed")
     ap.add_argument("--pc", choices=["jacobi", "two_level", "additive", "vcycle"], default="additive")
     ap.add_argument("--handles", type=int, default=192)
@@ -103,7 +104,12 @@ def cpu_baseline(scene="block", grid=32, n_tets=None):
     import scenes
     from oracle import fem, newton
     g = max(4, (3 * grid) // 8 if scene == "gyroid" else grid // 2)
-    s = scenes.gyroid_sphere(res=g) if scene == "gyroid" else scenes.inclusion_block(g, seed=0, steps=1)
+    if scene == "gyroid":
+        s = scenes.gyroid_sphere(res=g)
+    elif scene == "sliding":
+        s = scenes.sliding_cube(g, steps=1)
+    else:
+        s = scenes.inclusion_block(g, seed=0, steps=1)
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
         body = fem.Body(s["rest"], s["tets"], s["E"], s["nu"], s["rho"])
@@ -561,7 +567,11 @@ def main():
     import scenes
     from paper_2508_13386_amd import ms
 
-    if a.scene == "gyroid":
+    if a.scene == "sliding":
+        s = scenes.sliding_cube(a.grid, steps=a.warmup + a.steps)
+        wname = (f"cube {a.grid}^3 hexes x 6 tets (0.2 m, E=1e6, nu=0.4) sliding at 1.1 m/s on a rigid half-space, "
+                 f"IPC barrier d_hat=1e-3, lagged friction mu=0.5, eps_v=1e-3, dt=1/100")
+    elif a.scene == "gyroid":
         s = scenes.gyroid_sphere(res=a.grid)
         wname = (f"gyroid-lattice sphere voxelized at {a.grid}^3 (E=1e7, nu=0.45) falling at 5 m/s onto a rigid "
                  f"half-space, IPC barrier d_hat=1e-3, dt=1/100")
