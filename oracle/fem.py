@@ -2,7 +2,9 @@
 
 Test infrastructure only.  Follows Sec. 3.1 of the paper:
   E(x) = K(x) + alpha h^2 (Psi(x) + B(x) + D(x)),  K = 1/2 ||x - x~||_M^2,
-  implicit Euler: x~ = x^t + h v^t, alpha = 1, v^{t+1} = (x^{t+1} - x^t)/h.
+  implicit Euler: x~ = x^t + h v^t, alpha = 1, v^{t+1} = (x^{t+1} - x^t)/h;
+  BDF2: x~ = 4/3 x^t - 1/3 x^{t-1} + h (8 v^t - 2 v^{t-1}) / 9, alpha = 4/9,
+        v^{t+1} = (3 x^{t+1} - 4 x^t + x^{t-1}) / (2h).
 
 Readings where the paper is silent (each also listed in the design notes):
   * Psi is the stable Neo-Hookean energy
@@ -188,11 +190,22 @@ def friction_f2(y, eh):
 class StepProblem:
     """E(x) of one implicit Euler step (Eq. IP with alpha = 1)."""
 
-    def __init__(self, body: Body, x_t, v_t, h, gravity, halfspace=None):
+    def __init__(self, body: Body, x_t, v_t, h, gravity, halfspace=None, prev=None):
+        """prev = (x^{t-1}, v^{t-1}) selects BDF2: x~ = 4/3 x^t - 1/3 x^{t-1} +
+        8/9 h v^t - 2/9 h v^{t-1} and the weight alpha = 4/9 on the h^2 terms
+        (Sec. 3.1 names BDF2 beside implicit Euler; the scheme is the standard
+        second-order backward difference in x and v).  None: implicit Euler."""
         self.b = body
         self.h = float(h)
         self.x_t = np.asarray(x_t, dtype=np.float64)
-        self.xtilde = self.x_t + self.h * np.asarray(v_t, dtype=np.float64)
+        v_t = np.asarray(v_t, dtype=np.float64)
+        if prev is None:
+            self.alpha = 1.0
+            self.xtilde = self.x_t + self.h * v_t
+        else:
+            xp, vp = (np.asarray(a, dtype=np.float64) for a in prev)
+            self.alpha = 4.0 / 9.0
+            self.xtilde = (4.0 * self.x_t - xp) / 3.0 + self.h * (8.0 * v_t - 2.0 * vp) / 9.0
         self.gravity = np.asarray(gravity, dtype=np.float64)
         self.hs = halfspace
         # lagged friction: mu lambda_v from the contact forces at x^t
@@ -209,7 +222,7 @@ class StepProblem:
         return x @ n - float(self.hs["offset"])
 
     def energy_parts(self, x):
-        b, h2 = self.b, self.h * self.h
+        b, h2 = self.b, self.alpha * self.h * self.h
         dx = x - self.xtilde
         K = 0.5 * float((b.mass[:, None] * dx * dx).sum())
         F = b.deformation_gradient(x)
@@ -233,7 +246,7 @@ class StepProblem:
         return sum(abs(v) for v in p.values())
 
     def gradient(self, x):
-        b, h2 = self.b, self.h * self.h
+        b, h2 = self.b, self.alpha * self.h * self.h
         g = b.mass[:, None] * (x - self.xtilde)
         F = b.deformation_gradient(x)
         P = snh_P(F, b.mu, b.lam)
@@ -272,7 +285,7 @@ class StepProblem:
 
     def hessian(self, x, project=True):
         """Sparse 3n x 3n Hessian M + h^2 (sum_e H_e + kappa b'' n n^T)."""
-        b, h2 = self.b, self.h * self.h
+        b, h2 = self.b, self.alpha * self.h * self.h
         n3 = 3 * b.n
         He = h2 * self.element_hessians(x, project)
         dof = (3 * b.tets[:, :, None] + np.arange(3)[None, None, :]).reshape(-1, 12)

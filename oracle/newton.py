@@ -56,9 +56,10 @@ def ccd_bound(x, d, halfspace, safety=0.9):
 
 
 def newton_step(body: Body, x_t, v_t, h, gravity, dbc=None, dbc_target=None, halfspace=None,
-                dense=False, max_iter=100, tol=1e-12, project=True, record=None):
+                dense=False, max_iter=100, tol=1e-12, project=True, record=None, prev=None):
+    """One timestep; prev = (x^{t-1}, v^{t-1}) selects BDF2, else implicit Euler."""
     x_t = np.asarray(x_t, dtype=np.float64)
-    prob = StepProblem(body, x_t, v_t, h, gravity, halfspace)
+    prob = StepProblem(body, x_t, v_t, h, gravity, halfspace, prev)
     x = x_t.copy()
     n = body.n
     free = np.ones((n, 3), dtype=bool)
@@ -113,7 +114,10 @@ def newton_step(body: Body, x_t, v_t, h, gravity, dbc=None, dbc_target=None, hal
             stall += 1
             if stall >= 3:
                 break
-    v = (x - x_t) / h
+    if prev is None:
+        v = (x - x_t) / h
+    else:
+        v = (3.0 * x - 4.0 * x_t + np.asarray(prev[0], dtype=np.float64)) / (2.0 * h)
     return x, v, its
 
 

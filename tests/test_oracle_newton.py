@@ -151,3 +151,22 @@ def test_contact_filter_keeps_vertices_above_plane():
     prob = fem.StepProblem(body, x, v, 0.01, np.array([0.0, 0.0, -9.81]), hs)
     assert fem.barrier(x[:, 2], 5e-3).sum() > 0  # in contact
     assert newton.ccd_bound(x, np.tile([0.0, 0.0, -1.0], (len(x), 1)), hs) == pytest.approx(0.9 * x[:, 2].min())
+
+
+def test_bdf2_free_fall_is_exact():
+    """BDF2 is exact on trajectories quadratic in time: an unconstrained,
+    undeformed body in free fall, started with the exact history, follows
+    x(t) = x0 + v0 t + g t^2 / 2 to round-off (this also fixes the weight
+    4/9 on the h^2 terms)."""
+    rest, tets, _, _ = scenes.kuhn_cube(2)
+    T = len(tets)
+    body = fem.Body(rest, tets, np.full(T, 1e6), np.full(T, 0.3), np.full(T, 1000.0))
+    g = np.array([0.0, 0.0, -9.81])
+    v0 = np.array([0.3, -0.2, 1.0])
+    h = 0.01
+    X = lambda t: rest + v0 * t + 0.5 * g * t * t
+    V = lambda t: np.tile(v0 + g * t, (len(rest), 1))
+    for k in range(1, 4):
+        x, v, _ = newton.newton_step(body, X(k * h), V(k * h), h, g, prev=(X((k - 1) * h), V((k - 1) * h)))
+        assert np.abs(x - X((k + 1) * h)).max() <= 1e-12
+        assert np.abs(v - V((k + 1) * h)).max() <= 1e-9
