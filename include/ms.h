@@ -136,6 +136,12 @@ typedef struct {
                               many Newton iterations without convergence (0: never)    */
   int32_t mixed_endgame_fp64; /* mixed precision: 1 = assemble and solve in FP64 once
                               ||d|| <= endgame_ratio * ||x - x^t|| (the tight solves)   */
+  int32_t integrator;      /* plain mode: 0 implicit Euler; 1 BDF2 (Sec. 3.1):
+                              x~ = 4/3 x^t - 1/3 x^{t-1} + h (8 v^t - 2 v^{t-1}) / 9,
+                              weight 4/9 on the h^2 terms, v^{t+1} = (3 x^{t+1} - 4 x^t
+                              + x^{t-1}) / (2h), using the previous plain step of this
+                              context (implicit Euler when there is none: the first
+                              step after ms_set_state)                               */
 } ms_solver_params;
 
 /* Statistics of the last ms_step. */

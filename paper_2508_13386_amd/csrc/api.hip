@@ -77,6 +77,7 @@ static ms_status alloc_workspace(ms_ctx* c) {
   const int64_t n = c->n, T = c->T, n3 = 3 * n;
   ms_status s;
   if ((s = alloc_n(c, &c->d_x, n3)) || (s = alloc_n(c, &c->d_v, n3)) || (s = alloc_n(c, &c->d_xt, n3)) ||
+      (s = alloc_n(c, &c->d_xprev, n3)) || (s = alloc_n(c, &c->d_vprev, n3)) ||
       (s = alloc_n(c, &c->d_xtilde, n3)) || (s = alloc_n(c, &c->d_xtrial, n3)) || (s = alloc_n(c, &c->d_g, n3)) ||
       (s = alloc_n(c, &c->d_ge, 12 * T)) || (s = alloc_n(c, &c->d_He, 90 * T)) ||
       (s = alloc_n(c, &c->d_He32, 90 * T)) || (s = alloc_n(c, &c->d_vals, 9 * c->pat.nslots)) ||
@@ -248,6 +249,7 @@ void ms_solver_defaults(ms_solver_params* p) {
   p->coarse_move = 0.0;
   p->mixed_max_newton = 20;
   p->mixed_endgame_fp64 = 0;
+  p->integrator = 0;
 }
 
 void ms_basis_defaults(ms_basis_params* p) {
@@ -412,6 +414,7 @@ ms_status ms_set_state(ms_ctx* c, const double* x, const double* v) {
   MS_HIP(hipMemcpyAsync(c->d_v, v, n3 * sizeof(double), hipMemcpyHostToDevice, c->stream));
   c->stage = 3;
   c->q_hist = 0;
+  c->has_prev = false;
   return sync(c);
 }
 
@@ -520,6 +523,8 @@ ms_status ms_step(ms_ctx* c, double dt, const ms_solver_params* pin, ms_step_sta
     ms_solver_defaults(&P);
   if (!(P.coarse_move >= 0.0) || P.mixed_max_newton < 0)
     return fail(c, MS_E_ARG, "coarse_move and mixed_max_newton must not be negative");
+  if (P.integrator != 0 && P.integrator != 1) return fail(c, MS_E_ARG, "integrator must be 0 or 1");
+  if (P.integrator == 1 && P.mode == MS_MODE_PAPER) return fail(c, MS_E_ARG, "paper mode steps with implicit Euler");
   if (P.mode == MS_MODE_PAPER) return paper_step(c, dt, P, st);
   return plain_step(c, dt, P, st);
 }

@@ -720,8 +720,8 @@ extern "C" ms_status ms_batch_step(ms_ctx* const* scenes, int32_t n_scenes, doub
     P = *pin;
   else
     ms_solver_defaults(&P);
-  if (P.mode != MS_MODE_PLAIN || P.preconditioner != MS_PC_BLOCK_JACOBI || P.warm_start)
-    return fail(c0, MS_E_ARG, "batched steps support plain mode with block-Jacobi PCG");
+  if (P.mode != MS_MODE_PLAIN || P.preconditioner != MS_PC_BLOCK_JACOBI || P.warm_start || P.integrator != 0)
+    return fail(c0, MS_E_ARG, "batched steps support plain implicit-Euler mode with block-Jacobi PCG");
   for (int q = 0; q < n_scenes; ++q) {
     ms_ctx* sc = scenes[q];
     if (sc->stage < 3) return fail(c0, MS_E_ORDER, "scene " + std::to_string(q) + " has no state");
@@ -772,6 +772,7 @@ extern "C" ms_status ms_batch_step(ms_ctx* const* scenes, int32_t n_scenes, doub
                           u->stream));
   }
   u->stage = 3;
+  for (int q = 0; q < n_scenes; ++q) scenes[q]->has_prev = false;  // no BDF2 history across batched steps
   s = batch_step(B, dt, P, per_scene);
   if (s) return fail(c0, s, "batch: " + u->err);
   for (int q = 0; q < n_scenes; ++q) {

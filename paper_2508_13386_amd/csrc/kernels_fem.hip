@@ -483,12 +483,44 @@ __global__ void k_velocity(int64_t n3, const double* __restrict__ x, const doubl
   v[i] = (x[i] - xt[i]) * inv_h;
 }
 
+// BDF2 predictor: x^t kept, x~ = 4/3 x^t - 1/3 x^{t-1} + h (8 v^t - 2 v^{t-1}) / 9.
+__global__ void k_predict_bdf2(int64_t n3, const double* __restrict__ x, const double* __restrict__ v,
+                               const double* __restrict__ xprev, const double* __restrict__ vprev, double h,
+                               double* __restrict__ xt, double* __restrict__ xtilde) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n3) return;
+  xt[i] = x[i];
+  xtilde[i] = (4.0 * x[i] - xprev[i]) / 3.0 + h * (8.0 * v[i] - 2.0 * vprev[i]) / 9.0;
+}
+
+// End of a step: v^{t+1} ((x - x^t)/h, or (3x - 4x^t + x^{t-1})/(2h) for
+// BDF2) and the history shift x^{t-1} <- x^t, v^{t-1} <- v^t.
+__global__ void k_velocity_hist(int64_t n3, const double* __restrict__ x, const double* __restrict__ xt,
+                                double* __restrict__ xprev, double* __restrict__ v, double* __restrict__ vprev,
+                                double h, int bdf2) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n3) return;
+  const double vold = v[i], xp = xprev[i], xo = xt[i];
+  v[i] = bdf2 ? (3.0 * x[i] - 4.0 * xo + xp) / (2.0 * h) : (x[i] - xo) / h;
+  xprev[i] = xo;
+  vprev[i] = vold;
+}
+
 static inline unsigned nblocks(int64_t n, int b) { return unsigned((n + b - 1) / b); }
 
 
 void launch_predict(ms_ctx* c, double dt) {
   c->step_h = dt;  // the friction smoothing length eps_v h uses it
   k_predict<<<nblocks(3 * c->n, 256), 256, 0, c->stream>>>(3 * c->n, c->d_x, c->d_v, dt, c->d_xt, c->d_xtilde);
+}
+void launch_predict_bdf2(ms_ctx* c, double dt) {
+  c->step_h = dt;
+  k_predict_bdf2<<<nblocks(3 * c->n, 256), 256, 0, c->stream>>>(3 * c->n, c->d_x, c->d_v, c->d_xprev, c->d_vprev, dt,
+                                                                c->d_xt, c->d_xtilde);
+}
+void launch_velocity_hist(ms_ctx* c, double dt, bool bdf2) {
+  k_velocity_hist<<<nblocks(3 * c->n, 256), 256, 0, c->stream>>>(3 * c->n, c->d_x, c->d_xt, c->d_xprev, c->d_v,
+                                                                 c->d_vprev, dt, bdf2 ? 1 : 0);
 }
 void launch_apply_dbc(ms_ctx* c, int64_t nd) {
   if (nd == 0) return;

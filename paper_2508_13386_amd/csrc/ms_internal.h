@@ -135,6 +135,10 @@ struct ms_ctx {
   double* d_v = nullptr;
   double* d_xt = nullptr;
   double* d_xtilde = nullptr;
+  // BDF2 history: x^{t-1}, v^{t-1} of the last plain step (valid if has_prev)
+  double* d_xprev = nullptr;
+  double* d_vprev = nullptr;
+  bool has_prev = false;
   double* d_xtrial = nullptr;
   // assembly workspace
   double* d_He = nullptr;     // [T][10][9] FP64
@@ -281,6 +285,8 @@ void launch_dots(ms_ctx* c, const double* a, const double* b, const double* a2, 
                  const double* a3, const double* b3);
 void launch_axpy(ms_ctx* c, double* y, const double* x, double alpha, int64_t len);
 void launch_velocity(ms_ctx* c, double inv_h);
+void launch_predict_bdf2(ms_ctx* c, double dt);
+void launch_velocity_hist(ms_ctx* c, double dt, bool bdf2);
 void launch_cg_init(ms_ctx* c, int prec, double eta_max, double eta_min, bool first, int max_it, int forcing);
 void launch_coarse_correction(ms_ctx* c, int prec, bool from_w);
 void launch_precond_apply(ms_ctx* c, int prec, int pc);

@@ -215,6 +215,7 @@ ms_status paper_step(ms_ctx* c, double dt, const ms_solver_params& P, ms_step_st
   if (!c->has_basis) return fail(c, MS_E_ORDER, "paper mode needs a basis");
   if (c->has_hs && c->hs_mu > 0.0) return fail(c, MS_E_ARG, "paper mode does not support friction");
   set_coarse_f32(c, false);
+  c->has_prev = false;  // no BDF2 history across paper-mode steps
   const double h2 = dt * dt;
   const int prec = P.precision == MS_PREC_MIXED ? MS_PREC_MIXED : MS_PREC_FP64;
   ms_status s;

@@ -81,12 +81,17 @@ ms_status try_move(ms_ctx* c, double h2) {
 
 ms_status plain_step(ms_ctx* c, double dt, const ms_solver_params& P, ms_step_stats* st) {
   const double t0 = now_ms();
-  const double h2 = dt * dt;
+  // BDF2 once a previous step is known (the first step is implicit Euler)
+  const bool bdf2 = P.integrator == 1 && c->has_prev;
+  const double h2 = (bdf2 ? 4.0 / 9.0 : 1.0) * dt * dt;
   int prec = P.precision == MS_PREC_MIXED ? MS_PREC_MIXED : MS_PREC_FP64;
   set_coarse_f32(c, prec == MS_PREC_MIXED);
   const int pc = (P.preconditioner >= 0 && P.preconditioner <= 3) ? P.preconditioner : MS_PC_BLOCK_JACOBI;
   if (two_level(pc) && !c->has_basis) return fail(c, MS_E_ORDER, "two-level preconditioner needs a basis");
-  launch_predict(c, dt);
+  if (bdf2)
+    launch_predict_bdf2(c, dt);
+  else
+    launch_predict(c, dt);
   launch_apply_dbc(c, int64_t(c->h_dbc.size()));
   c->timing = P.time_kernels != 0;
   ms_step_stats S{};
@@ -185,7 +190,8 @@ ms_status plain_step(ms_ctx* c, double dt, const ms_solver_params& P, ms_step_st
     }
   }
   if (!converged) return restore(c, fail(c, MS_E_NOCONV, "Newton did not converge"));
-  launch_velocity(c, 1.0 / dt);
+  launch_velocity_hist(c, dt, bdf2);
+  c->has_prev = true;
   double ef[4];
   if ((s = energy(c, c->d_x, nullptr, 0.0, h2, ef))) return restore(c, s);
   if (c->has_basis && c->mlp) {

@@ -222,3 +222,33 @@ def test_block_jacobi_preconditioner_is_spd(dev):
     assert (za * a)[free].sum() > 0
     assert np.abs(za[~free]).max() == 0.0
     c.close()
+
+
+@pytest.mark.parametrize("scene", ["plain_cube", "sliding_cube"])
+def test_bdf2_trajectory_matches_oracle(dev, scene):
+    """BDF2 (implicit Euler for the first step, which has no history): the
+    GPU trajectory against the oracle's, step by step."""
+    from paper_2508_13386_amd import ms
+    s = scenes.plain_cube(4, seed=3) if scene == "plain_cube" else scenes.sliding_cube(4)
+    c = _ctx(dev, s)
+    body = fem.Body(s["rest"], s["tets"], s["E"], s["nu"], s["rho"])
+    x, v, prev = s["x0"].copy(), s["v0"].copy(), None
+    if scene == "plain_cube":
+        v = 0.5 * np.random.default_rng(2).standard_normal(x.shape)
+        v[s["dirichlet"]] = 0.0
+        c.ms_set_state(x, v)
+    for k in range(1, 5):
+        tgt = s["dbc_targets"](k)
+        xo, vo, _ = newton.newton_step(body, x, v, s["dt"], s["gravity"], s["dirichlet"], tgt,
+                                       halfspace=s["halfspace"], prev=prev)
+        if len(s["dirichlet"]):
+            c.ms_set_dirichlet(s["dirichlet"], tgt)
+        st = c.ms_step(s["dt"], integrator=1)
+        xg, vg = c.ms_get_state()
+        err = e_rel(xg, xo, x)
+        verr = float(np.linalg.norm(vg - vo) / np.linalg.norm(vo))
+        say("bdf2", scene, "step", k, "e_rel", err, "v rel", verr, "newton", st["newton_iters"])
+        assert err <= 1e-6 and verr <= 1e-6
+        prev = (x, v)
+        x, v = xo, vo
+    c.close()
