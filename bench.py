@@ -48,6 +48,8 @@ def parse():
                          "sphere voxelized at --grid^3 falling at 5 m/s onto a rigid half-space; sliding: a "
                          "--grid^3 cube sliding on the half-space with lagged friction (mu = 0.5)")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="mixed")
+    ap.add_argument("--integrator", choices=["euler", "bdf2"], default="euler",
+                    help="implicit Euler or BDF2 (first step implicit Euler) for every form in the run")
     ap.add_argument("--pc", choices=["jacobi", "two_level", "additive", "vcycle"], default="additive")
     ap.add_argument("--handles", type=int, default=192)
     ap.add_argument("--oversample", type=float, default=1.0, help="k-means++ seed oversampling of the basis build")
@@ -586,7 +588,8 @@ def main():
     prec = ms.PREC_MIXED if a.precision == "mixed" else ms.PREC_FP64
     params = ms.solver_defaults(precision=prec, preconditioner=pc, forcing=1, pcg_eta_max=a.eta_max,
                                 pcg_eta_min=a.eta_min, coarse_every=a.coarse_every, coarse_move=a.coarse_move,
-                                mixed_endgame_fp64=a.endgame_fp64, endgame_ratio=a.endgame_ratio)
+                                mixed_endgame_fp64=a.endgame_fp64, endgame_ratio=a.endgame_ratio,
+                                integrator=1 if a.integrator == "bdf2" else 0)
     value, elapsed, stats, states, ctx, basis_s = run(dev, s, params, a.warmup, a.steps,
                                                       handles=a.handles if pc != ms.PC_BLOCK_JACOBI else 0,
                                                       oversample=a.oversample, lattice=a.lattice)
@@ -608,7 +611,8 @@ def main():
     ctx.ms_set_dirichlet(s["dirichlet"], s["dbc_targets"](k))
     tparams = ms.solver_defaults(precision=prec, preconditioner=pc, forcing=1, pcg_eta_max=a.eta_max,
                                  pcg_eta_min=a.eta_min, coarse_every=a.coarse_every, coarse_move=a.coarse_move,
-                                 mixed_endgame_fp64=a.endgame_fp64, endgame_ratio=a.endgame_ratio, time_kernels=1)
+                                 mixed_endgame_fp64=a.endgame_fp64, endgame_ratio=a.endgame_ratio, time_kernels=1,
+                                 integrator=1 if a.integrator == "bdf2" else 0)
     tstat = ctx.ms_step(s["dt"], tparams)
     k_us, k_bytes = ctx.ms_time_kernel(0, kprec, 0)
     # slice height of the chosen layout, from the byte count of the product
@@ -620,14 +624,17 @@ def main():
     S = next(c for c in (16, 32, 64) if -(-n // c) == nslices)
     kernel_name = f"k_cg_spmv<{'double' if vb == 8 else 'float'}, {S}>"
     achieved = k_bytes / (k_us * 1e-6) / 1e9
-    accuracy = None if a.no_accuracy else step_errors(dev, s, ctx, params, a.warmup, a.steps)
+    # the per-step check solves single steps from given states: implicit Euler only
+    accuracy = None if (a.no_accuracy or a.integrator == "bdf2") else step_errors(dev, s, ctx, params, a.warmup,
+                                                                                   a.steps)
     basis = ctx.ms_get_basis() if pc != ms.PC_BLOCK_JACOBI else None
     ctx.close()
 
     ref = None
     if not a.no_reference:
         pref = ms.solver_defaults(precision=ms.PREC_FP64, preconditioner=ms.PC_BLOCK_JACOBI, forcing=1,
-                                  pcg_eta_max=a.eta_max, pcg_eta_min=a.eta_min)
+                                  pcg_eta_max=a.eta_max, pcg_eta_min=a.eta_min,
+                                  integrator=1 if a.integrator == "bdf2" else 0)
         rv, _, rstats, rstates, rctx, _ = run(dev, s, pref, a.warmup, a.steps)
         rctx.close()
         xr, xg = rstates[-1], states[-1]
@@ -640,7 +647,8 @@ def main():
             # the same preconditioner and policy in FP64 throughout, on the
             # same basis: isolates what the mixed-precision form gains
             p64 = ms.solver_defaults(precision=ms.PREC_FP64, preconditioner=pc, forcing=1, pcg_eta_max=a.eta_max,
-                                     pcg_eta_min=a.eta_min, coarse_every=a.coarse_every, coarse_move=a.coarse_move)
+                                     pcg_eta_min=a.eta_min, coarse_every=a.coarse_every, coarse_move=a.coarse_move,
+                                     integrator=1 if a.integrator == "bdf2" else 0)
             fv, _, fstats, fstates, fctx, _ = run(dev, s, p64, a.warmup, a.steps, basis=basis)
             fctx.close()
             ref["fp64_same_preconditioner"] = {
@@ -667,7 +675,7 @@ def main():
                    "precision": a.precision, "preconditioner": a.pc,
                    "handles": a.handles if pc != ms.PC_BLOCK_JACOBI else None, "pcg_eta_max": a.eta_max,
                    "coarse_every": a.coarse_every, "coarse_move": a.coarse_move, "endgame_fp64": a.endgame_fp64,
-                   "endgame_ratio": a.endgame_ratio, "pcg_eta_min": a.eta_min,
+                   "endgame_ratio": a.endgame_ratio, "pcg_eta_min": a.eta_min, "integrator": a.integrator,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kernel_name, f"{a.scene}{a.grid}"),
