@@ -497,11 +497,13 @@ __global__ void k_predict_bdf2(int64_t n3, const double* __restrict__ x, const d
 // BDF2) and the history shift x^{t-1} <- x^t, v^{t-1} <- v^t.
 __global__ void k_velocity_hist(int64_t n3, const double* __restrict__ x, const double* __restrict__ xt,
                                 double* __restrict__ xprev, double* __restrict__ v, double* __restrict__ vprev,
-                                double h, int bdf2) {
+                                double inv_h, int bdf2) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n3) return;
   const double vold = v[i], xp = xprev[i], xo = xt[i];
-  v[i] = bdf2 ? (3.0 * x[i] - 4.0 * xo + xp) / (2.0 * h) : (x[i] - xo) / h;
+  // the implicit-Euler form is the one of k_velocity (same rounding as the
+  // batched steps)
+  v[i] = bdf2 ? (3.0 * x[i] - 4.0 * xo + xp) * (0.5 * inv_h) : (x[i] - xo) * inv_h;
   xprev[i] = xo;
   vprev[i] = vold;
 }
@@ -520,7 +522,7 @@ void launch_predict_bdf2(ms_ctx* c, double dt) {
 }
 void launch_velocity_hist(ms_ctx* c, double dt, bool bdf2) {
   k_velocity_hist<<<nblocks(3 * c->n, 256), 256, 0, c->stream>>>(3 * c->n, c->d_x, c->d_xt, c->d_xprev, c->d_v,
-                                                                 c->d_vprev, dt, bdf2 ? 1 : 0);
+                                                                 c->d_vprev, 1.0 / dt, bdf2 ? 1 : 0);
 }
 void launch_apply_dbc(ms_ctx* c, int64_t nd) {
   if (nd == 0) return;
