@@ -45,3 +45,30 @@ def test_binding_fails_loudly_without_library(monkeypatch):
     monkeypatch.setattr(ms, "_lib", None)
     with pytest.raises(RuntimeError):
         ms.lib()
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """The ctypes mirrors of the parameter and statistics structs have the
+    C layout of include/ms.h (size and offset of every field)."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    from paper_2508_13386_amd import ms
+    structs = [ms.ms_solver_params, ms.ms_step_stats, ms.ms_basis_params]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ms.h"', "int main(void) {"]
+    for st in structs:
+        lines.append(f'  printf("{st.__name__} %zu\\n", sizeof({st.__name__}));')
+        for f, _ in st._fields_:
+            lines.append(f'  printf("{st.__name__}.{f} %zu\\n", offsetof({st.__name__}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(line.split() for line in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                       text=True).stdout.splitlines())
+    for st in structs:
+        assert int(got[st.__name__]) == ctypes.sizeof(st), st.__name__
+        for f, _ in st._fields_:
+            assert int(got[f"{st.__name__}.{f}"]) == getattr(st, f).offset, (st.__name__, f)
