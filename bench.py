@@ -78,6 +78,9 @@ def parse():
     ap.add_argument("--eval-seeds", type=int, default=6)
     ap.add_argument("--traj-grid", type=int, default=16)
     ap.add_argument("--traj-steps", type=int, default=30)
+    ap.add_argument("--traj-kind", choices=["inclusions", "drive"], default="inclusions",
+                    help="learned workload: per-seed inclusions with a 43-handle lattice basis, or one fixed "
+                         "geometry with a per-seed drive and one material-aware 43-handle basis")
     ap.add_argument("--no-reference", action="store_true", help="skip the plain FP64 block-Jacobi run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=200, help="back-to-back replays of the product kernel")
@@ -338,11 +341,25 @@ def learned_main(a):
             print(f"trajectory seed {seed} warm {warm is not None}: {e}", file=sys.stderr, flush=True)
             return None
 
+    fixed_basis = {}
+
     def _trajectory(seed, warm, form):
-        sc = scenes.learned_trajectory_scene(seed, N=a.traj_grid, steps=a.traj_steps)
+        if a.traj_kind == "drive":
+            sc = scenes.learned_drive_scene(seed, N=a.traj_grid, steps=a.traj_steps)
+        else:
+            sc = scenes.learned_trajectory_scene(seed, N=a.traj_grid, steps=a.traj_steps)
         c = ms.context_from_scene(dev, sc)
         try:
-            c.ms_build_basis(n_handles=43, lattice_seeding=1)
+            if a.traj_kind == "drive":
+                # one geometry: one material-aware basis, built once and shared
+                if not fixed_basis:
+                    c.ms_build_basis(n_handles=43)
+                    fixed_basis.update(c.ms_get_basis())
+                else:
+                    c.ms_set_basis(fixed_basis["origins"], fixed_basis["vptr"], fixed_basis["vhandle"],
+                                   fixed_basis["vphi"])
+            else:
+                c.ms_build_basis(n_handles=43, lattice_seeding=1)
             r = 12 * c.ms_get_basis()["m"]
             if warm is not None:
                 c.ms_set_warmstart(*warm)
@@ -411,7 +428,10 @@ def learned_main(a):
         "steps": a.traj_steps * len(rows), "warmup": 0, "ms_per_step": t_warm / (a.traj_steps * len(rows)),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if a.precision == "fp64" else "f32+f64", "data": "synthetic",
-        "config": {"workload": f"heterogeneous block {a.traj_grid}^3, per-seed inclusions, {a.traj_steps} steps",
+        "config": {"workload": f"heterogeneous block {a.traj_grid}^3, "
+                               + ("per-seed inclusions" if a.traj_kind == "inclusions" else
+                                  "one geometry, per-seed drive (0.05-0.15 m over 6-14 steps)")
+                               + f", {a.traj_steps} steps",
                    "handles": r // 12, "train_seeds": len(train), "samples": int(len(Xn)),
                    "network": f"{2 * r}-256-256-{r} SiLU, bf16 products", "parallelism": "single GPU"},
         "training": {"steps": steps, "batch": 128, "lr": 1e-3, "loss_first": float(losses[0]),

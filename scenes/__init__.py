@@ -264,6 +264,20 @@ def learned_trajectory_scene(seed: int, N: int = 32, steps: int = 60):
     return inclusion_block(N=N, seed=seed, steps=steps, ramp_steps=10)
 
 
+def learned_drive_scene(seed: int, N: int = 32, steps: int = 60, geometry_seed: int = 0):
+    """Warm-start trajectories on one fixed heterogeneous block (inclusions
+    from geometry_seed) whose drive varies with `seed`: the top face moves
+    down by an amplitude ~U[0.05, 0.15] m over a ramp of ~U{6..14} steps, then
+    is held.  One geometry keeps the coarse coordinates of a material-aware
+    basis meaningful across trajectories."""
+    rng = np.random.default_rng(seed)
+    drive = float(rng.uniform(0.05, 0.15))
+    ramp = int(rng.integers(6, 15))
+    s = inclusion_block(N=N, seed=geometry_seed, steps=steps, drive=drive, ramp_steps=ramp)
+    s["name"] = f"inclusion_block_{N}_g{geometry_seed}_drive{seed}"
+    return s
+
+
 TRAIN_SEEDS = list(range(1000, 1200))
 HELDOUT_SEEDS = list(range(2000, 2020))
 
