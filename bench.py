@@ -66,11 +66,16 @@ def parse():
     ap.add_argument("--coarse-move", type=float, default=0.2,
                     help="> 0: rebuild U^T H U once the iterate has moved by this fraction of the step's "
                          "displacement since the last rebuild (replaces --coarse-every)")
-    ap.add_argument("--workload", choices=["block32", "batch64", "learned", "spmv_sweep", "paper"], default="block32",
+    ap.add_argument("--workload", choices=["block32", "batch64", "learned", "spmv_sweep", "paper", "cubature"],
+                    default="block32",
                     help="block32: the heterogeneous block (default); batch64: 64 uneven scenes stepped together; "
                          "learned: train the coarse warm start on trajectories and evaluate it on held-out seeds; "
                          "spmv_sweep: the PCG product kernel on the heterogeneous block at --sweep grid sizes; "
-                         "paper: the paper's three-level step (Alg. 1/2) and its error against the exact step")
+                         "paper: the paper's three-level step (Alg. 1/2) and its error against the exact step; "
+                         "cubature: the coarse matrix integrated by modal moment-fitting cubature (Sec. 3.8)")
+    ap.add_argument("--cub-tol", type=float, default=1e-9, help="cubature workload: moment residual tolerance")
+    ap.add_argument("--cub-batch", type=int, default=16,
+                    help="cubature workload: tets drawn initially and per round of the fit")
     ap.add_argument("--sweep", default="32,64,96,128", help="grid sizes of the spmv_sweep workload")
     ap.add_argument("--order", choices=["natural", "random", "rcm"], default="natural",
                     help="vertex numbering of the spmv_sweep meshes")
@@ -198,9 +203,12 @@ def copy_probe(mib):
     print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n, "copies": 5}), flush=True)
 
 
-def run(dev, s, params, warmup, steps, basis=None, handles=0, timed=True, oversample=1.0, lattice=0):
+def run(dev, s, params, warmup, steps, basis=None, handles=0, timed=True, oversample=1.0, lattice=0,
+        cubature=None):
     """Runs warmup + steps timesteps; returns (timesteps/s, per-step stats,
-    states after each timed step, context, basis seconds)."""
+    states after each timed step, context, basis seconds).  cubature =
+    (tets, weights) integrates the elastic part of the coarse matrix by
+    cubature."""
     import torch
 
     from paper_2508_13386_amd import ms
@@ -212,6 +220,9 @@ def run(dev, s, params, warmup, steps, basis=None, handles=0, timed=True, oversa
         t0 = time.perf_counter()
         ctx.ms_build_basis(n_handles=handles, oversample=oversample, lattice_seeding=lattice)
         basis_s = time.perf_counter() - t0
+    if cubature is not None:
+        ctx.ms_set_cubature(*cubature)
+        ctx.ms_set_coarse_integration(ms.COARSE_CUBATURE)
     stats, states = [], []
     for k in range(1, warmup + 1):
         ctx.ms_set_dirichlet(s["dirichlet"], s["dbc_targets"](k))
@@ -525,6 +536,119 @@ def paper_main(a):
                                   "same state (the paper reports about 1e-2)"}), flush=True)
 
 
+def cubature_main(a):
+    """Modal moment-fitting cubature of the coarse matrix (Sec. 3.8, Alg. 3)
+    on the heterogeneous block: the host fit, the coarse-matrix integration
+    time (exact Galerkin product vs cubature), the difference of the two
+    matrices, and the benchmarked plain form with the cubature coarse matrix
+    against the same form with the exact one (timesteps/s, PCG iterations,
+    per-step error).  Then paper mode on the cube with the cubature subspace
+    matrix against exact integration, from the same states."""
+    import scenes
+    from paper_2508_13386_amd import ms
+    dev = ms.TorchDevice(0)
+    prec = ms.PREC_MIXED if a.precision == "mixed" else ms.PREC_FP64
+    s = scenes.inclusion_block(a.grid, seed=0, steps=a.warmup + a.steps + 1)
+    params = ms.solver_defaults(precision=prec, preconditioner=ms.PC_TWO_LEVEL_ADDITIVE, forcing=1,
+                                pcg_eta_max=a.eta_max, pcg_eta_min=a.eta_min, coarse_every=a.coarse_every,
+                                coarse_move=a.coarse_move, mixed_endgame_fp64=a.endgame_fp64,
+                                endgame_ratio=a.endgame_ratio)
+    v_ex, _, st_ex, states_ex, ctx, basis_s = run(dev, s, params, a.warmup, a.steps, handles=a.handles,
+                                                  oversample=a.oversample)
+    print(f"# exact coarse matrix: {v_ex:.3f} timesteps/s", flush=True)
+    basis = ctx.ms_get_basis()
+    t0 = time.perf_counter()
+    worst = ctx.ms_build_cubature(tol=a.cub_tol, n_init=a.cub_batch, n_add=a.cub_batch, seed=0)
+    fit_s = time.perf_counter() - t0
+    tets, w = ctx.ms_get_cubature()
+    print(f"# cubature fit: {len(tets)} of {len(s['tets'])} tets in {fit_s:.1f} s, worst residual {worst:.2e}",
+          flush=True)
+    x_now, _ = ctx.ms_get_state()
+    r = 12 * basis["m"]
+    integ = {}
+    for pname, pr in (("fp64", ms.PREC_FP64), ("mixed", ms.PREC_MIXED)):
+        out = {}
+        for mode_name, mode in (("exact", ms.COARSE_EXACT), ("cubature", ms.COARSE_CUBATURE)):
+            ctx.ms_set_coarse_integration(mode)
+            ctx.ms_eval(x_now, s["dt"], prec=pr, hess=False)
+            K = ctx.ms_get_coarse_matrix(r)
+            us, _ = ctx.ms_time_kernel(6, pr, a.kernel_reps)
+            out[mode_name] = (K, us)
+        Ke, Kc = out["exact"][0], out["cubature"][0]
+        integ[pname] = {"exact_us": out["exact"][1], "cubature_us": out["cubature"][1],
+                        "speedup": out["exact"][1] / out["cubature"][1],
+                        "rel_frobenius_difference": float(np.linalg.norm(Kc - Ke) / np.linalg.norm(Ke)),
+                        "rel_max_difference": float(np.abs(Kc - Ke).max() / np.abs(Ke).max())}
+    ctx.close()
+    print("# coarse-matrix integration: " + json.dumps(integ), flush=True)
+    v_cu, el_cu, st_cu, states_cu, cctx, _ = run(dev, s, params, a.warmup, a.steps, basis=basis,
+                                                 cubature=(tets, w))
+    print(f"# cubature coarse matrix: {v_cu:.3f} timesteps/s", flush=True)
+    accuracy = None if a.no_accuracy else step_errors(dev, s, cctx, params, a.warmup, a.steps)
+    cctx.close()
+    e_forms = float(np.linalg.norm(states_cu[-1] - states_ex[-1]) / np.linalg.norm(states_ex[-1] - s["x0"]))
+    print(json.dumps({
+        "workload": "cubature", "scene": f"heterogeneous block {a.grid}^3, 20 inclusions E=1e10 in E=1e5",
+        "n_verts": len(s["rest"]), "n_tets": len(s["tets"]), "handles": a.handles, "precision": a.precision,
+        "fit": {"points": int(len(tets)), "fraction_of_tets": len(tets) / len(s["tets"]), "seconds": fit_s,
+                "worst_rel_moment_residual": worst, "tol": a.cub_tol, "n_init": a.cub_batch,
+                "n_add": a.cub_batch, "threads": "all hardware threads of the host"},
+        "basis_build_s": basis_s,
+        "coarse_matrix_integration": integ,
+        "steps": a.steps, "warmup": a.warmup,
+        "exact_coarse": {"timesteps_per_s": v_ex, "pcg_iters": [st["pcg_iters"] for st in st_ex],
+                         "newton_iters": [st["newton_iters"] for st in st_ex]},
+        "cubature_coarse": {"timesteps_per_s": v_cu, "ms_per_step": 1e3 * el_cu / a.steps,
+                            "pcg_iters": [st["pcg_iters"] for st in st_cu],
+                            "newton_iters": [st["newton_iters"] for st in st_cu]},
+        "e_rel_final_state_cubature_vs_exact_form": e_forms,
+        "accuracy": accuracy}), flush=True)
+    # paper mode: cubature subspace matrix vs exact integration
+    import torch
+    sp_ = scenes.plain_cube(a.grid, seed=0, steps=a.warmup + a.steps)
+    c = ms.context_from_scene(dev, sp_)
+    c.ms_build_basis(n_handles=a.handles, oversample=a.oversample)
+    t0 = time.perf_counter()
+    worst_p = c.ms_build_cubature(tol=a.cub_tol, n_init=a.cub_batch, n_add=a.cub_batch, seed=0)
+    fit_p = time.perf_counter() - t0
+    npts = len(c.ms_get_cubature()[0])
+    print(f"# paper-mode cube: cubature of {npts} tets in {fit_p:.1f} s", flush=True)
+    pparams = ms.solver_defaults(mode=ms.MODE_PAPER, precision=prec, refine_iters=0, max_newton=100)
+    times = {"exact": [], "cubature": []}
+    errs, iters = [], []
+    x, v = sp_["x0"].copy(), sp_["v0"].copy()
+    for k in range(1, a.warmup + a.steps + 1):
+        c.ms_set_dirichlet(sp_["dirichlet"], sp_["dbc_targets"](k))
+        res = {}
+        for mode_name, mode in (("exact", ms.COARSE_EXACT), ("cubature", ms.COARSE_CUBATURE)):
+            c.ms_set_coarse_integration(mode)
+            c.ms_set_state(x, v)
+            dev.stream.synchronize()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = c.ms_step(sp_["dt"], pparams)
+            dev.stream.synchronize()
+            t1 = time.perf_counter()
+            res[mode_name] = (c.ms_get_state(), st, t1 - t0)
+        if k > a.warmup:
+            for mname in times:
+                times[mname].append(res[mname][2])
+            xe, xc = res["exact"][0][0], res["cubature"][0][0]
+            errs.append(float(np.linalg.norm(xc - xe) / np.linalg.norm(xe - x)))
+            iters.append((res["exact"][1]["newton_iters"], res["cubature"][1]["newton_iters"]))
+        x, v = res["cubature"][0]
+    c.close()
+    print(json.dumps({
+        "workload": "cubature", "scene": f"paper mode, cube {a.grid}^3, per-tet E log-uniform in [1e5, 1e8]",
+        "n_tets": len(sp_["tets"]), "handles": a.handles, "precision": a.precision,
+        "fit": {"points": npts, "fraction_of_tets": npts / len(sp_["tets"]), "seconds": fit_p,
+                "worst_rel_moment_residual": worst_p},
+        "timesteps_per_s": {m: len(t) / sum(t) for m, t in times.items()},
+        "newton_iters_exact_vs_cubature": iters,
+        "e_rel_cubature_step_vs_exact_integration_step": errs,
+        "note": "both steps start from the same state (the cubature trajectory)"}), flush=True)
+
+
 def spmv_sweep_main(a):
     """The PCG product kernel (k_cg_spmv, fused with its dot partials) on the
     Hessian of the heterogeneous block at growing grid sizes: one Newton
@@ -585,6 +709,9 @@ def main():
         return
     if a.workload == "paper":
         paper_main(a)
+        return
+    if a.workload == "cubature":
+        cubature_main(a)
         return
     import scenes
     from paper_2508_13386_amd import ms

@@ -85,6 +85,13 @@ typedef enum {
   MS_PC_TWO_LEVEL_VCYCLE = 3
 } ms_preconditioner;
 typedef enum { MS_MODE_PLAIN = 0, MS_MODE_PAPER = 1 } ms_mode;
+/* How the coarse (subspace) matrix U^T H U is integrated (Sec. 3.8):
+ *   MS_COARSE_EXACT      every tet's elastic Hessian (the Galerkin product)
+ *   MS_COARSE_CUBATURE   the elastic part from the installed cubature only,
+ *                        h^2 sum_q (w_q / V_q) U_q^T H_q U_q; inertia, barrier
+ *                        and friction curvature stay exact.  Symmetric
+ *                        positive semi-definite for non-negative weights. */
+typedef enum { MS_COARSE_EXACT = 0, MS_COARSE_CUBATURE = 1 } ms_coarse_integration;
 
 /* Parameters of one timestep solve.  ms_solver_defaults() fills them. */
 typedef struct {
@@ -270,6 +277,55 @@ ms_status ms_basis_get(const ms_basis* b, int32_t* m, int64_t* nnz, double* orig
                        int32_t* vhandle, double* vphi, int32_t* part);
 void ms_basis_free(ms_basis* b);
 
+/* Modal moment-fitting cubature (Sec. 3.8, modal moment fitting and its
+ * solver; Alg. 3), host-only (no device involved).  Per partition p
+ * (tets with part[t] == p, part [T] >= 0): the basis functions touching p,
+ * evaluated per tet as the mean of their vertex weights, give the degree-2
+ * moment conditions (1, u_i, u_i u_j for i <= j) with targets the
+ * volume-weighted sums over all of p's tets.  Starting from n_init tets
+ * drawn uniformly, non-negative least squares is solved on the drawn tets;
+ * while the relative residual exceeds tol and rounds remain (at most
+ * max_rounds), n_add more tets are drawn with probability proportional to
+ * (A_k^T r)^2.  Draws use SplitMix64 as a counter-based generator of `seed`
+ * (draw j of partition p: state seed + (2^32 p + j + 1) * 0x9E3779B97F4A7C15).
+ * The basis is given as in ms_set_basis (vptr [n+1], vhandle / vphi
+ * [vptr[n]], handles < m).  n_threads <= 0 uses every hardware thread.
+ * *out receives an opaque result that ms_cubature_get queries (first with
+ * null arrays for *n_pts, then with tets / weights of n_pts entries: the
+ * selected tets ascending and their weights in volume units) and
+ * ms_cubature_free releases.  Errors: MS_E_ARG. */
+typedef struct ms_cubature ms_cubature;
+ms_status ms_cubature_compute(int64_t n, const double* rest_xyz, int64_t T, const int32_t* tets,
+                              const int32_t* part, int32_t m, const int64_t* vptr, const int32_t* vhandle,
+                              const double* vphi, double tol, int32_t n_init, int32_t n_add, int32_t max_rounds,
+                              uint64_t seed, int32_t n_threads, ms_cubature** out);
+ms_status ms_cubature_get(const ms_cubature* q, int64_t* n_pts, int32_t* tets, double* weights,
+                          double* max_rel_residual);
+void ms_cubature_free(ms_cubature* q);
+
+/* The same fit on the context's mesh and installed basis (which must carry
+ * its partitioning, i.e. come from ms_build_basis), installed as by
+ * ms_set_cubature.  max_rel_residual (may be NULL) receives the largest
+ * relative moment residual over the partitions.  Errors: MS_E_ORDER (no
+ * basis or no partitioning), MS_E_ARG. */
+ms_status ms_build_cubature(ms_ctx* c, double tol, int32_t n_init, int32_t n_add, int32_t max_rounds,
+                            uint64_t seed, double* max_rel_residual);
+
+/* Install a cubature: n_pts distinct tets [n_pts] with weights >= 0 in
+ * volume units (copied).  n_pts = 0 removes it (and selects
+ * MS_COARSE_EXACT).  Errors: MS_E_ORDER (no mesh), MS_E_ARG (a tet out of
+ * range or repeated, a negative or non-finite weight). */
+ms_status ms_set_cubature(ms_ctx* c, int64_t n_pts, const int32_t* tets, const double* weights);
+
+/* Query the installed cubature: *n_pts, then, if non-null, tets [n_pts]
+ * (ascending) and weights [n_pts]. */
+ms_status ms_get_cubature(const ms_ctx* c, int64_t* n_pts, int32_t* tets, double* weights);
+
+/* Select how every later coarse matrix (two-level preconditioners, paper
+ * mode's subspace level, ms_eval) is integrated (ms_coarse_integration).
+ * Errors: MS_E_ARG, MS_E_ORDER (MS_COARSE_CUBATURE without a cubature). */
+ms_status ms_set_coarse_integration(ms_ctx* c, int32_t mode);
+
 /* Advance one timestep of size dt (s) with parameters p (NULL = defaults);
  * stats may be NULL.  Transactional: on any error x and v are unchanged.
  * Errors: MS_E_ORDER, MS_E_NOCONV, MS_E_LINESEARCH, MS_E_NONFINITE,
@@ -361,7 +417,10 @@ ms_status ms_get_coarse_matrix(ms_ctx* c, double* A);
  * on the current buffers: 1 the update (p, s, d, r, u), 2 the restriction
  * c = U^T r, 3 the coarse GEMV e = A^-1 c, 4 the prolongation u += U e,
  * 5 one whole iteration (bytes 0: not a single kernel).  These overwrite
- * the PCG vectors.
+ * the PCG vectors.  kernel 6 (reps > 0) replays the integration of the
+ * coarse matrix U^T H U on the last assembled Hessian with the selected
+ * ms_coarse_integration (bytes 0); it leaves the coarse factor to be
+ * rebuilt by the next step.
  * Errors: MS_E_ORDER (nothing assembled / recorded yet, or no basis for
  * 2..4), MS_E_ARG. */
 ms_status ms_time_kernel(ms_ctx* c, int32_t kernel, int32_t prec, int32_t reps, double* avg_us, double* bytes);

@@ -34,6 +34,7 @@ from __future__ import annotations
 import numpy as np
 import scipy.sparse as sp
 
+from .cubature import cubature_galerkin
 from .fem import Body, StepProblem, barrier_d2
 from .linops import dense_basis
 from .newton import LineSearchError, ccd_bound
@@ -87,12 +88,14 @@ def block_jacobi_pcg(A, b, n_iter):
     return x
 
 
-def subspace_direction(H, g, Ua, Us):
-    """Alg. 2's SolveSubspaceDirection: returns (affine part, d_s)."""
+def subspace_direction(H, g, Ua, Us, Ks=None):
+    """Alg. 2's SolveSubspaceDirection: returns (affine part, d_s).  Ks, if
+    given, replaces the subspace matrix U_s^T H U_s (the cubature-integrated
+    one of Sec. 3.8)."""
     qa = _solve_reg(Ua.T @ (H @ Ua), -(Ua.T @ g))
     da = Ua @ qa
     r = -g - H @ da
-    qs = _solve_reg(Us.T @ (H @ Us), Us.T @ r)
+    qs = _solve_reg(Us.T @ (H @ Us) if Ks is None else Ks, Us.T @ r)
     return da, da + Us @ qs
 
 
@@ -119,9 +122,10 @@ def basis_matrices(body: Body, basis, pinned):
 
 
 def paper_step(body: Body, x_t, v_t, h, gravity, dbc, dbc_target, halfspace, basis, eps=1e-3, refine_iters=20,
-               window=3, threshold=0.5, gap=5, max_newton=50, max_bt=30, record=None):
+               window=3, threshold=0.5, gap=5, max_newton=50, max_bt=30, record=None, cubature=None):
     """One timestep; basis = dict(origins, vptr, vhandle, vphi, m).  Returns
-    (x, v, info)."""
+    (x, v, info).  cubature = (tets, weights) integrates the elastic part of
+    the subspace matrix by cubature (Sec. 3.8) instead of exactly."""
     x_t = np.asarray(x_t, dtype=np.float64)
     prob = StepProblem(body, x_t, v_t, h, gravity, halfspace)
     n = body.n
@@ -151,7 +155,8 @@ def paper_step(body: Body, x_t, v_t, h, gravity, dbc, dbc_target, halfspace, bas
             refreshes += 1
         Hlag = (Hlag_base + B).tocsr()
         # affine, then sparse subspace level
-        _, ds = subspace_direction(H, g, Ua, Us)
+        Ks = None if cubature is None else cubature_galerkin(prob, x, Us, cubature[0], cubature[1])
+        _, ds = subspace_direction(H, g, Ua, Us, Ks)
         # full-space refinement on the lagged Hessian
         rf = -g - H @ ds
         idx = np.nonzero(fmask)[0]

@@ -178,6 +178,8 @@ ms_status pcg_solve(ms_ctx* c, int prec, int pc, double eta_max, double eta_min,
 ms_status assemble(ms_ctx* c, const double* x, double h2, int prec, bool project, bool need_pc, int pc,
                    bool refresh_coarse) {
   c->assembled[prec == MS_PREC_FP64 ? 0 : 1] = true;
+  c->asm_x = x;
+  c->asm_h2 = h2;
   launch_element(c, x, h2, prec, true, project);
   launch_gather_grad(c, x, h2, c->d_g);
   launch_gather_hess(c, x, h2, prec);
@@ -187,7 +189,7 @@ ms_status assemble(ms_ctx* c, const double* x, double h2, int prec, bool project
     else
       launch_block_jacobi(c, prec);
     if (two_level(pc) && (refresh_coarse || !c->coarse_valid)) {
-      ms_status s = launch_galerkin(c, prec);
+      ms_status s = launch_galerkin(c, prec, x, h2);
       if (s) return s;
       s = coarse_factor(c);
       if (s) return s;
@@ -373,7 +375,7 @@ ms_status ms_set_dirichlet(ms_ctx* c, int64_t nd, const int32_t* verts, const do
     MS_HIP(hipMemcpyAsync(c->d_dbc_tgt, tgt, 3 * nd * sizeof(double), hipMemcpyHostToDevice, c->stream));
   }
   MS_HIP(hipMemcpyAsync(c->d_pinned, pin.data(), c->n, hipMemcpyHostToDevice, c->stream));
-  if (!same) c->coarse_valid = 0;
+  if (!same) c->coarse_valid = 0, c->cub.built = false;
   return sync(c);
 }
 
@@ -450,7 +452,7 @@ ms_status ms_eval(ms_ctx* c, const double* x, double dt, int32_t prec, double* e
   ms_status s = assemble(c, c->d_xtrial, h2, prec, true, true, MS_PC_BLOCK_JACOBI, true);
   if (s) return s;
   if (c->has_basis) {
-    if ((s = launch_galerkin(c, prec))) return s;
+    if ((s = launch_galerkin(c, prec, c->d_xtrial, h2))) return s;
     if ((s = coarse_factor(c))) return s;
   }
   double parts[4];
@@ -567,7 +569,7 @@ ms_status ms_mat_spmv(ms_mat* A, const void* x, void* y) {
 double ms_mat_bytes(const ms_mat* A) { return A ? A->bytes : 0.0; }
 
 ms_status ms_time_kernel(ms_ctx* c, int32_t kernel, int32_t prec, int32_t reps, double* avg_us, double* bytes) {
-  if (!c || !avg_us || !bytes || reps < 0 || kernel < 0 || kernel > 5 || (prec != MS_PREC_FP64 && prec != MS_PREC_MIXED))
+  if (!c || !avg_us || !bytes || reps < 0 || kernel < 0 || kernel > 6 || (prec != MS_PREC_FP64 && prec != MS_PREC_MIXED))
     return MS_E_ARG;
   if (!c->assembled[prec == MS_PREC_FP64 ? 0 : 1]) return fail(c, MS_E_ORDER, "no Hessian assembled in that precision");
   if (reps == 0) {
@@ -579,6 +581,7 @@ ms_status ms_time_kernel(ms_ctx* c, int32_t kernel, int32_t prec, int32_t reps, 
     c->timed_n[q] = 0;
     return MS_OK;
   }
+  if (kernel == 6) return time_coarse_matrix(c, prec, reps, avg_us, bytes);
   if (kernel > 0) {
     if (reps == 0) return fail(c, MS_E_ARG, "in-loop timing is recorded for kernel 0 only");
     return time_loop_kernel(c, kernel, prec, reps, avg_us, bytes);

@@ -20,6 +20,7 @@
 #include <map>
 #include <type_traits>
 
+#include "contact.h"
 #include "ms_internal.h"
 #include "reduce.h"
 
@@ -311,6 +312,85 @@ __global__ void __launch_bounds__(256) k_galerkin_a(int r, const int32_t* __rest
     A[int64_t(row) * r + col] = acc;
     if (i != j) A[int64_t(col) * r + row] = acc;
   }
+}
+
+// Cubature stage 1 (Sec. 3.8): one thread per row of Z, written in the
+// layout of k_galerkin_z so that k_galerkin_a forms U^T Z.  Element rows
+// (tet t, local vertex a, handle j): Z = h^2 (w_t / V_t) sum_b H_t[a,b] (x) W_bj
+// over the tet's unpinned vertices b carrying j; vertex rows (v, j):
+// Z = (m_v I + h^2 (kappa b''(d_v) n n^T + D''_v)) (x) W_vj.
+template <typename HT>
+__global__ void __launch_bounds__(256) k_cub_z(int64_t nz, const int4* __restrict__ info,
+                                               const double* __restrict__ scale, const int32_t* __restrict__ ent,
+                                               const HT* __restrict__ He, const double* __restrict__ vw,
+                                               const double* __restrict__ mass, const double* __restrict__ x,
+                                               double h2, HalfSpace hs, double* __restrict__ Z) {
+  const int64_t z = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (z >= nz) return;
+  const int4 in = info[z];
+  double acc[36];
+#pragma unroll
+  for (int q = 0; q < 36; ++q) acc[q] = 0.0;
+  if (in.x >= 0) {
+    const int a = in.y;
+    for (int e = in.z; e < in.w; ++e) {
+      const int b = ent[2 * e];
+      const double* w = vw + 4 * int64_t(ent[2 * e + 1]);
+      const int lo = min(a, b), hi = max(a, b);
+      const HT* blk = He + 90 * int64_t(in.x) + 9 * (4 * lo - (lo * (lo - 1)) / 2 + (hi - lo));
+      double hb[9];
+      if (a <= b) {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) hb[q] = double(blk[q]);
+      } else {
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int j = 0; j < 3; ++j) hb[3 * i + j] = double(blk[3 * j + i]);
+      }
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+          for (int l = 0; l < 4; ++l) acc[12 * i + 4 * j + l] += hb[3 * i + j] * w[l];
+    }
+    const double sc = h2 * scale[z];
+#pragma unroll
+    for (int q = 0; q < 36; ++q) acc[q] *= sc;
+  } else {
+    const int64_t v = -1 - int64_t(in.x);
+    double D[9];
+    const double m = mass[v];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) D[q] = (q % 4 == 0) ? m : 0.0;
+    if (hs.on) {
+      const double y[3] = {x[3 * v], x[3 * v + 1], x[3 * v + 2]};
+      double b, b1, b2;
+      barrier_terms(hs.n[0] * y[0] + hs.n[1] * y[1] + hs.n[2] * y[2] - hs.off, hs.dhat, b, b1, b2);
+      const double f = h2 * hs.kappa * b2;
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) D[3 * i + j] += f * hs.n[i] * hs.n[j];
+      if (hs.mu > 0.0) {
+        double gf[3], Hf[9];
+        friction_terms(hs, v, y, gf, Hf);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) D[q] += h2 * Hf[q];
+      }
+    }
+    const double* w = vw + 4 * int64_t(in.y);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int l = 0; l < 4; ++l) acc[12 * i + 4 * j + l] = D[3 * i + j] * w[l];
+  }
+  double* out = Z + 36 * z;
+#pragma unroll
+  for (int q = 0; q < 36; ++q) out[q] = acc[q];
 }
 
 // ---------------------------------------------------------------------------
@@ -607,6 +687,7 @@ ms_status install_basis(ms_ctx* c, Basis&& B) {
   c->rp = rp;
   c->has_basis = true;
   c->coarse_valid = 0;
+  c->cub.built = false;
   for (auto& row : c->cg_graph)
     for (int pc = 1; pc < 4; ++pc)
       if (row[pc]) {
@@ -616,8 +697,59 @@ ms_status install_basis(ms_ctx* c, Basis&& B) {
   return sync(c);
 }
 
-ms_status launch_galerkin(ms_ctx* c, int prec) {
+// Coarse matrix with the elastic part integrated by the installed cubature.
+static ms_status launch_galerkin_cubature(ms_ctx* c, int prec, const double* x, double h2) {
+  Cubature& C = c->cub;
+  if (!C.present) return fail(c, MS_E_ORDER, "no cubature installed");
+  if (!C.built) {
+    ms_status s = build_cubature_lists(c);
+    if (s) return s;
+  }
+  MS_HIP(hipMemsetAsync(c->d_Ac, 0, size_t(c->r) * c->r * sizeof(double), c->stream));
+  if (C.nz > 0) {
+    if (prec == MS_PREC_FP64)
+      k_cub_z<double><<<nblocks(C.nz, 256), 256, 0, c->stream>>>(C.nz, C.d_info, C.d_scale, C.d_ent, c->d_He,
+                                                                 c->basis.d_vw, c->d_mass, x, h2, hs_of(c), C.d_Z);
+    else
+      k_cub_z<float><<<nblocks(C.nz, 256), 256, 0, c->stream>>>(C.nz, C.d_info, C.d_scale, C.d_ent, c->d_He32,
+                                                                c->basis.d_vw, c->d_mass, x, h2, hs_of(c), C.d_Z);
+  }
+  if (C.npairs > 0)
+    k_galerkin_a<<<unsigned(C.npairs), 256, 0, c->stream>>>(c->r, C.d_pair_ij, C.d_pair_ptr, C.d_pair_ent,
+                                                           c->basis.d_vw, C.d_Z, c->d_Ac);
+  return MS_OK;
+}
+
+// Average duration of the coarse-matrix integration (exact Galerkin or
+// cubature, whichever is selected) on the last assembled Hessian, over reps
+// back-to-back launches bracketed by events on the library stream.
+ms_status time_coarse_matrix(ms_ctx* c, int prec, int reps, double* avg_us, double* bytes) {
   if (!c->has_basis) return fail(c, MS_E_ORDER, "no basis");
+  if (reps < 1) return fail(c, MS_E_ARG, "the coarse matrix is timed by replays (reps >= 1)");
+  if (!c->asm_x) return fail(c, MS_E_ORDER, "nothing assembled yet");
+  ms_status s = launch_galerkin(c, prec, c->asm_x, c->asm_h2);  // builds the cubature lists if needed
+  if (s) return s;
+  hipEvent_t e0, e1;
+  MS_HIP(hipEventCreate(&e0));
+  MS_HIP(hipEventCreate(&e1));
+  MS_HIP(hipEventRecord(e0, c->stream));
+  for (int k = 0; k < reps && !s; ++k) s = launch_galerkin(c, prec, c->asm_x, c->asm_h2);
+  MS_HIP(hipEventRecord(e1, c->stream));
+  MS_HIP(hipEventSynchronize(e1));
+  float ms = 0.0f;
+  MS_HIP(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (s) return s;
+  *avg_us = 1e3 * double(ms) / reps;
+  *bytes = 0.0;
+  c->coarse_valid = 0;  // the factor no longer matches a freshly integrated matrix
+  return MS_OK;
+}
+
+ms_status launch_galerkin(ms_ctx* c, int prec, const double* x, double h2) {
+  if (!c->has_basis) return fail(c, MS_E_ORDER, "no basis");
+  if (c->coarse_mode == MS_COARSE_CUBATURE) return launch_galerkin_cubature(c, prec, x, h2);
   Basis& D = c->basis;
   MS_HIP(hipMemsetAsync(c->d_Ac, 0, size_t(c->r) * c->r * sizeof(double), c->stream));
   if (D.nz > 0) {

@@ -44,6 +44,31 @@ struct Pattern {
   std::vector<int32_t> h_slice_base;
 };
 
+// Cubature of the elastic part of the coarse matrix (Sec. 3.8): the selected
+// tets with their weights and the device lists of its two-stage product.
+struct Cubature {
+  std::vector<int32_t> tets;     // ascending
+  std::vector<double> w;         // weights (volume units)
+  bool present = false;
+  bool built = false;            // device lists match the basis and Dirichlet set
+  int64_t nz = 0;                // stage-1 rows
+  int4* d_info = nullptr;        // [nz] {tet, local a, first, end} or {-1 - v, k_v, 0, 0}
+  double* d_scale = nullptr;     // [nz] w / V of the row's tet
+  int32_t* d_ent = nullptr;      // [L][2] (local b, k_b)
+  double* d_Z = nullptr;         // [nz][36]
+  int32_t npairs = 0;
+  int32_t* d_pair_ij = nullptr;  // [npairs][2]
+  int32_t* d_pair_ptr = nullptr; // [npairs+1]
+  int32_t* d_pair_ent = nullptr; // [L2][2] (k_v, z)
+};
+
+struct CubatureParams {
+  double tol;
+  int32_t n_init, n_add, max_rounds;
+  uint64_t seed;
+  int32_t n_threads;
+};
+
 struct Basis {
   int32_t m = 0;
   int64_t nnz = 0;
@@ -186,6 +211,11 @@ struct ms_ctx {
   float* d_Ac32 = nullptr;    // FP32 Galerkin accumulation
   double* d_cpart = nullptr;  // coarse restriction partials
   int coarse_valid = 0;
+  // coarse matrix: exact Galerkin product or the cubature of its elastic part
+  ms::Cubature cub;
+  int coarse_mode = MS_COARSE_EXACT;
+  const double* asm_x = nullptr;  // positions and h^2 of the last assembly
+  double asm_h2 = 0.0;
   // learned warm start
   Mlp* mlp = nullptr;
   std::vector<double> q_prev, q_cur;  // last two coarse states
@@ -312,7 +342,13 @@ ms_status time_loop_kernel(ms_ctx* c, int kernel, int prec, int reps, double* av
 void launch_cg_iteration(ms_ctx* c, int prec, int pc, int parity, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 void launch_precond(ms_ctx* c, int pc, int prec, const double* r, double* z);
 void launch_spmv(ms_ctx* c, int prec, const double* x, double* y);
-ms_status launch_galerkin(ms_ctx* c, int prec);
+ms_status launch_galerkin(ms_ctx* c, int prec, const double* x, double h2);
+ms_status time_coarse_matrix(ms_ctx* c, int prec, int reps, double* avg_us, double* bytes);
+ms_status fit_cubature_host(int64_t n, const double* rest, int64_t T, const int32_t* tets, const int32_t* part,
+                            const int64_t* vptr, const int32_t* vhandle, const double* vphi,
+                            const CubatureParams& P, std::vector<int32_t>& sel, std::vector<double>& wts,
+                            double* max_rel);
+ms_status build_cubature_lists(ms_ctx* c);
 ms_status coarse_factor(ms_ctx* c);
 int coarse_pad(int r);
 void launch_extract_bsr(ms_ctx* c, const int64_t* slot_of_bsr_dev, int64_t nnzb, double* out, int prec);

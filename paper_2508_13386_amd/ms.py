@@ -20,6 +20,7 @@ MS_OK, MS_E_ARG, MS_E_MESH, MS_E_ORDER, MS_E_DEVICE, MS_E_NOMEM, MS_E_NOCONV, MS
 PREC_FP64, PREC_MIXED = 0, 1
 PC_BLOCK_JACOBI, PC_TWO_LEVEL, PC_TWO_LEVEL_ADDITIVE, PC_TWO_LEVEL_VCYCLE = 0, 1, 2, 3
 MODE_PLAIN, MODE_PAPER = 0, 1
+COARSE_EXACT, COARSE_CUBATURE = 0, 1
 
 _ALLOC = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 _FREE = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
@@ -109,6 +110,13 @@ def lib():
             "ms_energy_difference": [vp, dp, dp, d, d, dp],
             "ms_basis_compute": [i64, dp, i64, ip, dp, i64, ip, C.POINTER(ms_basis_params), C.POINTER(C.c_void_p)],
             "ms_basis_get": [vp, C.POINTER(i32), C.POINTER(i64), dp, ip, ip, dp, ip],
+            "ms_cubature_compute": [i64, dp, i64, ip, ip, i32, ip, ip, dp, d, i32, i32, i32, C.c_uint64, i32,
+                                    C.POINTER(C.c_void_p)],
+            "ms_cubature_get": [vp, C.POINTER(i64), ip, dp, C.POINTER(d)],
+            "ms_build_cubature": [vp, d, i32, i32, i32, C.c_uint64, C.POINTER(d)],
+            "ms_set_cubature": [vp, i64, ip, dp],
+            "ms_get_cubature": [vp, C.POINTER(i64), ip, dp],
+            "ms_set_coarse_integration": [vp, i32],
             "ms_mlp_forward": [C.POINTER(ms_device), i32, i32, i32, vp, i64, vp, vp],
             "ms_mlp_train": [C.POINTER(ms_device), i32, i32, i32, vp, i64, vp, vp, i32, i32, vp, C.c_float, vp, vp],
         }
@@ -122,6 +130,8 @@ def lib():
         L.ms_mat_destroy.restype = None
         L.ms_basis_free.argtypes = [vp]
         L.ms_basis_free.restype = None
+        L.ms_cubature_free.argtypes = [vp]
+        L.ms_cubature_free.restype = None
         L.ms_destroy.argtypes = [vp]
         L.ms_destroy.restype = None
         L.ms_last_error.argtypes = [vp]
@@ -285,6 +295,28 @@ class Context:
         self._check(self.L.ms_get_basis(self.h, _ptr(o), _ptr(vp), _ptr(vh), _ptr(w), _ptr(part)))
         return dict(origins=o, vptr=vp, vhandle=vh, vphi=w, part=part, m=m.value)
 
+    # -- cubature of the coarse matrix (Sec. 3.8) --------------------------------
+    def ms_build_cubature(self, tol=1e-9, n_init=16, n_add=16, max_rounds=64, seed=0):
+        res = C.c_double()
+        self._check(self.L.ms_build_cubature(self.h, float(tol), int(n_init), int(n_add), int(max_rounds),
+                                             int(seed), C.byref(res)))
+        return res.value
+
+    def ms_set_cubature(self, tets, weights):
+        t, w = _i32(tets), _f64(weights)
+        self._check(self.L.ms_set_cubature(self.h, len(t), _ptr(t) if len(t) else None, _ptr(w) if len(w) else None))
+
+    def ms_get_cubature(self):
+        n = C.c_int64()
+        self._check(self.L.ms_get_cubature(self.h, C.byref(n), None, None))
+        t = np.empty(n.value, dtype=np.int32)
+        w = np.empty(n.value)
+        self._check(self.L.ms_get_cubature(self.h, C.byref(n), _ptr(t), _ptr(w)))
+        return t, w
+
+    def ms_set_coarse_integration(self, mode):
+        self._check(self.L.ms_set_coarse_integration(self.h, int(mode)))
+
     # -- stepping ---------------------------------------------------------------
     def ms_step(self, dt, params=None, **kw):
         p = params or solver_defaults(**kw)
@@ -385,6 +417,32 @@ def ms_basis_compute(rest, tets, E, dbc=(), params=None, **kw):
     finally:
         L.ms_basis_free(h)
     return dict(origins=o, vptr=vp, vhandle=vh, vphi=w, part=part, m=m.value)
+
+
+def ms_cubature_compute(rest, tets, part, basis, tol=1e-9, n_init=16, n_add=16, max_rounds=64, seed=0,
+                        n_threads=0):
+    """Host-only cubature fit (Alg. 3); basis = dict(m, vptr, vhandle, vphi).
+    Returns (tets ascending, weights, largest relative moment residual)."""
+    L = lib()
+    rest, tets, part = _f64(rest), _i32(tets), _i32(part)
+    vp = np.ascontiguousarray(basis["vptr"], dtype=np.int64)
+    vh, w = _i32(basis["vhandle"]), _f64(basis["vphi"])
+    h = C.c_void_p()
+    code = L.ms_cubature_compute(len(rest), _ptr(rest), len(tets), _ptr(tets), _ptr(part), int(basis["m"]),
+                                 _ptr(vp), _ptr(vh), _ptr(w), float(tol), int(n_init), int(n_add),
+                                 int(max_rounds), int(seed), int(n_threads), C.byref(h))
+    if code != MS_OK:
+        raise MSError(code, "ms_cubature_compute")
+    try:
+        n = C.c_int64()
+        res = C.c_double()
+        L.ms_cubature_get(h, C.byref(n), None, None, None)
+        t = np.empty(n.value, dtype=np.int32)
+        wt = np.empty(n.value)
+        L.ms_cubature_get(h, C.byref(n), _ptr(t), _ptr(wt), C.byref(res))
+    finally:
+        L.ms_cubature_free(h)
+    return t, wt, res.value
 
 
 MLP_KEYS = ("W0", "b0", "W1", "b1", "W2", "b2")

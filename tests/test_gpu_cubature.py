@@ -1,0 +1,150 @@
+"""GPU parity of the cubature-integrated coarse matrix (Sec. 3.8) against the
+oracle, the library's own fit checked by the oracle's moment conditions, and
+steps that use the cubature coarse matrix: plain two-level PCG (which still
+reaches the exact minimiser) and paper mode (against the paper-mode oracle
+given the same cubature)."""
+import numpy as np
+import pytest
+
+import scenes
+from oracle import cubature as cub
+from oracle import fem, newton, paper
+from tests.gpu_util import device, e_rel, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return device()
+
+
+def _ctx(dev, s, m, seed=1):
+    from paper_2508_13386_amd import ms
+    c = ms.context_from_scene(dev, s)
+    c.ms_build_basis(n_handles=m, seed=seed)
+    return c, c.ms_get_basis()
+
+
+def _eval_state(s, seed):
+    rng = np.random.default_rng(seed)
+    if s["halfspace"] is None:
+        return s["x0"] + 0.002 * rng.standard_normal(s["x0"].shape)
+    # tangential slip on both sides of the friction smoothing length, normal
+    # offsets inside the barrier's range
+    eh = s["halfspace"]["eps_v"] * s["dt"]
+    u = rng.standard_normal(s["rest"].shape) * np.array([1.0, 1.0, 0.0])
+    scale = np.where(np.arange(len(u)) % 2 == 0, 0.3 * eh, 5.0 * eh)
+    x = s["x0"] + u / np.linalg.norm(u, axis=1)[:, None] * scale[:, None]
+    x[:, 2] += 1e-4 * rng.uniform(-1.0, 1.0, len(x))
+    return x
+
+
+@pytest.mark.parametrize("name,prec_name", [("block", "fp64"), ("block", "mixed"), ("sliding", "fp64")])
+def test_cubature_coarse_matrix_matches_oracle(dev, name, prec_name):
+    from paper_2508_13386_amd import ms
+    prec = ms.PREC_MIXED if prec_name == "mixed" else ms.PREC_FP64
+    s = scenes.inclusion_block(6, seed=0, steps=3) if name == "block" else scenes.sliding_cube(4)
+    c, B = _ctx(dev, s, 8)
+    t, w, res = cub.fit_cubature(s["rest"], s["tets"], B["part"], B, seed=4, n_init=8, n_add=8)
+    say("cubature", name, prec_name, "points", len(t), "of", len(s["tets"]), "worst residual", max(res.values()))
+    c.ms_set_cubature(t, w)
+    tg, wg = c.ms_get_cubature()
+    assert np.array_equal(tg, t) and np.array_equal(wg, w)
+    c.ms_set_coarse_integration(ms.COARSE_CUBATURE)
+    x = _eval_state(s, 3)
+    c.ms_eval(x, s["dt"], prec=prec, hess=False)
+    K = c.ms_get_coarse_matrix(12 * B["m"])
+    body = fem.Body(s["rest"], s["tets"], s["E"], s["nu"], s["rho"])
+    pinned = np.zeros(len(x), bool)
+    pinned[s["dirichlet"]] = True
+    Us, _ = paper.basis_matrices(body, B, pinned)
+    prob = fem.StepProblem(body, s["x0"], s["v0"], s["dt"], s["gravity"], s["halfspace"])
+    Kref = cub.cubature_galerkin(prob, x, Us, t, w)
+    # FP64 element Hessians: round-off only; mixed: FP32 element Hessians
+    tol = 1e-12 if prec_name == "fp64" else 1e-6
+    err = np.abs(K - Kref).max() / np.abs(Kref).max()
+    say("  max |K - K_oracle| / max |K|", err)
+    assert err <= tol
+    # every tet with weight V: the exact Galerkin matrix of the same run
+    c.ms_set_cubature(np.arange(len(s["tets"]), dtype=np.int32), body.vol)
+    c.ms_eval(x, s["dt"], prec=prec, hess=False)
+    Kf = c.ms_get_coarse_matrix(12 * B["m"])
+    c.ms_set_coarse_integration(ms.COARSE_EXACT)
+    c.ms_eval(x, s["dt"], prec=prec, hess=False)
+    Ke = c.ms_get_coarse_matrix(12 * B["m"])
+    # (mixed: the exact product reads the FP32-rounded assembled blocks)
+    assert np.abs(Kf - Ke).max() <= tol * np.abs(Ke).max()
+    c.close()
+
+
+def test_library_fit_meets_moment_conditions(dev):
+    from paper_2508_13386_amd import ms
+    s = scenes.inclusion_block(8, seed=1, steps=1)
+    c, B = _ctx(dev, s, 12)
+    worst = c.ms_build_cubature(tol=1e-9, n_init=8, n_add=8, seed=5)
+    t, w = c.ms_get_cubature()
+    r = cub.moment_residuals(s["rest"], s["tets"], B["part"], B, t, w)
+    say("library fit: points", len(t), "of", len(s["tets"]), "worst", worst, "oracle check", max(r.values()))
+    assert max(r.values()) <= 1e-9 and np.all(w > 0.0)
+    assert worst == pytest.approx(max(r.values()), rel=1e-3, abs=1e-15)
+    # without a cubature the mode cannot be selected; removing it restores exact
+    c.ms_set_cubature(np.zeros(0, np.int32), np.zeros(0))
+    with pytest.raises(ms.MSError):
+        c.ms_set_coarse_integration(ms.COARSE_CUBATURE)
+    c.close()
+
+
+@pytest.mark.parametrize("prec_name,pc", [("fp64", "additive"), ("mixed", "additive"), ("fp64", "deflated")])
+def test_steps_with_cubature_coarse_reach_the_exact_minimiser(dev, prec_name, pc):
+    from paper_2508_13386_amd import ms
+    prec = ms.PREC_MIXED if prec_name == "mixed" else ms.PREC_FP64
+    kind = ms.PC_TWO_LEVEL_ADDITIVE if pc == "additive" else ms.PC_TWO_LEVEL
+    s = scenes.inclusion_block(6, seed=2, steps=3)
+    c, B = _ctx(dev, s, 8)
+    c.ms_build_cubature(tol=1e-9, n_init=8, n_add=8, seed=1)
+    c.ms_set_coarse_integration(ms.COARSE_CUBATURE)
+    body = fem.Body(s["rest"], s["tets"], s["E"], s["nu"], s["rho"])
+    x, v = s["x0"].copy(), s["v0"].copy()
+    for k in range(1, 4):
+        tgt = s["dbc_targets"](k)
+        xo, vo, _ = newton.newton_step(body, x, v, s["dt"], s["gravity"], s["dirichlet"], tgt)
+        c.ms_set_dirichlet(s["dirichlet"], tgt)
+        c.ms_set_state(x, v)
+        st = c.ms_step(s["dt"], precision=prec, preconditioner=kind)
+        xg, _ = c.ms_get_state()
+        err = e_rel(xg, xo, x)
+        say("cubature coarse step", k, prec_name, pc, "e_rel", err, "newton", st["newton_iters"], "pcg",
+            st["pcg_iters"])
+        assert err <= 1e-6
+        x, v = xo, vo
+    c.close()
+
+
+@pytest.mark.parametrize("prec_name,tol", [("fp64", 1e-6), ("mixed", 1e-4)])
+def test_paper_steps_with_cubature_match_paper_oracle(dev, prec_name, tol):
+    from paper_2508_13386_amd import ms
+    prec = ms.PREC_MIXED if prec_name == "mixed" else ms.PREC_FP64
+    s = scenes.plain_cube(8, seed=1, steps=2)
+    c, B = _ctx(dev, s, 8, seed=3)
+    t, w, _ = cub.fit_cubature(s["rest"], s["tets"], B["part"], B, seed=2, n_init=8, n_add=8)
+    c.ms_set_cubature(t, w)
+    c.ms_set_coarse_integration(ms.COARSE_CUBATURE)
+    body = fem.Body(s["rest"], s["tets"], s["E"], s["nu"], s["rho"])
+    x, v = s["x0"].copy(), s["v0"].copy()
+    for k in range(1, 3):
+        tgt = s["dbc_targets"](k)
+        xp, vp, info = paper.paper_step(body, x, v, s["dt"], s["gravity"], s["dirichlet"], tgt, None, B,
+                                        eps=1e-3, refine_iters=20, cubature=(t, w))
+        xe, _, _ = paper.paper_step(body, x, v, s["dt"], s["gravity"], s["dirichlet"], tgt, None, B,
+                                    eps=1e-3, refine_iters=20)
+        c.ms_set_dirichlet(s["dirichlet"], tgt)
+        c.ms_set_state(x, v)
+        st = c.ms_step(s["dt"], mode=ms.MODE_PAPER, precision=prec, refine_iters=20)
+        xg, _ = c.ms_get_state()
+        err = e_rel(xg, xp, x)
+        say("paper+cubature step", k, prec_name, "gpu vs oracle", err, "| cubature vs exact subspace matrix",
+            e_rel(xp, xe, x), "| newton gpu", st["newton_iters"], "oracle", info["newton"])
+        assert err <= tol
+        x, v = xp, vp
+    c.close()

@@ -146,3 +146,20 @@ def test_full_selection_galerkin_is_the_galerkin_matrix(name):
     Kc = cub.cubature_galerkin(prob, x, Us, t, w)
     assert np.abs(Kc - Kc.T).max() <= 1e-13 * np.abs(Kc).max()
     assert np.linalg.eigvalsh(Kc).min() >= -1e-12 * np.abs(Kc).max()
+
+
+def test_paper_step_with_full_selection_cubature_is_the_exact_paper_step():
+    s = scenes.plain_cube(3, seed=6)
+    part = _partition(s["rest"], s["tets"])
+    B = _basis(s, part)
+    body = fem.Body(s["rest"], s["tets"], s["E"], s["nu"], s["rho"])
+    tgt = s["dbc_targets"](1)
+    args = (body, s["x0"], s["v0"], s["dt"], s["gravity"], s["dirichlet"], tgt, None, B)
+    x0, _, i0 = paper.paper_step(*args)
+    x1, _, i1 = paper.paper_step(*args, cubature=(np.arange(len(s["tets"])), body.vol))
+    assert i0["newton"] == i1["newton"]
+    assert np.abs(x1 - x0).max() <= 1e-12 * np.abs(x0 - s["x0"]).max()
+    # a fitted cubature changes the step only slightly (an approximation)
+    t, w, _ = cub.fit_cubature(s["rest"], s["tets"], part, B, seed=1, n_init=8, n_add=8)
+    x2, _, _ = paper.paper_step(*args, cubature=(t, w))
+    assert np.abs(x2 - x0).max() <= 0.5 * np.abs(x0 - s["x0"]).max()
