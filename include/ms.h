@@ -90,7 +90,11 @@ typedef enum { MS_MODE_PLAIN = 0, MS_MODE_PAPER = 1 } ms_mode;
  *   MS_COARSE_CUBATURE   the elastic part from the installed cubature only,
  *                        h^2 sum_q (w_q / V_q) U_q^T H_q U_q; inertia, barrier
  *                        and friction curvature stay exact.  Symmetric
- *                        positive semi-definite for non-negative weights. */
+ *                        positive semi-definite for non-negative weights.
+ *                        Used by the additive and V-cycle preconditioners
+ *                        and paper mode; ms_step and ms_apply_preconditioner
+ *                        reject MS_PC_TWO_LEVEL (its deflation needs the
+ *                        exact matrix) with MS_E_ARG. */
 typedef enum { MS_COARSE_EXACT = 0, MS_COARSE_CUBATURE = 1 } ms_coarse_integration;
 
 /* Parameters of one timestep solve.  ms_solver_defaults() fills them. */

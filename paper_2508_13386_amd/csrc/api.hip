@@ -500,6 +500,8 @@ ms_status ms_apply_preconditioner(ms_ctx* c, int32_t kind, int32_t prec, const d
   set_coarse_f32(c, false);
   if (kind < 0 || kind > 3) return fail(c, MS_E_ARG, "bad preconditioner kind");
   if (two_level(kind) && !c->has_basis) return fail(c, MS_E_ORDER, "no basis");
+  if (kind == MS_PC_TWO_LEVEL && c->coarse_mode == MS_COARSE_CUBATURE)
+    return fail(c, MS_E_ARG, "the smoothed two-level preconditioner needs the exact coarse matrix");
   const int64_t n3 = 3 * c->n;
   std::vector<double> mr(r, r + n3);
   for (auto& v : mr) v = -v;
@@ -528,6 +530,10 @@ ms_status ms_step(ms_ctx* c, double dt, const ms_solver_params* pin, ms_step_sta
   if (P.integrator != 0 && P.integrator != 1) return fail(c, MS_E_ARG, "integrator must be 0 or 1");
   if (P.integrator == 1 && P.mode == MS_MODE_PAPER) return fail(c, MS_E_ARG, "paper mode steps with implicit Euler");
   if (P.mode == MS_MODE_PAPER) return paper_step(c, dt, P, st);
+  // the smoothed (deflated) form projects with the coarse matrix and stays a
+  // symmetric positive definite preconditioner only for the exact U^T H U
+  if (P.preconditioner == MS_PC_TWO_LEVEL && c->coarse_mode == MS_COARSE_CUBATURE)
+    return fail(c, MS_E_ARG, "the smoothed two-level preconditioner needs the exact coarse matrix");
   return plain_step(c, dt, P, st);
 }
 
