@@ -603,50 +603,61 @@ def cubature_main(a):
                             "newton_iters": [st["newton_iters"] for st in st_cu]},
         "e_rel_final_state_cubature_vs_exact_form": e_forms,
         "accuracy": accuracy}), flush=True)
-    # paper mode: cubature subspace matrix vs exact integration
+    # paper mode: cubature subspace matrix vs exact integration, on a cube
+    # with per-tet E over three decades and on a homogeneous one
     import torch
-    sp_ = scenes.plain_cube(a.grid, seed=0, steps=a.warmup + a.steps)
-    c = ms.context_from_scene(dev, sp_)
-    c.ms_build_basis(n_handles=a.handles, oversample=a.oversample)
-    t0 = time.perf_counter()
-    worst_p = c.ms_build_cubature(tol=a.cub_tol, n_init=a.cub_batch, n_add=a.cub_batch, seed=0)
-    fit_p = time.perf_counter() - t0
-    npts = len(c.ms_get_cubature()[0])
-    print(f"# paper-mode cube: cubature of {npts} tets in {fit_p:.1f} s", flush=True)
-    pparams = ms.solver_defaults(mode=ms.MODE_PAPER, precision=prec, refine_iters=0, max_newton=100)
-    times = {"exact": [], "cubature": []}
-    errs, iters = [], []
-    x, v = sp_["x0"].copy(), sp_["v0"].copy()
-    for k in range(1, a.warmup + a.steps + 1):
-        c.ms_set_dirichlet(sp_["dirichlet"], sp_["dbc_targets"](k))
-        res = {}
+    for label, e_lo, e_hi in (("per-tet E log-uniform in [1e5, 1e8]", 1e5, 1e8), ("homogeneous E = 1e6", 1e6, 1e6)):
+        sp_ = scenes.plain_cube(a.grid, seed=0, e_lo=e_lo, e_hi=e_hi, steps=a.warmup + a.steps)
+        c = ms.context_from_scene(dev, sp_)
+        c.ms_build_basis(n_handles=a.handles, oversample=a.oversample)
+        t0 = time.perf_counter()
+        worst_p = c.ms_build_cubature(tol=a.cub_tol, n_init=a.cub_batch, n_add=a.cub_batch, seed=0)
+        fit_p = time.perf_counter() - t0
+        npts = len(c.ms_get_cubature()[0])
+        print(f"# paper-mode cube ({label}): cubature of {npts} tets in {fit_p:.1f} s", flush=True)
+        # coarse matrices at the start state
+        r = 12 * c.ms_get_basis()["m"]
+        mats = {}
         for mode_name, mode in (("exact", ms.COARSE_EXACT), ("cubature", ms.COARSE_CUBATURE)):
             c.ms_set_coarse_integration(mode)
-            c.ms_set_state(x, v)
-            dev.stream.synchronize()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            st = c.ms_step(sp_["dt"], pparams)
-            dev.stream.synchronize()
-            t1 = time.perf_counter()
-            res[mode_name] = (c.ms_get_state(), st, t1 - t0)
-        if k > a.warmup:
-            for mname in times:
-                times[mname].append(res[mname][2])
-            xe, xc = res["exact"][0][0], res["cubature"][0][0]
-            errs.append(float(np.linalg.norm(xc - xe) / np.linalg.norm(xe - x)))
-            iters.append((res["exact"][1]["newton_iters"], res["cubature"][1]["newton_iters"]))
-        x, v = res["cubature"][0]
-    c.close()
-    print(json.dumps({
-        "workload": "cubature", "scene": f"paper mode, cube {a.grid}^3, per-tet E log-uniform in [1e5, 1e8]",
-        "n_tets": len(sp_["tets"]), "handles": a.handles, "precision": a.precision,
-        "fit": {"points": npts, "fraction_of_tets": npts / len(sp_["tets"]), "seconds": fit_p,
-                "worst_rel_moment_residual": worst_p},
-        "timesteps_per_s": {m: len(t) / sum(t) for m, t in times.items()},
-        "newton_iters_exact_vs_cubature": iters,
-        "e_rel_cubature_step_vs_exact_integration_step": errs,
-        "note": "both steps start from the same state (the cubature trajectory)"}), flush=True)
+            c.ms_eval(sp_["x0"], sp_["dt"], prec=ms.PREC_FP64, hess=False)
+            mats[mode_name] = c.ms_get_coarse_matrix(r)
+        kdiff = float(np.linalg.norm(mats["cubature"] - mats["exact"]) / np.linalg.norm(mats["exact"]))
+        pparams = ms.solver_defaults(mode=ms.MODE_PAPER, precision=prec, refine_iters=0, max_newton=100)
+        times = {"exact": [], "cubature": []}
+        errs, iters = [], []
+        x, v = sp_["x0"].copy(), sp_["v0"].copy()
+        for k in range(1, a.warmup + a.steps + 1):
+            c.ms_set_dirichlet(sp_["dirichlet"], sp_["dbc_targets"](k))
+            res = {}
+            for mode_name, mode in (("exact", ms.COARSE_EXACT), ("cubature", ms.COARSE_CUBATURE)):
+                c.ms_set_coarse_integration(mode)
+                c.ms_set_state(x, v)
+                dev.stream.synchronize()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st = c.ms_step(sp_["dt"], pparams)
+                dev.stream.synchronize()
+                t1 = time.perf_counter()
+                res[mode_name] = (c.ms_get_state(), st, t1 - t0)
+            if k > a.warmup:
+                for mname in times:
+                    times[mname].append(res[mname][2])
+                xe, xc = res["exact"][0][0], res["cubature"][0][0]
+                errs.append(float(np.linalg.norm(xc - xe) / np.linalg.norm(xe - x)))
+                iters.append((res["exact"][1]["newton_iters"], res["cubature"][1]["newton_iters"]))
+            x, v = res["cubature"][0]
+        c.close()
+        print(json.dumps({
+            "workload": "cubature", "scene": f"paper mode, cube {a.grid}^3, {label}",
+            "n_tets": len(sp_["tets"]), "handles": a.handles, "precision": a.precision,
+            "fit": {"points": npts, "fraction_of_tets": npts / len(sp_["tets"]), "seconds": fit_p,
+                    "worst_rel_moment_residual": worst_p},
+            "coarse_matrix_rel_frobenius_difference_at_rest": kdiff,
+            "timesteps_per_s": {m: len(t) / sum(t) for m, t in times.items()},
+            "newton_iters_exact_vs_cubature": iters,
+            "e_rel_cubature_step_vs_exact_integration_step": errs,
+            "note": "both steps start from the same state (the cubature trajectory)"}), flush=True)
 
 
 def spmv_sweep_main(a):

@@ -13,7 +13,8 @@
 //    without replacement with probability proportional to (A_k^T r)^2.
 //  * NNLS is Lawson and Hanson's active-set method (Solving Least Squares
 //    Problems, 1974, ch. 23) with the least-squares subproblem kept as an
-//    incrementally grown Householder QR (refactorised when a column leaves).
+//    incrementally updated QR (a Householder reflector when a column enters,
+//    Givens rotations restoring the triangle when one leaves).
 //    The solver continues from its current passive set when a round adds
 //    candidates.
 //  * Draws come from SplitMix64 (Steele, Lea and Flood, OOPSLA 2014) used as
@@ -136,8 +137,7 @@ class Nnls {
           // drop it and keep x
           passive_[t] = 0;
           blocked[t] = 1;
-          std::vector<int> keep(cols_.begin(), cols_.end() - 1);
-          refactor(keep);
+          remove(int(cols_.size()) - 1);
           break;
         }
         first = false;
@@ -147,7 +147,7 @@ class Nnls {
             const double xj = x_[cols_[q]];
             alpha = std::min(alpha, xj - z[q] > 0.0 ? xj / (xj - z[q]) : 0.0);
           }
-        std::vector<int> keep;
+        std::vector<int> leave;  // positions, ascending
         for (size_t q = 0; q < cols_.size(); ++q) {
           const int j = cols_[q];
           const double xo = x_[j];
@@ -157,11 +157,10 @@ class Nnls {
           if (hit || x_[j] <= 0.0) {
             x_[j] = 0.0;
             passive_[j] = 0;
-          } else {
-            keep.push_back(j);
+            leave.push_back(int(q));
           }
         }
-        refactor(keep);
+        for (size_t q = leave.size(); q-- > 0;) remove(leave[q]);
         std::fill(blocked.begin(), blocked.end(), 0);
         if (cols_.empty()) break;
       }
@@ -202,18 +201,40 @@ class Nnls {
     qtb_.assign(b_, b_ + m_);
     cols_.clear();
     R_.clear();
-    V_.clear();
+    ops_.clear();
   }
 
-  // Brings column j of Q^T A up to date (only columns that have been
-  // candidates are kept transformed).
+  // Brings column j of Q^T A up to date by replaying the transformations
+  // applied so far (only columns that have been candidates are kept).
   void ready(int j) {
     if (ready_[j]) return;
     double* a = QA_.data() + size_t(j) * m_;
     std::copy(A_ + size_t(j) * m_, A_ + size_t(j + 1) * m_, a);
-    for (size_t q = 0; q < V_.size(); ++q) reflect(V_[q], int(q), a);
+    for (const Op& o : ops_) apply(o, a);
     ready_[j] = 1;
     touched_.push_back(j);
+  }
+
+  // Removes the passive column at position q: the columns after it shift
+  // left and Givens rotations of rows (k, k+1) restore R's triangle; every
+  // current column and Q^T b take the same rotations.
+  void remove(int q) {
+    cols_.erase(cols_.begin() + q);
+    R_.erase(R_.begin() + q);
+    for (int k = q; k < int(cols_.size()); ++k) {
+      const double a = R_[k][k], b = R_[k][k + 1];
+      const double r = std::hypot(a, b);
+      Op o;
+      o.q = k;
+      o.c = r > 0.0 ? a / r : 1.0;
+      o.s = r > 0.0 ? b / r : 0.0;
+      R_[k][k] = r;
+      R_[k].pop_back();
+      for (int kk = k + 1; kk < int(cols_.size()); ++kk) rotate(o, R_[kk].data());
+      for (int jj : touched_) rotate(o, QA_.data() + size_t(jj) * m_);
+      rotate(o, qtb_.data());
+      ops_.push_back(std::move(o));
+    }
   }
 
   // Appends column j to the QR of the passive columns and applies the new
@@ -237,27 +258,39 @@ class Nnls {
     std::vector<double> rcol(a, a + p);
     rcol.push_back(alpha);
     R_.push_back(std::move(rcol));
-    for (int k : touched_) reflect(v, p, QA_.data() + size_t(k) * m_);
-    reflect(v, p, qtb_.data());
-    V_.push_back(std::move(v));
+    Op o;
+    o.q = p;
+    o.v = std::move(v);
+    for (int k : touched_) apply(o, QA_.data() + size_t(k) * m_);
+    apply(o, qtb_.data());
+    ops_.push_back(std::move(o));
     cols_.push_back(j);
     return true;
   }
 
-  void reflect(const std::vector<double>& v, int q, double* a) const {
+  // An orthogonal transformation of Q^T: a Householder reflector I - 2 v v^T
+  // (v nonzero from row q on) or a rotation [c s; -s c] of rows (q, q+1).
+  struct Op {
+    int q = 0;
+    std::vector<double> v;  // empty for a rotation
+    double c = 1.0, s = 0.0;
+  };
+
+  void apply(const Op& o, double* a) const {
+    if (o.v.empty()) {
+      rotate(o, a);
+      return;
+    }
     double s = 0.0;
-    for (int i = q; i < m_; ++i) s += v[i] * a[i];
+    for (int i = o.q; i < m_; ++i) s += o.v[i] * a[i];
     s *= 2.0;
-    for (int i = q; i < m_; ++i) a[i] -= s * v[i];
+    for (int i = o.q; i < m_; ++i) a[i] -= s * o.v[i];
   }
 
-  void refactor(const std::vector<int>& keep) {
-    reset();
-    for (int j : keep)
-      if (!add(j)) {
-        x_[j] = 0.0;
-        passive_[j] = 0;
-      }
+  static void rotate(const Op& o, double* a) {
+    const double y0 = a[o.q], y1 = a[o.q + 1];
+    a[o.q] = o.c * y0 + o.s * y1;
+    a[o.q + 1] = -o.s * y0 + o.c * y1;
   }
 
   // z = argmin || A_P z - b || by back substitution on R z = Q^T b.
@@ -280,7 +313,7 @@ class Nnls {
   std::vector<double> QA_;                // Q^T A, column-major (columns in touched_)
   std::vector<char> ready_;               // column of QA_ is current
   std::vector<int> touched_;              // the current columns
-  std::vector<std::vector<double>> V_;    // Householder vectors
+  std::vector<Op> ops_;                   // transformations applied to Q^T, in order
   std::vector<double> qtb_;               // Q^T b
   std::vector<int> cols_;                 // passive columns in factorisation order
   std::vector<std::vector<double>> R_;    // R by columns
