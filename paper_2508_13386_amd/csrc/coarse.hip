@@ -111,11 +111,15 @@ __global__ void __launch_bounds__(kRThreads) k_restrict(const int4* __restrict__
 // and the formation of c, so their latency overlaps both.
 constexpr int kGemvRows = 16;
 constexpr int kGemvPre = 10;
+// direct != 0: every handle's restriction is a single chunk and chunk i is
+// handle i, so the partials are the coarse right-hand side itself; they are
+// then loaded together with the matrix rows, before the flag test.
+constexpr int kGemvPart = 3;  // direct loads per thread (r <= 3 * 64 * kGemvRows)
 template <typename AT>
 __global__ void __launch_bounds__(64 * kGemvRows) k_coarse_gemv(int r, int ld, const AT* __restrict__ A,
                                                       const int2* __restrict__ hinfo,
                                                       const double* __restrict__ part, double* __restrict__ e,
-                                                      const double* __restrict__ scal) {
+                                                      const double* __restrict__ scal, int direct) {
   extern __shared__ double sc[];
   const double done = scal ? scal[S_DONE] : 0.0;
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
@@ -124,6 +128,14 @@ __global__ void __launch_bounds__(64 * kGemvRows) k_coarse_gemv(int r, int ld, c
   constexpr int VW = 16 / sizeof(AT);  // elements per 16-byte load
   constexpr int STRIDE = 64 * VW;
   using V16 = typename std::conditional<sizeof(AT) == 4, float4, double2>::type;
+  double pc[kGemvPart];
+  if (direct) {
+#pragma unroll
+    for (int u = 0; u < kGemvPart; ++u) {
+      const int idx = t + u * int(blockDim.x);
+      pc[u] = idx < r ? part[idx] : 0.0;
+    }
+  }
   V16 pre[kGemvPre];
 #pragma unroll
   for (int p = 0; p < kGemvPre; ++p) {
@@ -131,12 +143,20 @@ __global__ void __launch_bounds__(64 * kGemvRows) k_coarse_gemv(int r, int ld, c
     pre[p] = j < ld ? *reinterpret_cast<const V16*>(a + j) : V16{};
   }
   if (done != 0.0) return;  // the flag is the same for the whole grid
-  for (int idx = t; idx < r; idx += blockDim.x) {
-    const int2 hi = hinfo[idx / 12];
-    const int q = idx % 12;
-    double s = 0.0;
-    for (int k = 0; k < hi.y; ++k) s += part[12 * int64_t(hi.x + k) + q];
-    sc[idx] = s;
+  if (direct) {
+#pragma unroll
+    for (int u = 0; u < kGemvPart; ++u) {
+      const int idx = t + u * int(blockDim.x);
+      if (idx < r) sc[idx] = pc[u];
+    }
+  } else {
+    for (int idx = t; idx < r; idx += blockDim.x) {
+      const int2 hi = hinfo[idx / 12];
+      const int q = idx % 12;
+      double s = 0.0;
+      for (int k = 0; k < hi.y; ++k) s += part[12 * int64_t(hi.x + k) + q];
+      sc[idx] = s;
+    }
   }
   __syncthreads();
   if (row >= r) return;
@@ -772,12 +792,13 @@ void launch_coarse_gemv(ms_ctx* c, int prec, const double* scal) {
   Basis& D = c->basis;
   const unsigned nb = nblocks(c->r, kGemvRows);
   const size_t lds = size_t(c->r) * sizeof(double);
+  const int direct = (D.nrchunks == D.m && c->r <= kGemvPart * 64 * kGemvRows) ? 1 : 0;
   if (prec == MS_PREC_MIXED || c->coarse_f32)
     k_coarse_gemv<float><<<nb, 64 * kGemvRows, lds, c->stream>>>(c->r, c->rp, c->d_Ainv32, D.d_hinfo, D.d_rpart,
-                                                                 c->d_e, scal);
+                                                                 c->d_e, scal, direct);
   else
     k_coarse_gemv<double><<<nb, 64 * kGemvRows, lds, c->stream>>>(c->r, c->rp, c->d_Ainv, D.d_hinfo, D.d_rpart,
-                                                                  c->d_e, scal);
+                                                                  c->d_e, scal, direct);
 }
 
 void launch_prolong_add(ms_ctx* c, double* target, const double* scal) {
@@ -853,7 +874,7 @@ ms_status coarse_coordinates(ms_ctx* c, const double* x_dev, double* q_host, dou
   k_sub<<<nblocks(3 * c->n, 256), 256, 0, c->stream>>>(3 * c->n, x_dev, c->d_rest, c->d_w);
   launch_restrict(c, c->d_w, c->d_mass, nullptr);
   k_coarse_gemv<double><<<nblocks(c->r, kGemvRows), 64 * kGemvRows, size_t(c->r) * sizeof(double), c->stream>>>(
-      c->r, c->r, D.d_Minv, D.d_hinfo, D.d_rpart, q_dev ? q_dev : c->d_e, nullptr);
+      c->r, c->r, D.d_Minv, D.d_hinfo, D.d_rpart, q_dev ? q_dev : c->d_e, nullptr, 0);
   if (q_host)
     MS_HIP(hipMemcpyAsync(q_host, q_dev ? q_dev : c->d_e, c->r * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   return sync(c);
