@@ -20,6 +20,9 @@ Modules
             partition of unity, Dirichlet-compatible variant)
   mlp       FP64 forward / backward / Adam of the warm-start network
   paper     the paper's three-level inexact Newton solve (Alg. 1 and 2)
+  cubature  modal moment-fitting cubature of the subspace Hessian (Alg. 3)
+  selfcontact  IPC point-triangle / edge-edge barriers between surface
+            primitives and their time of impact under linear motion
 
 Parity status of each function is stated in its module header.
 """
