@@ -325,6 +325,22 @@ ms_status ms_set_cubature(ms_ctx* c, int64_t n_pts, const int32_t* tets, const d
  * (ascending) and weights [n_pts]. */
 ms_status ms_get_cubature(const ms_ctx* c, int64_t* n_pts, int32_t* tets, double* weights);
 
+/* Continuous collision detection of IPC self-contact primitive pairs (the
+ * paper filters every search direction with additive CCD: Sec. 3.9 line
+ * search, Sec. 4), on the GPU without a context.  Pair q is a point and a
+ * triangle (kind[q] = 0; x12 [q][12] = point, then the triangle's three
+ * vertices) or two edges (kind[q] = 1; first edge's two vertices, then the
+ * second's), moving by p12 [q][12] over t in [0, t_max].  Additive CCD with
+ * zero thickness and gap fraction s in (0, 1): toi [q] receives a time at
+ * which the pair is still separated by at least s times its initial gap and
+ * before any contact, hit [q] = 1; or hit [q] = 0 and toi [q] = t_max when
+ * the pair cannot meet before t_max.  max_iter caps the steps per pair
+ * (reached: a hit at the time reached).  Host arrays; work runs on
+ * dev->hip_stream and the call returns when it is done.  Errors: MS_E_ARG
+ * (kinds, s, t_max, max_iter), MS_E_NONFINITE, MS_E_NOMEM, MS_E_DEVICE. */
+ms_status ms_contact_toi(const ms_device* dev, int64_t n_pairs, const int32_t* kind, const double* x12,
+                         const double* p12, double s, double t_max, int32_t max_iter, double* toi, int32_t* hit);
+
 /* Select how every later coarse matrix (two-level preconditioners, paper
  * mode's subspace level, ms_eval) is integrated (ms_coarse_integration).
  * Errors: MS_E_ARG, MS_E_ORDER (MS_COARSE_CUBATURE without a cubature). */

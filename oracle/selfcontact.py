@@ -29,6 +29,8 @@ no vertex, whose unsigned distance is below d_hat.
   * Time of impact: for motion x(t) = x + t p, t in [0, 1], the first time
     the four points are coplanar (roots of the cubic triple product) with
     the point inside the triangle (PT) or the two segments crossing (EE).
+  * Additive CCD, the conservative filter the paper uses (Sec. 4), as its
+    authors publish it, with zero thickness.
 
 Parity status (tests/test_oracle_selfcontact.py)
   surface                      pinned: counts and the Euler characteristic
@@ -40,6 +42,10 @@ Parity status (tests/test_oracle_selfcontact.py)
                                eps_x, zero beyond d_hat
   toi                          pinned: analytic impacts and dense sampling
                                of the distance along the motion
+  accd                         pinned: never later than toi, the pair still
+                               separated at the returned time, a hit
+                               whenever toi finds one, translations of the
+                               whole pair ignored
 """
 from __future__ import annotations
 
@@ -237,3 +243,37 @@ def toi(kind, x12, p12, tol=1e-9):
         if d2 <= (tol * scale) ** 2:
             return t
     return None
+
+
+# ----------------------------------------------------------------------------
+# Additive CCD (Li et al., "Codimensional Incremental Potential Contact",
+# 2021): a conservative time of impact from distance evaluations only
+# ----------------------------------------------------------------------------
+def accd(kind, x12, p12, s=0.1, t_max=1.0, max_iter=100000):
+    """(hit, t): advance along x + t p in steps that cannot close more than
+    90% of the current gap (the first step (1 - s) of it), given the bound
+    l_p on the relative speed of the pair after removing the mean
+    displacement; stop once the gap falls below s times the initial one
+    (hit, t the last time before that step) or t passes t_max (no hit)."""
+    x = np.asarray(x12, dtype=np.float64).reshape(4, 3).copy()
+    p = np.asarray(p12, dtype=np.float64).reshape(4, 3).copy()
+    p = p - p.mean(axis=0)
+    nrm = np.sqrt((p * p).sum(axis=1))
+    lp = nrm[0] + nrm[1:].max() if kind == "pt" else max(nrm[0], nrm[1]) + max(nrm[2], nrm[3])
+    if lp == 0.0:
+        return False, t_max
+    dist = pt_dist2 if kind == "pt" else ee_dist2
+    d = float(np.sqrt(float(dist(torch.tensor(x.ravel(), dtype=torch_f64)))))
+    g = s * d
+    t = 0.0
+    tl = (1.0 - s) * d / lp
+    for _ in range(max_iter):
+        x = x + tl * p
+        d = float(np.sqrt(float(dist(torch.tensor(x.ravel(), dtype=torch_f64)))))
+        if t > 0.0 and d < g:
+            return True, t
+        t += tl
+        if t > t_max:
+            return False, t_max
+        tl = 0.9 * d / lp
+    return True, t

@@ -117,6 +117,7 @@ def lib():
             "ms_set_cubature": [vp, i64, ip, dp],
             "ms_get_cubature": [vp, C.POINTER(i64), ip, dp],
             "ms_set_coarse_integration": [vp, i32],
+            "ms_contact_toi": [C.POINTER(ms_device), i64, ip, dp, dp, d, d, i32, dp, ip],
             "ms_mlp_forward": [C.POINTER(ms_device), i32, i32, i32, vp, i64, vp, vp],
             "ms_mlp_train": [C.POINTER(ms_device), i32, i32, i32, vp, i64, vp, vp, i32, i32, vp, C.c_float, vp, vp],
         }
@@ -443,6 +444,22 @@ def ms_cubature_compute(rest, tets, part, basis, tol=1e-9, n_init=16, n_add=16, 
     finally:
         L.ms_cubature_free(h)
     return t, wt, res.value
+
+
+def ms_contact_toi(dev, kind, x12, p12, s=0.1, t_max=1.0, max_iter=100000):
+    """Additive CCD of point-triangle (kind 0) / edge-edge (kind 1) pairs on
+    the GPU; returns (hit [n] bool, toi [n])."""
+    L = lib()
+    kind = _i32(kind)
+    x12, p12 = _f64(np.asarray(x12).reshape(-1, 12)), _f64(np.asarray(p12).reshape(-1, 12))
+    n = len(kind)
+    toi = np.empty(n)
+    hit = np.empty(n, dtype=np.int32)
+    code = L.ms_contact_toi(C.byref(dev.desc), n, _ptr(kind), _ptr(x12), _ptr(p12), float(s), float(t_max), int(max_iter),
+                            _ptr(toi), _ptr(hit))
+    if code != MS_OK:
+        raise MSError(code, "ms_contact_toi")
+    return hit.astype(bool), toi
 
 
 MLP_KEYS = ("W0", "b0", "W1", "b1", "W2", "b2")

@@ -196,3 +196,31 @@ def test_time_of_impact_against_sampled_distance():
             before = ts < t - 1e-3
             assert np.all(d[before] > 0.0)
     assert found > 5
+
+
+def test_additive_ccd_is_conservative():
+    rng = np.random.default_rng(6)
+    hits = 0
+    for _ in range(60):
+        X = rng.uniform(-1, 1, (4, 3))
+        P = rng.uniform(-2, 2, (4, 3))
+        for kind, dist in (("pt", sc.pt_dist2), ("ee", sc.ee_dist2)):
+            t_exact = sc.toi(kind, X.ravel(), P.ravel())
+            hit, t = sc.accd(kind, X.ravel(), P.ravel(), s=0.1)
+            if t_exact is not None:
+                assert hit and t <= t_exact
+                hits += 1
+            if hit:
+                d0 = np.sqrt(float(dist(T(X))))
+                dt = np.sqrt(float(dist(T(X + t * P))))
+                assert dt >= 0.1 * d0 * (1 - 1e-12)  # separated by at least s times the start gap
+    assert hits > 5
+    # the falling point: hit before t = 0.5, within the last step's margin
+    tri = np.array([(0, 0, 0), (1, 0, 0), (0, 1, 0)], dtype=float)
+    x = np.concatenate([[0.2, 0.2, 1.0], tri.ravel()])
+    p = np.concatenate([[0.0, 0.0, -2.0], np.zeros(9)])
+    hit, t = sc.accd("pt", x, p, s=0.1)
+    assert hit and 0.45 <= t < 0.5
+    # a common translation is no relative motion
+    hit, t = sc.accd("pt", x, np.tile([0.0, 0.0, -2.0], 4))
+    assert not hit and t == 1.0
