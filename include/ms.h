@@ -341,6 +341,27 @@ ms_status ms_get_cubature(const ms_ctx* c, int64_t* n_pts, int32_t* tets, double
 ms_status ms_contact_toi(const ms_device* dev, int64_t n_pairs, const int32_t* kind, const double* x12,
                          const double* p12, double s, double t_max, int32_t max_iter, double* toi, int32_t* hit);
 
+/* The self-contact constraint set (IPC's point-triangle and edge-edge
+ * pairs closer than d_hat) on the GPU without a context.  x [n_verts][3];
+ * the surface: vertices sverts [n_sverts], triangles tris [n_tris][3] and
+ * edges edges [n_edges][2] (vertex ids).  Boxes inflated by d_hat / 2 are
+ * entered into a grid of cell size `cell` (<= 0: the largest primitive
+ * extent plus d_hat), pairs sharing a cell are deduplicated and kept when
+ * their exact distance is below d_hat (a vertex is never paired with a
+ * triangle containing it, nor an edge with one sharing a vertex).  *out
+ * receives an opaque result that ms_pairs_get queries (first with null
+ * arrays, then with pt [n_pt][2] = (vertex id, triangle index) and
+ * ee [n_ee][2] = (edge index i, edge index j > i), both in ascending order)
+ * and ms_pairs_free releases.  Host arrays; work runs on dev->hip_stream.
+ * Errors: MS_E_ARG (indices, d_hat, a scene too large for the grid),
+ * MS_E_NONFINITE, MS_E_NOMEM, MS_E_DEVICE. */
+typedef struct ms_pairs ms_pairs;
+ms_status ms_contact_pairs(const ms_device* dev, int64_t n_verts, const double* x, int64_t n_sverts,
+                           const int32_t* sverts, int64_t n_tris, const int32_t* tris, int64_t n_edges,
+                           const int32_t* edges, double dhat, double cell, ms_pairs** out);
+ms_status ms_pairs_get(const ms_pairs* p, int64_t* n_pt, int32_t* pt, int64_t* n_ee, int32_t* ee);
+void ms_pairs_free(ms_pairs* p);
+
 /* Select how every later coarse matrix (two-level preconditioners, paper
  * mode's subspace level, ms_eval) is integrated (ms_coarse_integration).
  * Errors: MS_E_ARG, MS_E_ORDER (MS_COARSE_CUBATURE without a cubature). */

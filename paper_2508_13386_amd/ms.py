@@ -118,6 +118,9 @@ def lib():
             "ms_get_cubature": [vp, C.POINTER(i64), ip, dp],
             "ms_set_coarse_integration": [vp, i32],
             "ms_contact_toi": [C.POINTER(ms_device), i64, ip, dp, dp, d, d, i32, dp, ip],
+            "ms_contact_pairs": [C.POINTER(ms_device), i64, dp, i64, ip, i64, ip, i64, ip, d, d,
+                                 C.POINTER(C.c_void_p)],
+            "ms_pairs_get": [vp, C.POINTER(i64), ip, C.POINTER(i64), ip],
             "ms_mlp_forward": [C.POINTER(ms_device), i32, i32, i32, vp, i64, vp, vp],
             "ms_mlp_train": [C.POINTER(ms_device), i32, i32, i32, vp, i64, vp, vp, i32, i32, vp, C.c_float, vp, vp],
         }
@@ -133,6 +136,8 @@ def lib():
         L.ms_basis_free.restype = None
         L.ms_cubature_free.argtypes = [vp]
         L.ms_cubature_free.restype = None
+        L.ms_pairs_free.argtypes = [vp]
+        L.ms_pairs_free.restype = None
         L.ms_destroy.argtypes = [vp]
         L.ms_destroy.restype = None
         L.ms_last_error.argtypes = [vp]
@@ -460,6 +465,29 @@ def ms_contact_toi(dev, kind, x12, p12, s=0.1, t_max=1.0, max_iter=100000):
     if code != MS_OK:
         raise MSError(code, "ms_contact_toi")
     return hit.astype(bool), toi
+
+
+def ms_contact_pairs(dev, x, sverts, tris, edges, dhat, cell=0.0):
+    """Self-contact constraint set on the GPU: (pt [k,2] of (vertex, triangle
+    index), ee [k,2] of (edge index, edge index), i < j), both ascending."""
+    L = lib()
+    x = _f64(np.asarray(x).reshape(-1, 3))
+    sv, tr, ed = _i32(sverts), _i32(np.asarray(tris).reshape(-1, 3)), _i32(np.asarray(edges).reshape(-1, 2))
+    h = C.c_void_p()
+    code = L.ms_contact_pairs(C.byref(dev.desc), len(x), _ptr(x), len(sv), _ptr(sv) if len(sv) else None, len(tr),
+                              _ptr(tr) if len(tr) else None, len(ed), _ptr(ed) if len(ed) else None, float(dhat),
+                              float(cell), C.byref(h))
+    if code != MS_OK:
+        raise MSError(code, "ms_contact_pairs")
+    try:
+        npt, nee = C.c_int64(), C.c_int64()
+        L.ms_pairs_get(h, C.byref(npt), None, C.byref(nee), None)
+        pt = np.empty((npt.value, 2), dtype=np.int32)
+        ee = np.empty((nee.value, 2), dtype=np.int32)
+        L.ms_pairs_get(h, C.byref(npt), _ptr(pt), C.byref(nee), _ptr(ee))
+    finally:
+        L.ms_pairs_free(h)
+    return pt, ee
 
 
 MLP_KEYS = ("W0", "b0", "W1", "b1", "W2", "b2")

@@ -68,3 +68,39 @@ def test_accd_rejects_bad_arguments(dev):
     Xn[0, 0, 0] = np.nan
     with pytest.raises(ms.MSError):
         ms.ms_contact_toi(dev, kind, Xn.reshape(-1, 12), P.reshape(-1, 12))
+
+
+def _two_cubes(N, gap, seed):
+    import scenes
+    rest, tets, _, _ = scenes.kuhn_cube(N)
+    top = rest + np.array([0.15, 0.1, 1.0 + gap])
+    rest2 = np.concatenate([rest, top])
+    tets2 = np.concatenate([tets, tets + len(rest)])
+    x = rest2 + 1e-3 * np.random.default_rng(seed).standard_normal(rest2.shape)
+    return x, tets2
+
+
+@pytest.mark.parametrize("N,gap,cell", [(2, 0.02, 0.0), (2, 0.02, 0.07), (3, 0.01, 0.0), (2, 0.5, 0.0)])
+def test_contact_pairs_match_brute_force(dev, N, gap, cell):
+    from paper_2508_13386_amd import ms
+    x, tets = _two_cubes(N, gap, N)
+    tris, edges, verts = sc.surface(tets)
+    dhat = 0.05
+    say("pairs: surface", len(verts), "verts", len(tris), "tris", len(edges), "edges; cell", cell)
+    pt, ee = ms.ms_contact_pairs(dev, x, verts, tris, edges, dhat, cell)
+    opt, oee = sc.active_pairs(x, (tris, edges, verts), dhat)
+    got_pt = {(int(v), *map(int, tris[t])) for v, t in pt}
+    got_ee = {(*map(int, edges[i]), *map(int, edges[j])) for i, j in ee}
+    say("  gpu", len(got_pt), "PT", len(got_ee), "EE | oracle", len(opt), "PT", len(oee), "EE")
+    assert len(got_pt) == len(pt) and len(got_ee) == len(ee)  # no duplicates
+    assert np.all(np.diff(pt[:, 0].astype(np.int64) * 2**32 + pt[:, 1]) > 0) if len(pt) > 1 else True
+    assert all(i < j for i, j in ee)
+
+    def borderline(kind, q):
+        d2 = float((sc.pt_dist2 if kind == "pt" else sc.ee_dist2)(torch.tensor(x[list(q)].ravel())))
+        return abs(d2 - dhat * dhat) <= 1e-12 * dhat * dhat
+
+    assert {q for q in got_pt ^ set(opt) if not borderline("pt", q)} == set()
+    assert {q for q in got_ee ^ set(oee) if not borderline("ee", q)} == set()
+    if gap < 0.1:
+        assert len(opt) > 0 and len(oee) > 0
