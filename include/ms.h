@@ -353,7 +353,8 @@ ms_status ms_contact_toi(const ms_device* dev, int64_t n_pairs, const int32_t* k
  * arrays, then with pt [n_pt][2] = (vertex id, triangle index) and
  * ee [n_ee][2] = (edge index i, edge index j > i), both in ascending order)
  * and ms_pairs_free releases.  Host arrays; work runs on dev->hip_stream.
- * Errors: MS_E_ARG (indices, d_hat, a scene too large for the grid),
+ * Errors: MS_E_ARG (indices, d_hat, a scene too large for the grid or
+ * spanning 2^31 cells or more),
  * MS_E_NONFINITE, MS_E_NOMEM, MS_E_DEVICE. */
 typedef struct ms_pairs ms_pairs;
 ms_status ms_contact_pairs(const ms_device* dev, int64_t n_verts, const double* x, int64_t n_sverts,

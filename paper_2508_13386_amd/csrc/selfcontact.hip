@@ -466,8 +466,12 @@ extern "C" ms_status ms_contact_pairs(const ms_device* dev, int64_t n_verts, con
     for (int64_t e = 0; e < n_edges; ++e) grow(edges + 2 * e, 2);
     cell = ext + dhat;
   }
-  for (int i = 0; i < 3; ++i)
+  double cells = 1.0;  // cells of the whole scene: bounds every primitive's count
+  for (int i = 0; i < 3; ++i) {
     if (std::max(std::fabs(lo[i]), std::fabs(hi[i])) + dhat >= cell * double(ms::kCellBias - 2)) return MS_E_ARG;
+    cells *= (hi[i] - lo[i] + dhat) / cell + 2.0;
+  }
+  if (cells >= double(int64_t(1) << 31)) return MS_E_ARG;
   if (hipSetDevice(dev->device) != hipSuccess) return MS_E_DEVICE;
   hipStream_t st = static_cast<hipStream_t>(dev->hip_stream);
   ms::Pool pool(dev);
