@@ -20,7 +20,7 @@ def _basis(s, part):
     out = obasis.basis_weights(s["rest"], s["tets"], s["E"], s["dirichlet"], part)
     vptr = np.zeros(len(s["rest"]) + 1, np.int64)
     vptr[1:] = np.cumsum([len(r) for r in out["rows"]])
-    return dict(origins=out["origins"], vptr=vptr, m=len(out["origins"]),
+    return dict(origins=out["origins"], vptr=vptr, m=len(out["origins"]), part=np.asarray(part),
                 vhandle=np.array([i for r in out["rows"] for i, _ in r], np.int32),
                 vphi=np.array([p for r in out["rows"] for _, p in r]))
 
@@ -158,7 +158,9 @@ def test_paper_step_with_full_selection_cubature_is_the_exact_paper_step():
     x0, _, i0 = paper.paper_step(*args)
     x1, _, i1 = paper.paper_step(*args, cubature=(np.arange(len(s["tets"])), body.vol))
     assert i0["newton"] == i1["newton"]
-    assert np.abs(x1 - x0).max() <= 1e-12 * np.abs(x0 - s["x0"]).max()
+    # the two subspace matrices agree to round-off; through the iterative
+    # subspace solves that reaches the positions as a few ulps of x
+    assert np.abs(x1 - x0).max() <= 1e-12 * np.abs(x0 - s["x0"]).max() + 8 * np.finfo(float).eps * np.abs(x0).max()
     # a fitted cubature changes the step only slightly (an approximation)
     t, w, _ = cub.fit_cubature(s["rest"], s["tets"], part, B, seed=1, n_init=8, n_add=8)
     x2, _, _ = paper.paper_step(*args, cubature=(t, w))
