@@ -112,13 +112,14 @@ typedef struct {
   double abs_floor;        /* absolute displacement floor of that test (m)              */
   double pcg_eta_max;      /* upper bound of the PCG forcing term (see forcing)         */
   double pcg_eta_min;      /* lower bound of the forcing term                           */
-  int32_t replace_every;   /* mixed precision: FP64 true-residual recomputation period  */
   int32_t max_backtracks;  /* line-search halvings before MS_E_LINESEARCH               */
   int32_t exact_endgame;   /* 1: drop the PSD projection once steps are small           */
   int32_t warm_start;      /* 1: use the learned coarse warm start if one is set        */
   /* paper mode (Alg. 1 and 2) */
   double paper_eps;        /* termination on mean per-vertex ||d_s,v|| / h  (m/s)       */
-  double subspace_rtol;    /* relative residual of the affine and subspace PCG solves   */
+  double subspace_rtol;    /* relative residual ||r_k|| <= subspace_rtol ||r_0|| at which the
+                              affine and sparse subspace PCG solves stop (Sec. 3.7.1;
+                              12x12 block-Jacobi, at most max_pcg iterations), in [0,1) */
   int32_t refine_iters;    /* fixed Jacobi-PCG iterations of the full-space refinement;
                               0: 20 or 40 from the partitions' mean hop diameter      */
   int32_t lag_window;      /* step sizes averaged by the Hessian-lag trigger             */
@@ -173,6 +174,10 @@ typedef struct {
   double disp_norm;           /* ||x^{t+1} - x^t||_2                                     */
   double min_alpha;           /* smallest accepted line-search step                      */
   double time_ms;             /* host wall time of the step                              */
+  int32_t subspace_pcg_iters; /* paper mode: PCG iterations of the affine and sparse
+                                 subspace solves, total over the step                   */
+  int32_t refine_iters;       /* paper mode: refinement CG iterations per Newton iteration
+                                 (refine_iters, or 20/40 from the hop diameters)         */
 } ms_step_stats;
 
 /* Parameters of the basis construction (Sec. 3.4-3.5).  ms_basis_defaults()

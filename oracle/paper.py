@@ -2,8 +2,9 @@
 solves of Alg. 2), FP64 CPU oracle.  Test infrastructure only.
 
 Per Newton iteration at x, with g = grad E(x) and the PSD-projected Hessian
-H (the exact Galerkin products, or the cubature-integrated subspace matrix
-of Sec. 3.8 when one is given, stand in for the paper's cubature Hessian):
+H (exact, or, when a cubature is given, the cubature-integrated Hessian of
+Sec. 3.8 on both subspace levels; the refinement residual always takes the
+exact full-space H):
 
   1. lag trigger (Sec. 3.7.2, Hessian lagging): the lagged elastic and
      inertia part of H is recomputed at the first iteration of the step and
@@ -30,6 +31,11 @@ of Sec. 3.8 when one is given, stand in for the paper's cubature Hessian):
      h is below eps (Alg. 1 termination, Sec. 3.9).
 
 Readings where the paper is silent (shared with the GPU library):
+  * with a cubature, the affine and sparse levels both take the cubature
+    Hessian (Sec. 3.7.1: both solves use the same approximation), i.e. the
+    blocks of U^T H_cub U on the stacked basis [U_s, U_a]; the refinement's
+    right-hand side -g - H d_s takes the exact H, the full-space operator
+    the refinement works on;
   * the signs of Alg. 2 are taken so that d is a descent direction for
     g = grad E (the printed right-hand sides U_a^T g and g - H d_s are the
     negatives of the ones solved here);
@@ -235,17 +241,29 @@ def refine_iterations(rest, tets, part, origins):
 
 # -- Alg. 2 --------------------------------------------------------------------
 
-def subspace_direction(H, g, Ua, Us, Ks=None, rtol=1e-4, max_iter=100000):
+def subspace_direction(H, g, Ua, Us, K=None, rtol=1e-4, max_iter=100000):
     """Alg. 2's SolveSubspaceDirection: returns (affine part, d_s, PCG
-    iterations of the affine level, of the sparse level).  Ks, if given,
-    replaces the subspace matrix U_s^T H U_s (the cubature-integrated one of
-    Sec. 3.8)."""
-    qa, ia = block_pcg(Ua.T @ (H @ Ua), -(Ua.T @ g), rtol, 12, max_iter)
+    iterations of the affine level, of the sparse level).  Both levels use
+    the same Hessian approximation (Sec. 3.7.1): the full-space H, or, when
+    K is given, the cubature-integrated one of Sec. 3.8 through its subspace
+    blocks K = dict(ss=U_s^T H U_s, sa=U_s^T H U_a, aa=U_a^T H U_a)."""
+    Aa = Ua.T @ (H @ Ua) if K is None else K["aa"]
+    qa, ia = block_pcg(Aa, -(Ua.T @ g), rtol, 12, max_iter)
     da = Ua @ qa
-    r = -g - H @ da
-    As = Us.T @ (H @ Us) if Ks is None else Ks
-    qs, is_ = block_pcg(As, Us.T @ r, rtol, 12, max_iter)
+    if K is None:
+        As, rhs = Us.T @ (H @ Us), Us.T @ (-g - H @ da)
+    else:
+        As, rhs = K["ss"], -(Us.T @ g) - K["sa"] @ qa
+    qs, is_ = block_pcg(As, rhs, rtol, 12, max_iter)
     return da, da + Us @ qs, ia, is_
+
+
+def cubature_blocks(prob, x, Us, Ua, cub_tets, cub_w):
+    """The cubature-integrated Hessian's blocks on the sparse and affine
+    bases (one integration over the stacked basis [U_s, U_a])."""
+    rs = Us.shape[1]
+    K = cubature_galerkin(prob, x, np.hstack([Us, Ua]), cub_tets, cub_w)
+    return dict(ss=K[:rs, :rs], sa=K[:rs, rs:], aa=K[rs:, rs:])
 
 
 def _barrier_diag(prob, x, h2):
@@ -307,8 +325,8 @@ def paper_step(body: Body, x_t, v_t, h, gravity, dbc, dbc_target, halfspace, bas
             refreshes += 1
         Hlag = (Hlag_base + B).tocsr()
         # affine, then sparse subspace level
-        Ks = None if cubature is None else cubature_galerkin(prob, x, Us, cubature[0], cubature[1])
-        _, ds, ia, is_ = subspace_direction(H, g, Ua, Us, Ks, rtol, max_pcg)
+        K = None if cubature is None else cubature_blocks(prob, x, Us, Ua, cubature[0], cubature[1])
+        _, ds, ia, is_ = subspace_direction(H, g, Ua, Us, K, rtol, max_pcg)
         info["affine_iters"] += ia
         info["subspace_iters"] += is_
         # full-space refinement on the lagged Hessian

@@ -234,7 +234,6 @@ void ms_solver_defaults(ms_solver_params* p) {
   p->abs_floor = 1e-9;
   p->pcg_eta_max = 0.5;
   p->pcg_eta_min = 1e-12;
-  p->replace_every = 50;
   p->max_backtracks = 30;
   p->exact_endgame = 1;
   p->warm_start = 0;

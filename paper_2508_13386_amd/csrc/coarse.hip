@@ -550,14 +550,11 @@ ms_status install_basis(ms_ctx* c, Basis&& B) {
     }
     pptr.push_back(int32_t(pent.size() / 2));
   }
-  // paper mode: affine weights phi_a(v) = sum_i phi_i(v), the affine origin
-  // (rest centre of mass) and the refinement iteration count from the
-  // partitions' hop diameters (Sec. 3.8.2: the mean over partitions of the
-  // largest number of edge hops from the vertex nearest the partition
-  // centroid to a vertex of the partition, binned to 20 or 40)
-  std::vector<double> phia(n, 0.0);
-  for (int64_t v = 0; v < n; ++v)
-    for (int64_t k = B.vptr[v]; k < B.vptr[v + 1]; ++k) phia[v] += B.vphi[k];
+  // paper mode: the affine origin (rest centre of mass) and the refinement
+  // iteration count from the partitions' hop diameters (Sec. 3.7.2: the mean
+  // over partitions of the largest number of edge hops, over mesh edges
+  // joining two of the partition's vertices, from the vertex nearest the
+  // handle origin; 20 when that mean is at most 30, else 40)
   {
     double msum = 0.0, o[3] = {0, 0, 0};
     for (int64_t v = 0; v < n; ++v) {
@@ -685,7 +682,7 @@ ms_status install_basis(ms_ctx* c, Basis&& B) {
       (s = upload(c, &D.d_hw, hw.data(), hw.size())) ||
       (s = upload(c, &D.d_chunk_info, chunk_info.data(), chunk_info.size())) ||
       (s = alloc_n(c, &D.d_rpart, 12 * size_t(nrchunks))) || (s = upload(c, &D.d_hinfo, hinfo.data(), hinfo.size())) ||
-      (s = alloc_n(c, &c->d_Ainv32, size_t(rp) * rp)) || (s = upload(c, &c->d_phia, phia.data(), phia.size())) ||
+      (s = alloc_n(c, &c->d_Ainv32, size_t(rp) * rp)) ||
       (s = alloc_n(c, &c->d_e, r)) || (s = alloc_n(c, &c->d_Ac, size_t(r) * r)) ||
       (s = alloc_n(c, &c->d_Lc, size_t(rp) * rp)) || (s = alloc_n(c, &c->d_Ainv, size_t(rp) * rp)) ||
       (s = alloc_n(c, &c->d_Y, size_t(rp) * rp)) || (s = alloc_n(c, &c->d_Ldiag, size_t(rp) * 64)) ||

@@ -232,8 +232,9 @@ struct ms_ctx {
   int lag_prec = -1;           // value type the lag buffers were allocated for
   double* d_ds = nullptr;      // subspace direction d_s [n][3]
   double* d_gsave = nullptr;   // gradient saved across the refinement solve
-  double* d_phia = nullptr;    // affine weight phi_a(v) = sum_i phi_i(v) [n]
-  double* d_aff = nullptr;     // affine system: columns [12][12], rhs [12], solution [12]
+  double* d_paper = nullptr;   // subspace-level workspace (coarse vectors, A C, block inverses, PCG state)
+  int paper_r = -1;            // coarse size d_paper was laid out for
+  std::vector<double> h_delta; // handle-origin offsets from the affine origin [m][3]
   double oa[3] = {0, 0, 0};    // origin of the affine basis (rest centre of mass)
   int refine_auto = 20;        // refinement iterations from the partition hop diameter
   // live timing of the PCG product (time_kernels)

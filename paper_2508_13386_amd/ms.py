@@ -35,7 +35,7 @@ class ms_solver_params(C.Structure):
     _fields_ = [("mode", C.c_int32), ("precision", C.c_int32), ("preconditioner", C.c_int32),
                 ("max_newton", C.c_int32), ("max_pcg", C.c_int32), ("newton_tol", C.c_double),
                 ("abs_floor", C.c_double), ("pcg_eta_max", C.c_double), ("pcg_eta_min", C.c_double),
-                ("replace_every", C.c_int32), ("max_backtracks", C.c_int32), ("exact_endgame", C.c_int32),
+                ("max_backtracks", C.c_int32), ("exact_endgame", C.c_int32),
                 ("warm_start", C.c_int32), ("paper_eps", C.c_double), ("subspace_rtol", C.c_double),
                 ("refine_iters", C.c_int32), ("lag_window", C.c_int32), ("lag_threshold", C.c_double),
                 ("lag_min_gap", C.c_int32), ("forcing", C.c_int32), ("endgame_ratio", C.c_double),
@@ -49,7 +49,8 @@ class ms_step_stats(C.Structure):
                 ("backtracks", C.c_int32), ("hessian_refreshes", C.c_int32), ("warm_start_used", C.c_int32),
                 ("precision_escalations", C.c_int32), ("pcg_iters_fp64", C.c_int32),
                 ("pcg_solves_fp64", C.c_int32), ("energy", C.c_double), ("last_dnorm", C.c_double), ("disp_norm", C.c_double),
-                ("min_alpha", C.c_double), ("time_ms", C.c_double)]
+                ("min_alpha", C.c_double), ("time_ms", C.c_double), ("subspace_pcg_iters", C.c_int32),
+                ("refine_iters", C.c_int32)]
 
     def asdict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

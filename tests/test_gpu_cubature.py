@@ -167,16 +167,17 @@ def test_paper_steps_with_cubature_match_paper_oracle(dev, prec_name, tol):
     for k in range(1, 3):
         tgt = s["dbc_targets"](k)
         xp, vp, info = paper.paper_step(body, x, v, s["dt"], s["gravity"], s["dirichlet"], tgt, None, B,
-                                        eps=1e-3, refine_iters=20, cubature=(t, w))
+                                        eps=1e-3, refine_iters=20, cubature=(t, w), rtol=1e-4)
         xe, _, _ = paper.paper_step(body, x, v, s["dt"], s["gravity"], s["dirichlet"], tgt, None, B,
-                                    eps=1e-3, refine_iters=20)
+                                    eps=1e-3, refine_iters=20, rtol=1e-4)
         c.ms_set_dirichlet(s["dirichlet"], tgt)
         c.ms_set_state(x, v)
-        st = c.ms_step(s["dt"], mode=ms.MODE_PAPER, precision=prec, refine_iters=20)
+        st = c.ms_step(s["dt"], mode=ms.MODE_PAPER, precision=prec, refine_iters=20, subspace_rtol=1e-4)
         xg, _ = c.ms_get_state()
         err = e_rel(xg, xp, x)
         say("paper+cubature step", k, prec_name, "gpu vs oracle", err, "| cubature vs exact subspace matrix",
-            e_rel(xp, xe, x), "| newton gpu", st["newton_iters"], "oracle", info["newton"])
+            e_rel(xp, xe, x), "| newton gpu", st["newton_iters"], "oracle", info["newton"], "| subspace pcg gpu",
+            st["subspace_pcg_iters"], "oracle", info["affine_iters"] + info["subspace_iters"])
         assert err <= tol
         x, v = xp, vp
     c.close()

@@ -16,7 +16,7 @@ def dev():
     return device()
 
 
-def _run(dev, s, m, steps, prec_name, tol, halfspace=None):
+def _run(dev, s, m, steps, prec_name, tol, refine=20, rtol=1e-4, counts=True):
     from paper_2508_13386_amd import ms
     prec = ms.PREC_MIXED if prec_name == "mixed" else ms.PREC_FP64
     c = ms.context_from_scene(dev, s)
@@ -26,14 +26,15 @@ def _run(dev, s, m, steps, prec_name, tol, halfspace=None):
     x, v = s["x0"].copy(), s["v0"].copy()
     for k in range(1, steps + 1):
         tgt = s["dbc_targets"](k)
+        rec = []
         xp, vp, info = paper.paper_step(body, x, v, s["dt"], s["gravity"], s["dirichlet"], tgt, s["halfspace"], B,
-                                        eps=1e-3, refine_iters=20)
+                                        eps=1e-3, refine_iters=refine or None, rtol=rtol, record=rec)
         xo, _, _ = newton.newton_step(body, x, v, s["dt"], s["gravity"], s["dirichlet"], tgt,
                                       halfspace=s["halfspace"])
         if len(s["dirichlet"]):
             c.ms_set_dirichlet(s["dirichlet"], tgt)
         c.ms_set_state(x, v)
-        st = c.ms_step(s["dt"], mode=ms.MODE_PAPER, precision=prec, refine_iters=20)
+        st = c.ms_step(s["dt"], mode=ms.MODE_PAPER, precision=prec, refine_iters=refine, subspace_rtol=rtol)
         xg, _ = c.ms_get_state()
         err = e_rel(xg, xp, x)
         approx = e_rel(xp, xo, x)
@@ -41,9 +42,16 @@ def _run(dev, s, m, steps, prec_name, tol, halfspace=None):
         e_bbox = float(np.linalg.norm(xp - xo, axis=1).max() / bbox)
         say(s["name"], "step", k, prec_name, "gpu vs paper oracle", err, "| paper vs exact e_rel", approx,
             "e_bbox", e_bbox, "| newton gpu", st["newton_iters"], "oracle", info["newton"],
-            "refreshes", st["hessian_refreshes"], "pcg", st["pcg_iters"])
+            "refreshes", st["hessian_refreshes"], "pcg", st["pcg_iters"], "subspace pcg gpu",
+            st["subspace_pcg_iters"], "oracle", info["affine_iters"] + info["subspace_iters"],
+            "refine", st["refine_iters"], info["refine_iters"], "| oracle per iteration",
+            [(r["affine_iters"], r["subspace_iters"]) for r in rec])
         assert err <= tol
-        assert st["newton_iters"] == info["newton"] or prec_name == "mixed"
+        assert st["refine_iters"] == info["refine_iters"]
+        if prec_name == "fp64" and counts:
+            assert st["newton_iters"] == info["newton"]
+            assert st["hessian_refreshes"] == info["refreshes"]
+            assert st["subspace_pcg_iters"] == info["affine_iters"] + info["subspace_iters"]
         assert approx < 1.0  # an approximation of the exact step, not a different motion
         x, v = xp, vp
     c.close()
@@ -57,13 +65,32 @@ def test_paper_steps_match_paper_oracle(dev, prec_name, tol):
     _run(dev, s, 8, 3, prec_name, tol)
 
 
-def test_paper_stiff_inclusions_match_paper_oracle(dev):
+def test_paper_steps_with_hop_rule_refinement(dev):
+    """refine_iters = 0: the library's 20/40 choice from the partitions' hop
+    diameters must be the oracle's (Sec. 3.7.2)."""
+    s = scenes.plain_cube(8, seed=2, steps=1)
+    _run(dev, s, 8, 1, "fp64", 1e-6, refine=0)
+
+
+@pytest.mark.parametrize("rtol,tol", [(1e-10, 1e-6), (1e-4, 2e-2)])
+def test_paper_stiff_inclusions_match_paper_oracle(dev, rtol, tol):
     """1e5 stiffness contrast: the approximation needs about 20 iterations and
-    stays well away from the exact step (reported, not asserted)."""
+    stays well away from the exact step (reported, not asserted).  The
+    subspace system is so ill-conditioned that a solve stopped at the
+    paper's relative residual of 1e-4 amplifies round-off: the oracle alone,
+    with the Galerkin product merely associated differently, moves the step
+    by 0.4% (first solve 218 vs 148 iterations).  Solved to 1e-10 that
+    sensitivity is 1e-8, so parity is asserted there at 1e-6; at 1e-4 the
+    two runs are held to 2e-2, five times the oracle's own spread."""
     s = scenes.inclusion_block(8, seed=0, steps=1)
-    _run(dev, s, 20, 1, "fp64", 1e-6)
+    _run(dev, s, 20, 1, "fp64", tol, rtol=rtol, counts=False)
 
 
 def test_paper_contact_steps_match_paper_oracle(dev):
+    """The face-disconnected gyroid gives handles with degenerate support, so
+    the subspace matrix is singular; a PCG residual that hovers at the stop
+    threshold then moves only null directions of U_s, and the iteration
+    counts of the two sides can differ while d_s (and the state) agree.
+    Counts are reported, not asserted."""
     s = scenes.gyroid_sphere(res=16)
-    _run(dev, s, 8, 2, "fp64", 1e-6)
+    _run(dev, s, 8, 2, "fp64", 1e-6, counts=False)
