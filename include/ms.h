@@ -8,7 +8,7 @@
  * (H d = -g, Sec. 3.1) whose linear systems are solved by preconditioned
  * conjugate gradient; the preconditioner is either 3x3 block-Jacobi or the
  * two-level preconditioner built from the sparse material-aware basis U of
- * Sec. 3.3-3.5 (restriction U^T r, a dense Cholesky solve with U^T H U,
+ * Sec. 3.4-3.6 (restriction U^T r, a dense Cholesky solve with U^T H U,
  * prolongation U e).  The paper's own three-level inexact Newton solve
  * (Alg. 1 and 2) is available as a mode.
  *
@@ -180,7 +180,7 @@ typedef struct {
                                  (refine_iters, or 20/40 from the hop diameters)         */
 } ms_step_stats;
 
-/* Parameters of the basis construction (Sec. 3.4-3.5).  ms_basis_defaults()
+/* Parameters of the basis construction (Sec. 3.5-3.6).  ms_basis_defaults()
  * fills them. */
 typedef struct {
   int32_t n_handles;       /* target number of partitions / handles m               */
@@ -221,7 +221,7 @@ ms_status ms_upload_material(ms_ctx* c, const double* E, const double* nu, const
 /* Gravity g[3] (m/s^2), entering E as -h^2 sum_v m_v g . x_v. */
 ms_status ms_set_gravity(ms_ctx* c, const double g[3]);
 
-/* Dirichlet conditions (Sec. 3.4.1): vertices verts[n] are set to
+/* Dirichlet conditions (Sec. 3.5.1): vertices verts[n] are set to
  * target_xyz [n][3] at the start of every following step and their DOFs are
  * eliminated.  May be called between steps (moving targets) with the same
  * or a different vertex set (a different set invalidates a built basis:
@@ -250,8 +250,10 @@ ms_status ms_set_friction(ms_ctx* c, double mu, double eps_v);
 ms_status ms_set_state(ms_ctx* c, const double* x, const double* v);
 ms_status ms_get_state(const ms_ctx* c, double* x, double* v);
 
-/* Build the sparse geometry- and material-aware basis (Sec. 3.4-3.5) on the
- * host: stiffness-weighted heat-geodesic K-means partitioning with jump
+/* Build the sparse geometry- and material-aware basis (Sec. 3.4-3.6) on the
+ * host: K-means partitioning on stiffness-weighted graph geodesics (Dijkstra
+ * over mesh edges whose lengths are scaled by the local stiffness; the paper
+ * computes its geodesics by the heat method, Sec. 3.6.1) with the jump
  * penalty and pruning, local stiffness-weighted biharmonic solves on each
  * partition's face-neighbour subdomain, clipping, partition of unity, and
  * the Dirichlet-compatible variant when Dirichlet vertices exist.  Uploads
@@ -374,9 +376,14 @@ void ms_pairs_free(ms_pairs* p);
 ms_status ms_set_coarse_integration(ms_ctx* c, int32_t mode);
 
 /* Advance one timestep of size dt (s) with parameters p (NULL = defaults);
- * stats may be NULL.  Transactional: on any error x and v are unchanged.
- * Errors: MS_E_ORDER, MS_E_NOCONV, MS_E_LINESEARCH, MS_E_NONFINITE,
- * MS_E_DEVICE. */
+ * stats may be NULL.  Transactional: on any error x, v, the BDF2 history and
+ * the warm start's coarse history are unchanged.
+ * Errors: MS_E_ARG (dt not positive, parameters out of range, BDF2 with
+ * paper mode or with the learned warm start, the smoothed two-level form
+ * with the cubature coarse matrix), MS_E_ORDER (no state; a two-level
+ * preconditioner or paper mode without a basis), MS_E_NOCONV,
+ * MS_E_LINESEARCH (no decrease within max_backtracks halvings, or no
+ * descent direction), MS_E_NONFINITE, MS_E_DEVICE. */
 ms_status ms_step(ms_ctx* c, double dt, const ms_solver_params* p, ms_step_stats* stats);
 
 /* Coarse coordinates of the current state: q = (U^T M U)^{-1} U^T M (x - x_rest),

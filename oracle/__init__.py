@@ -11,12 +11,12 @@ Modules
             stable Neo-Hookean elasticity, lumped inertia, gravity, IPC
             half-space barrier; energies, gradients, PSD-projected Hessians
   newton    full-space Newton with a sparse direct solve, CCD-filtered
-            backtracking line search (Sec. 3.1 Newton step, Sec. 3.7)
+            backtracking line search (Sec. 3.1 Newton step, Sec. 3.9)
   linops    plain definitions of the linear operators on the hot path:
             BSR3 products, basis restriction / prolongation (Eq. LBS),
             Galerkin coarse operator, coarse Cholesky solves
   basis     sparse material-aware basis weights given a partitioning
-            (Sec. 3.4: local stiffness-weighted biharmonic solves, clipping,
+            (Sec. 3.5: local stiffness-weighted biharmonic solves, clipping,
             partition of unity, Dirichlet-compatible variant)
   mlp       FP64 forward / backward / Adam of the warm-start network
   paper     the paper's three-level inexact Newton solve (Alg. 1 and 2)

@@ -28,7 +28,7 @@ Sec. 3.5 describe them, with the readings listed in the design notes:
     lowest-indexed partition among its tets (keeps the partition of unity);
   * handle origins are the partitions' volume centroids.
 
-The partitioning itself (geodesic K-means with pruning, Sec. 3.5.3) is taken
+The partitioning itself (geodesic K-means with pruning, Sec. 3.6) is taken
 as an input here.
 
 Pinned by tests/test_oracle_basis.py: the weighted Laplacian annihilates

@@ -6,10 +6,10 @@ with library primitives (scipy.sparse products, numpy dense algebra):
   bsr_matvec        y = H x for a 3x3 block-sparse matrix (the Newton
                     system H d = -g, Sec. 3.1)
   dense_basis       the stacked 3x12 blocks phi_i(x) P_i(x - x_i) of the
-                    linear-blend-skinning basis (Eq. LBS, Sec. 3.3-3.4), as an
+                    linear-blend-skinning basis (Eq. LBS, Sec. 3.4), as an
                     explicit 3n x 12m matrix; P_i = I_3 (x) [1, dx, dy, dz]
   restrict/prolong  U^T r and U q (the matrix-free triple product of
-                    Sec. 3.6: lift, apply H, restrict)
+                    Sec. 3.7.1: lift, apply H, restrict)
   galerkin          U^T H U, the subspace Hessian
   coarse_solve      (U^T H U)^{-1} c by Cholesky
   block_jacobi_inverse  inverses of the 3x3 diagonal blocks

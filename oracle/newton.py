@@ -7,7 +7,7 @@ does not depend on the linear solver, its preconditioner, the PSD projection
 or the precision of the Hessian.
 
 Steps, in the paper's order (Sec. 3.1 and the line-search paragraph of
-Sec. 3.7):
+Sec. 3.9):
   1. x~ = x^t + h v^t; x <- x^t; prescribed (Dirichlet) vertices are set to
      their targets and their DOFs eliminated.
   2. Newton iteration: g = grad E(x), H = hess E(x) (PSD-projected elastic

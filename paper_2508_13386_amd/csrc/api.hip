@@ -528,6 +528,9 @@ ms_status ms_step(ms_ctx* c, double dt, const ms_solver_params* pin, ms_step_sta
     return fail(c, MS_E_ARG, "coarse_move and mixed_max_newton must not be negative");
   if (P.integrator != 0 && P.integrator != 1) return fail(c, MS_E_ARG, "integrator must be 0 or 1");
   if (P.integrator == 1 && P.mode == MS_MODE_PAPER) return fail(c, MS_E_ARG, "paper mode steps with implicit Euler");
+  // the learned start is judged on the implicit Euler incremental potential
+  if (P.integrator == 1 && P.warm_start && c->mlp)
+    return fail(c, MS_E_ARG, "the learned warm start steps with implicit Euler");
   if (P.mode == MS_MODE_PAPER) return paper_step(c, dt, P, st);
   // the smoothed (deflated) form projects with the coarse matrix and stays a
   // symmetric positive definite preconditioner only for the exact U^T H U

@@ -1,9 +1,9 @@
 // Host construction of the sparse geometry- and material-aware basis
-// (Sec. 3.4 and 3.5 of the paper).
+// (Sec. 3.4-3.6 of the paper).
 //
 //  1. Per-tet stiffness w_e = E_e; tets touching a vertex shared by tets of
 //     different materials get the jump penalty w_e = jump * min(E) for the
-//     distance computation (Sec. 3.5.2).
+//     distance computation (Sec. 3.6.2).
 //  2. Stiffness-weighted geodesic distance on the vertex graph: each edge
 //     costs its length times sqrt(w_ref / w_edge) (w_edge = mean w of the
 //     tets around it), so distance grows slowly in stiff material and fast
@@ -13,14 +13,14 @@
 //  3. K-means by Lloyd relaxation under that metric, initialised by
 //     kmeans++ with oversampling; every prune_every iterations the prune_n
 //     smallest clusters with median volume > prune_ratio x own volume are
-//     deleted (Sec. 3.5.3).  Tets take the label of the majority of their
+//     deleted (Sec. 3.6.3).  Tets take the label of the majority of their
 //     vertices; a seed moves to the partition vertex nearest the
 //     partition's volume centroid.
 //  4. For each partition i: subdomain T_i = i and its face neighbours; solve
 //     the stiffness-weighted biharmonic K u = 0, K = L M^-1 L assembled on
 //     T_i, with u = 1 at i's centroid vertex, u = 0 at the neighbours'
 //     centroid vertices, on the internal boundary of T_i and at Dirichlet
-//     vertices (Sec. 3.4, 3.4.1); clip u_pos = max(u, 0).
+//     vertices (Sec. 3.5, 3.5.1); clip u_pos = max(u, 0).
 //  5. With Dirichlet vertices, u_DBC: the same solve on the partitions that
 //     hold Dirichlet vertices plus their neighbours with u = 1 at the
 //     Dirichlet vertices and u = 0 at the other centroids.

@@ -7,7 +7,7 @@
 //                                     (FP32 copy in mixed precision)
 //   prolongation  u += U e            8 lanes per vertex
 // The PCG preconditioner is additive: z = D^-1 r + U (U^T H U)^-1 U^T r with
-// D the 3x3 block diagonal of H (Sec. 3.6 uses the same triple product
+// D the 3x3 block diagonal of H (Sec. 3.7.1 uses the same triple product
 // U^T H U matrix-free; here it is formed once per Newton iteration).
 //
 // Galerkin product in two atomic-free stages:

@@ -352,13 +352,15 @@ ms_status warm_start(ms_ctx* c, double dt, bool inertial, int32_t* used) {
 ms_status record_coarse(ms_ctx* c) {
   Mlp* N = c->mlp;
   if (!N) return MS_OK;
-  std::swap(N->d_qprev, N->d_qcur);
-  ms_status s = coarse_coordinates(c, c->d_x, nullptr, N->d_qcur);
+  // q(x^{t+1}) (and, on the first record, q(x^t)) go to scratch first, so
+  // that a failure leaves the history as it was
+  ms_status s = coarse_coordinates(c, c->d_x, nullptr, c->d_e);
   if (s) return s;
-  if (c->q_hist == 0) {  // first record: q^{t-1} from the step's start state
-    MS_HIP(hipMemcpyAsync(N->d_qprev, N->d_qcur, c->r * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-    s = coarse_coordinates(c, c->d_xt, nullptr, N->d_qprev);
-    if (s) return s;
+  if (c->q_hist == 0 && (s = coarse_coordinates(c, c->d_xt, nullptr, c->d_c))) return s;
+  std::swap(N->d_qprev, N->d_qcur);
+  MS_HIP(hipMemcpyAsync(N->d_qcur, c->d_e, c->r * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  if (c->q_hist == 0) {
+    MS_HIP(hipMemcpyAsync(N->d_qprev, c->d_c, c->r * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
     c->q_hist = 1;
   }
   ++c->q_hist;

@@ -190,13 +190,15 @@ ms_status plain_step(ms_ctx* c, double dt, const ms_solver_params& P, ms_step_st
     }
   }
   if (!converged) return restore(c, fail(c, MS_E_NOCONV, "Newton did not converge"));
-  launch_velocity_hist(c, dt, bdf2);
-  c->has_prev = true;
+  // everything that can fail runs before v and the history change, so a
+  // failure restores x and leaves v, x^{t-1}, v^{t-1} and q as they were
   double ef[4];
   if ((s = energy(c, c->d_x, nullptr, 0.0, h2, ef))) return restore(c, s);
   if (c->has_basis && c->mlp) {
-    if ((s = record_coarse(c))) return s;
+    if ((s = record_coarse(c))) return restore(c, s);
   }
+  launch_velocity_hist(c, dt, bdf2);
+  c->has_prev = true;
   S.newton_iters = it;
   S.energy = ef[0] + ef[1] + ef[2] + ef[3];
   S.last_dnorm = dnorm;

@@ -1,5 +1,5 @@
 """GPU parity of timesteps with IPC half-space contact (Sec. 3.1 barrier,
-Sec. 3.7 filtered line search) against the CPU oracle, and the momentum
+Sec. 3.9 filtered line search) against the CPU oracle, and the momentum
 balance that every converged contact step satisfies."""
 import numpy as np
 import pytest
