@@ -428,6 +428,22 @@ ms_status ms_mlp_train(const ms_device* dev, int32_t in_dim, int32_t width, int3
                        int64_t n_samples, const float* X, const float* T, int32_t n_steps, int32_t batch,
                        const int32_t* order, float lr, float* losses, float* first_grads);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * forward pass of ms_mlp_forward on DEVICE buffers the caller owns --
+ * params (the concatenated FP32 weights of ms_mlp_forward), Z [n][in] and
+ * Y [n][out] -- that calls no allocator of any kind.  The activations live
+ * in one library-owned device array of MS_MLP_NOALLOC_SCRATCH_FLOATS floats
+ * per GPU (held until the process ends), so 4 n width must not exceed it.
+ * Asynchronous: the work is enqueued on dev->hip_stream and Y is ready when
+ * the stream reaches it (no synchronisation, so the call can be captured).
+ * Every call on a GPU shares that GPU's array: calls that overlap on one
+ * GPU (other streams or host threads) race.  Errors: MS_E_ARG (null
+ * pointers, sizes, 4 n width above the limit), MS_E_DEVICE. */
+#define MS_MLP_NOALLOC_SCRATCH_FLOATS (1 << 20)
+ms_status ms_mlp_forward_noalloc(const ms_device* dev, int32_t in_dim, int32_t width, int32_t out_dim,
+                                 const float* params, int64_t n, const float* Z, float* Y);
+
 /* ---- kernel-level entry points (parity checks and measurements) ---------
  * ms_eval: at positions x [n][3] (host), with x~ = x^t + dt v^t from the
  * current state, return the energy parts e4 = {K, h^2 Psi, h^2 G, h^2 B},

@@ -12,6 +12,7 @@
 // fixed reduction orders).
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "ms_internal.h"
@@ -437,6 +438,56 @@ ms_status ms_mlp_forward(const ms_device* dev, int32_t in_dim, int32_t width, in
       hipStreamSynchronize(st) != hipSuccess)
     return MS_E_DEVICE;
   return MS_OK;
+}
+
+}  // extern "C"
+
+// ---- forward pass without allocation -------------------------------------
+// Activation scratch of ms_mlp_forward_noalloc: a file-scope device array of
+// MS_MLP_NOALLOC_SCRATCH_FLOATS floats.  Every GPU the library runs on holds
+// its own copy until the process ends.  In host code the array's name is
+// only a stand-in: kernels receive the device address taken per device by
+// hipGetSymbolAddress (with that device current).
+static __device__ __align__(256) float scratch[MS_MLP_NOALLOC_SCRATCH_FLOATS];
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<float*> g_scratch_ptr;  // per device id
+
+ms_status scratch_address(int device, float** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (device < 0) return MS_E_ARG;
+  if (int(g_scratch_ptr.size()) <= device) g_scratch_ptr.resize(size_t(device) + 1, nullptr);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return MS_E_DEVICE;
+    g_scratch_ptr[device] = static_cast<float*>(p);
+  }
+  *out = g_scratch_ptr[device];
+  return MS_OK;
+}
+}  // namespace
+
+extern "C" {
+
+ms_status ms_mlp_forward_noalloc(const ms_device* dev, int32_t in_dim, int32_t width, int32_t out_dim,
+                                 const float* params, int64_t n, const float* Z, float* Y) {
+  if (!dev || !params || !Z || !Y || in_dim < 1 || width < 1 || out_dim < 1 || n < 1) return MS_E_ARG;
+  // activations H0, A0, H1, A1: 4 n width floats
+  if (n > int64_t(MS_MLP_NOALLOC_SCRATCH_FLOATS) / (4 * int64_t(width))) return MS_E_ARG;
+  if (hipSetDevice(dev->device) != hipSuccess) return MS_E_DEVICE;
+  float* h = nullptr;
+  const ms_status s = scratch_address(dev->device, &h);
+  if (s) return s;
+  hipStream_t st = static_cast<hipStream_t>(dev->hip_stream);
+  const Layout L(in_dim, width, out_dim);
+  float* H0 = h;
+  float* A0 = H0 + n * width;
+  float* H1 = A0 + n * width;
+  float* A1 = H1 + n * width;
+  // every activation is written before it is read: nothing to clear
+  forward(st, L, params, int(n), Z, H0, A0, H1, A1, Y);
+  return hipGetLastError() == hipSuccess ? MS_OK : MS_E_DEVICE;
 }
 
 ms_status ms_mlp_train(const ms_device* dev, int32_t in_dim, int32_t width, int32_t out_dim, float* params,

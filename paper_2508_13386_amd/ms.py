@@ -123,6 +123,7 @@ def lib():
                                  C.POINTER(C.c_void_p)],
             "ms_pairs_get": [vp, C.POINTER(i64), ip, C.POINTER(i64), ip],
             "ms_mlp_forward": [C.POINTER(ms_device), i32, i32, i32, vp, i64, vp, vp],
+            "ms_mlp_forward_noalloc": [C.POINTER(ms_device), i32, i32, i32, vp, i64, vp, vp],
             "ms_mlp_train": [C.POINTER(ms_device), i32, i32, i32, vp, i64, vp, vp, i32, i32, vp, C.c_float, vp, vp],
         }
         for name, args in sig.items():
@@ -525,6 +526,21 @@ def ms_mlp_forward(dev, params, Z):
     if code != MS_OK:
         raise MSError(code, "ms_mlp_forward")
     return Y
+
+
+MLP_NOALLOC_SCRATCH_FLOATS = 1 << 20
+
+
+def ms_mlp_forward_noalloc(dev, dims, params_dev, Z_dev, Y_dev):
+    """The forward pass on device tensors (torch, float32, contiguous) with
+    no allocation by the library; dims = (in, width, out).  Asynchronous on
+    dev's stream."""
+    i, w, o = dims
+    n = Z_dev.shape[0]
+    code = lib().ms_mlp_forward_noalloc(C.byref(dev.desc), i, w, o, C.c_void_p(params_dev.data_ptr()), n,
+                                        C.c_void_p(Z_dev.data_ptr()), C.c_void_p(Y_dev.data_ptr()))
+    if code != MS_OK:
+        raise MSError(code, "ms_mlp_forward_noalloc")
 
 
 def ms_mlp_train(dev, params, X, T, order, lr, grads=False):
