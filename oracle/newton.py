@@ -56,11 +56,14 @@ def ccd_bound(x, d, halfspace, safety=0.9):
 
 
 def newton_step(body: Body, x_t, v_t, h, gravity, dbc=None, dbc_target=None, halfspace=None,
-                dense=False, max_iter=100, tol=1e-12, project=True, record=None, prev=None):
-    """One timestep; prev = (x^{t-1}, v^{t-1}) selects BDF2, else implicit Euler."""
+                dense=False, max_iter=100, tol=1e-12, project=True, record=None, prev=None, x_start=None):
+    """One timestep; prev = (x^{t-1}, v^{t-1}) selects BDF2, else implicit
+    Euler.  x_start (default x^t) is the first Newton iterate: the minimiser
+    does not depend on it as long as it lies in the same basin, so a start
+    near the answer only saves iterations."""
     x_t = np.asarray(x_t, dtype=np.float64)
     prob = StepProblem(body, x_t, v_t, h, gravity, halfspace, prev)
-    x = x_t.copy()
+    x = (x_t if x_start is None else np.asarray(x_start, dtype=np.float64)).copy()
     n = body.n
     free = np.ones((n, 3), dtype=bool)
     if dbc is not None and len(dbc):

@@ -179,10 +179,10 @@ Partitioning kmeans(const ms_ctx* c, const Graph& G, const ms_basis_params& P) {
     }
   }
   std::vector<int> tl(T, 0);
-  for (int it = 0; it < std::max(1, P.max_lloyd); ++it) {
+  // Voronoi cells of the seeds, then every tet takes the majority label of
+  // its vertices (ties: the nearer vertex)
+  auto label_tets = [&]() {
     voronoi(G, seeds, label, dist);
-    const int k = int(seeds.size());
-    // tets: majority label of their vertices (ties: the nearer vertex)
     for (int64_t t = 0; t < T; ++t) {
       int best = -1, bc = 0;
       double bd = 1e300;
@@ -199,6 +199,12 @@ Partitioning kmeans(const ms_ctx* c, const Graph& G, const ms_basis_params& P) {
       }
       tl[t] = best < 0 ? 0 : best;
     }
+  };
+  bool labels_stale = false;  // tl refers to a seed set that pruning has since changed
+  for (int it = 0; it < std::max(1, P.max_lloyd); ++it) {
+    label_tets();
+    labels_stale = false;
+    const int k = int(seeds.size());
     std::vector<double> vol(k, 0.0), cen(3 * k, 0.0);
     for (int64_t t = 0; t < T; ++t) {
       const int l = tl[t];
@@ -227,7 +233,10 @@ Partitioning kmeans(const ms_ctx* c, const Graph& G, const ms_basis_params& P) {
         pruned = true;
       }
     }
-    if (pruned) continue;
+    if (pruned) {
+      labels_stale = true;
+      continue;
+    }
     // move each seed to the partition vertex nearest the volume centroid
     std::vector<int> nseeds(seeds);
     std::vector<double> bestd(k, 1e300);
@@ -248,6 +257,9 @@ Partitioning kmeans(const ms_ctx* c, const Graph& G, const ms_basis_params& P) {
     if (nseeds == seeds && !(int(seeds.size()) > m_target && !P.lattice_seeding)) break;
     seeds.swap(nseeds);
   }
+  // the Lloyd budget can end right after a pruning round: label the tets
+  // of the remaining seeds before compacting
+  if (labels_stale) label_tets();
   // compact labels (drop empty partitions)
   std::vector<int> remap(seeds.size(), -1);
   Partitioning out;

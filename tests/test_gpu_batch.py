@@ -5,7 +5,8 @@ import numpy as np
 import pytest
 
 import scenes
-from tests.gpu_util import device, say
+from oracle import fem, newton
+from tests.gpu_util import device, e_rel, say
 
 pytestmark = pytest.mark.gpu
 
@@ -29,7 +30,9 @@ def test_batch_equals_unbatched(dev, prec_name, forcing):
     ref = _contexts(dev, scs)
     bat = _contexts(dev, scs)
     dt = scs[0]["dt"]
+    bodies = [fem.Body(s["rest"], s["tets"], s["E"], s["nu"], s["rho"]) for s in scs]
     for step in range(1, 3):
+        starts = [c.ms_get_state() for c in bat]
         st_ref = [c.ms_step(dt, precision=prec, forcing=forcing) for c in ref]
         st_bat = ms.ms_batch_step(bat, dt, precision=prec, forcing=forcing)
         for q, (cr, cb) in enumerate(zip(ref, bat)):
@@ -42,6 +45,14 @@ def test_batch_equals_unbatched(dev, prec_name, forcing):
             assert st_ref[q]["newton_iters"] == st_bat[q]["newton_iters"]
             assert st_ref[q]["pcg_iters"] == st_bat[q]["pcg_iters"]
             assert np.array_equal(xr, xb) and np.array_equal(vr, vb)
+            # and each batched scene reaches the oracle's minimiser from the same state
+            x0, v0 = starts[q]
+            sc = scs[q]
+            xo, _, _ = newton.newton_step(bodies[q], x0, v0, dt, sc["gravity"], sc["dirichlet"],
+                                          sc["dbc_targets"](step))
+            err = e_rel(xb, xo, x0)
+            say("   scene", q, "batched vs oracle e_rel", err)
+            assert err <= 1e-6
     for c in ref + bat:
         c.close()
 

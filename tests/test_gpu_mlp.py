@@ -38,7 +38,31 @@ def test_mlp_forward_matches_oracle(dev, dims, n):
     assert err.max() <= 3 * 2.0 ** -8
 
 
+def _grad_scales(p, Z, Y, T):
+    """Absolute-value propagation of the backward pass: the same sums as the
+    gradients with every operand replaced by an upper bound of its magnitude
+    (forward magnitudes as in _abs_bound, |silu| <= |t|, silu' <= 1.1), plus
+    the forward error scale in dY.  Each bf16 product contributes at most
+    2 * 2^-8 of its absolute value and the deepest gradient passes through
+    five rounded products (three forward, two backward), so every entry's
+    error stays below 10 * 2^-8 of its scale."""
+    h0 = np.abs(Z) @ np.abs(p["W0"]).T + np.abs(p["b0"])
+    a0 = 1.1 * h0
+    h1 = a0 @ np.abs(p["W1"]).T + np.abs(p["b1"])
+    a1 = 1.1 * h1
+    yabs = a1 @ np.abs(p["W2"]).T + np.abs(p["b2"])
+    dY = 2.0 * (np.abs(Y - T) + yabs) / Y.size
+    S = {"W2": dY.T @ a1, "b2": dY.sum(axis=0)}
+    dh1 = 1.1 * (dY @ np.abs(p["W2"]))
+    S["W1"], S["b1"] = dh1.T @ a0, dh1.sum(axis=0)
+    dh0 = 1.1 * (dh1 @ np.abs(p["W1"]))
+    S["W0"], S["b0"] = dh0.T @ np.abs(Z), dh0.sum(axis=0)
+    return S
+
+
 def test_mlp_first_gradients_match_oracle(dev):
+    """Every gradient entry within the bf16 error bound of its propagated
+    absolute scale (elementwise, not through a norm)."""
     from paper_2508_13386_amd import ms
     i, w, o = 72, 48, 36
     p = scenes.mlp_init(i, w, o, seed=3)
@@ -46,16 +70,27 @@ def test_mlp_first_gradients_match_oracle(dev):
     X = rng.standard_normal((100, i)).astype(np.float32)
     T = np.tanh(X[:, :o]).astype(np.float32)
     order = scenes.minibatch_order(100, 32, 1, seed=5)
-    _, losses, g = ms.ms_mlp_train(dev, p, X, T, order, lr=1e-3, grads=True)
+    lr = 1e-3
+    p1, losses, g = ms.ms_mlp_train(dev, p, X, T, order, lr=lr, grads=True)
     p64 = {k: v.astype(np.float64) for k, v in p.items()}
     idx = order[0]
-    Yo, cache = mlp.forward(p64, X[idx].astype(np.float64))
+    Z = X[idx].astype(np.float64)
+    Yo, cache = mlp.forward(p64, Z)
     go = mlp.backward(p64, cache, Yo, T[idx].astype(np.float64))
+    S = _grad_scales(p64, Z, Yo, T[idx].astype(np.float64))
     assert losses[0] == pytest.approx(mlp.loss(Yo, T[idx]), rel=2e-2)
     for k in go:
-        rel = np.linalg.norm(g[k] - go[k]) / np.linalg.norm(go[k])
-        say("grad", k, "rel", rel)
-        assert rel <= 5e-2
+        err = np.abs(g[k] - go[k]) / S[k]
+        say("grad", k, "max err / scale", float(err.max()), "bound", 10 * 2.0 ** -8)
+        assert err.max() <= 10 * 2.0 ** -8
+        # Adam's first step moves each weight by -lr g / (|g| + eps): -lr sign(g)
+        # wherever the GPU gradient's sign is the oracle's (its error is below
+        # half the gradient) and |g| is well above eps
+        sure = (np.abs(go[k]) > 2 * np.abs(g[k] - go[k])) & (np.abs(go[k]) > 1e-5)
+        say("   adam first step checked on", int(sure.sum()), "of", sure.size)
+        if sure.any():
+            step = (p1[k] - p[k])[sure]
+            assert np.abs(step + lr * np.sign(go[k][sure])).max() <= 1e-3 * lr
 
 
 def test_mlp_training_tracks_oracle(dev):
@@ -69,7 +104,7 @@ def test_mlp_training_tracks_oracle(dev):
     _, lo = mlp.train(p0, X.astype(np.float64), T.astype(np.float64), order, lr=3e-3)
     say("loss gpu", lg[0], lg[-1], "oracle", lo[0], lo[-1])
     assert np.mean(lg[-20:]) < 0.2 * np.mean(lg[:5])
-    assert np.mean(lg[-20:]) <= 2.0 * np.mean(lo[-20:]) + 1e-4
+    assert np.mean(lg[-20:]) <= 1.5 * np.mean(lo[-20:]) + 1e-4
 
 
 def test_warm_started_steps_match_oracle(dev):

@@ -16,9 +16,9 @@ def dev():
     return device()
 
 
-def _setup(dev, N=6, m=8, seed=0):
+def _setup(dev, N=6, m=8, seed=0, scene="inclusion_block"):
     from paper_2508_13386_amd import ms
-    s = scenes.inclusion_block(N, seed=seed, steps=3)
+    s = scenes.inclusion_block(N, seed=seed, steps=3) if scene == "inclusion_block" else scenes.plain_cube(N, seed=seed)
     c = ms.context_from_scene(dev, s)
     c.ms_build_basis(n_handles=m, seed=1)
     return s, c
@@ -121,16 +121,33 @@ def test_two_level_apply_matches_dense(dev):
     c.close()
 
 
-@pytest.mark.parametrize("prec_name", ["fp64", "mixed"])
-def test_two_level_additive_apply_several_blocks(dev, prec_name):
+@pytest.mark.parametrize("prec_name,m,path", [("fp64", 16, "direct"), ("mixed", 16, "direct"),
+                                              ("fp64", 130, "gemv tail"), ("fp64", 2, "multi-chunk"),
+                                              ("mixed", 2, "multi-chunk")])
+def test_two_level_additive_apply_several_blocks(dev, prec_name, m, path):
     """The additive preconditioner (restriction by update-block segments, as
     in the PCG loop) on a mesh spanning several 256-vertex blocks with a
-    ragged last block; mixed precision applies FP32 inverses."""
+    ragged last block; mixed precision applies FP32 inverses.  The cases also
+    reach the two coarse paths the benchmarked forms take: an FP64 coarse
+    GEMV over more than 1280 columns (the loop after the preloaded row
+    pieces; the FP64 bench form has r = 2304), and handles with more than
+    1024 basis entries, whose restriction spans several chunks so that the
+    GEMV sums chunk partials per handle.  The tail case runs on the plain
+    cube: 170 handles on the 12^3 block with its 1e5 contrast make U^T H U
+    numerically singular (condition 3e16, so the regularisation of null
+    pivots, not the GEMV, would decide the comparison), while on the cube
+    the condition number is about 1e6."""
     from paper_2508_13386_amd import ms
     prec = ms.PREC_MIXED if prec_name == "mixed" else ms.PREC_FP64
-    s, c = _setup(dev, N=12, m=16, seed=3)
+    s, c = _setup(dev, N=12, m=m, seed=3, scene="plain_cube" if path == "gemv tail" else "inclusion_block")
     B = c.ms_get_basis()
-    say("n", len(s["rest"]), "basis nnz", len(B["vphi"]), prec_name)
+    per_handle = np.bincount(B["vhandle"], minlength=B["m"])
+    say("n", len(s["rest"]), "basis m", B["m"], "r", 12 * B["m"], "nnz", len(B["vphi"]),
+        "largest handle", int(per_handle.max()), prec_name, path)
+    if path == "gemv tail":
+        assert 12 * B["m"] > 1280
+    elif path == "multi-chunk":
+        assert per_handle.max() > 1024
     x = s["rest"] + 0.001 * np.random.default_rng(5).standard_normal(s["rest"].shape)
     _, _, Hb = c.ms_eval(x, s["dt"], prec=prec)
     rp, col = c.ms_get_pattern()

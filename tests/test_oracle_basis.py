@@ -162,3 +162,27 @@ def test_host_basis_matches_oracle(scene, m, dbc, rtol, atol):
         orc_row = out["rows"][v]
         assert [i for i, _ in lib_row] == [i for i, _ in orc_row], v
         assert np.allclose([p for _, p in lib_row], [p for _, p in orc_row], rtol=rtol, atol=atol), v
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+@pytest.mark.parametrize("m", [40, 130])
+def test_host_basis_when_pruning_meets_the_lloyd_budget(m):
+    """Regression: with more oversampled seeds than pruning rounds can remove,
+    the last Lloyd iteration prunes; the partition must then be relabelled
+    for the remaining seeds (it was compacted with the previous seed set's
+    labels).  Every tet gets a valid partition, the weights are non-negative
+    and at free vertices they sum to at most one (the Dirichlet weight takes
+    the rest); the same case, checked against the oracle, gives the basis of
+    the handle-count sweeps."""
+    from paper_2508_13386_amd import ms
+    s = scenes.inclusion_block(12, seed=3, steps=3)
+    b = ms.ms_basis_compute(s["rest"], s["tets"], s["E"], s["dirichlet"], n_handles=m, seed=1)
+    assert b["m"] >= m
+    assert b["part"].min() >= 0 and b["part"].max() < b["m"]
+    assert len(np.unique(b["part"])) == b["m"]
+    assert (b["vphi"] >= 0).all()
+    n = len(s["rest"])
+    sums = np.bincount(np.repeat(np.arange(n), np.diff(b["vptr"])), weights=b["vphi"], minlength=n)
+    free = np.ones(len(s["rest"]), bool)
+    free[s["dirichlet"]] = False
+    assert sums[free].max() <= 1 + 1e-12
