@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--coarse-every", type=int, default=1,
                     help="rebuild U^T H U and its inverse every this many Newton iterations (0: once per step)")
     ap.add_argument("--endgame-fp64", type=int, default=1, help="mixed precision: FP64 Hessian in the Newton endgame")
+    ap.add_argument("--newton-tol", type=float, default=1e-9,
+                    help="Newton stop: a full step with ||d|| <= newton_tol * ||x - x^t||")
     ap.add_argument("--endgame-ratio", type=float, default=1e-3,
                     help="endgame once ||d|| <= ratio * ||x - x^t|| (exact Hessian; FP64 with --endgame-fp64)")
     ap.add_argument("--no-accuracy", action="store_true",
@@ -104,11 +106,12 @@ def parse():
 
 def cpu_baseline(scene="block", grid=32, n_tets=None):
     """The CPU oracle (FP64 Newton + SuperLU, half-space barrier and CCD
-    filter for the contact scene) on a bounded sample: one timestep of the
-    same generator at a lower resolution (half the grid; 3/8 of it for the
-    contact scene, whose oracle step is costlier), one thread, scaled to the
-    workload by its tet count (linear scaling: a lower bound on the oracle's
-    cost, whose sparse solve grows faster)."""
+    filter for the contact scene) on a bounded sample for the scenes other
+    than the heterogeneous block: one timestep of the same generator at a
+    lower resolution (half the grid; 3/8 of it for the contact scene, whose
+    oracle step is costlier), one thread, scaled to the workload by its tet
+    count (linear scaling: a lower bound on the oracle's cost, whose sparse
+    solve grows faster)."""
     from threadpoolctl import threadpool_limits
 
     import scenes
@@ -127,9 +130,64 @@ def cpu_baseline(scene="block", grid=32, n_tets=None):
                            halfspace=s["halfspace"])
         dt = time.perf_counter() - t0
     ratio = (n_tets or 8 * len(s["tets"])) / len(s["tets"])
-    return dict(value=1.0 / (dt * ratio), unit="timesteps/s", cores=1, kind="oracle",
+    return dict(value=1.0 / (dt * ratio), unit="timesteps/s", cores=1, kind="oracle", cpu=cpu_model(),
                 sample=f"one timestep of the same generator at {g}^3 ({len(s['tets']):,} tets) took {dt:.1f} s on "
                        f"1 thread; value = 1/({ratio:.2f} x that), linear tet-count scaling to the workload")
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def oracle_on_workload(s, check, threads):
+    """One Newton iteration of the CPU oracle on the benchmarked workload
+    itself: the checked timestep k from the GPU's start state (x^t, v^t),
+    with the oracle's Newton started at the GPU's converged state (the
+    minimiser does not depend on the first iterate, so one exact Newton
+    correction lands on the oracle's own minimiser).  Returns the seconds
+    per oracle Newton iteration (mesh precompute excluded), the iterations,
+    e_rel = ||x_gpu - x_orc|| / ||x_orc - x^t|| and the BLAS threads used."""
+    from threadpoolctl import threadpool_info, threadpool_limits
+
+    from oracle import fem, newton
+    x0, v0, x1, k = check["x0"], check["v0"], check["x1"], check["step"]
+    body = fem.Body(s["rest"], s["tets"], s["E"], s["nu"], s["rho"])
+    with threadpool_limits(limits=threads):
+        used = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+        t0 = time.perf_counter()
+        xo, _, its = newton.newton_step(body, x0, v0, s["dt"], s["gravity"], s["dirichlet"], s["dbc_targets"](k),
+                                        halfspace=s["halfspace"], x_start=x1)
+        dt = time.perf_counter() - t0
+    e = float(np.linalg.norm(x1 - xo) / np.linalg.norm(xo - x0))
+    return dt / max(1, its), its, e, used
+
+
+def cpu_baseline_on_workload(s, check):
+    """cpu_baseline of the heterogeneous block: the oracle's seconds per
+    Newton iteration measured on the workload itself (oracle_on_workload),
+    times the Newton iterations of that timestep (the GPU's count: a whole
+    oracle step, about ten minutes at this size, is more than a bounded
+    sample), on one thread (SuperLU is sequential), and the same with all
+    host threads."""
+    per_it, its, e, _ = oracle_on_workload(s, check, 1)
+    per_all, _, _, used = oracle_on_workload(s, check, None)
+    n_it = check["newton_iters"]
+    out = dict(value=1.0 / (per_it * n_it), unit="timesteps/s", cores=1, kind="oracle", cpu=cpu_model(),
+               host_cores=os.cpu_count(),
+               sample=f"one oracle Newton iteration (assembly, SuperLU factorisation and solve) on the "
+                      f"{len(s['tets']):,}-tet workload itself, timestep {check['step']}: {per_it:.1f} s on 1 "
+                      f"thread; value = 1/({n_it} Newton iterations x that)",
+               all_cores=dict(value=1.0 / (per_all * n_it), cores=used,
+                              sample=f"the same iteration with all host threads: {per_all:.1f} s"))
+    return out, dict(step=check["step"], e_rel=e, oracle_newton_iters=its, bound=1e-6,
+                     check="the GPU's converged state of this timestep against the oracle's minimiser "
+                           "(FP64 Newton + SuperLU) from the same start state")
 
 
 def measured_traffic(kernel_name, workload):
@@ -253,13 +311,15 @@ def step_errors(dev, s, ctx, params, warmup, steps):
                                  newton_tol=1e-11, max_newton=100)
     ctx.ms_set_state(s["x0"], s["v0"])
     errs = []
+    last = None
     for k in range(1, warmup + steps + 1):
         ctx.ms_set_dirichlet(s["dirichlet"], s["dbc_targets"](k))
         x0, v0 = ctx.ms_get_state()
-        ctx.ms_step(s["dt"], params)
+        st = ctx.ms_step(s["dt"], params)
         x1, _ = ctx.ms_get_state()
         if k <= warmup:
             continue
+        last = dict(step=k, x0=x0, v0=v0, x1=x1, newton_iters=int(st["newton_iters"]))
         tight.ms_set_dirichlet(s["dirichlet"], s["dbc_targets"](k))
         tight.ms_set_state(x0, v0)
         tight.ms_step(s["dt"], tparams)
@@ -268,7 +328,7 @@ def step_errors(dev, s, ctx, params, warmup, steps):
     tight.close()
     return {"check": "each timed step vs the same step solved by FP64 block-Jacobi Newton-PCG to "
                      "||d|| <= 1e-11 ||x - x^t|| from the same state", "e_rel_per_step": errs,
-            "e_rel_max": max(errs), "bound": 1e-6}
+            "e_rel_max": max(errs), "bound": 1e-6}, last
 
 
 def batch_main(a):
@@ -584,7 +644,7 @@ def cubature_main(a):
     v_cu, el_cu, st_cu, states_cu, cctx, _ = run(dev, s, params, a.warmup, a.steps, basis=basis,
                                                  cubature=(tets, w))
     print(f"# cubature coarse matrix: {v_cu:.3f} timesteps/s", flush=True)
-    accuracy = None if a.no_accuracy else step_errors(dev, s, cctx, params, a.warmup, a.steps)
+    accuracy = None if a.no_accuracy else step_errors(dev, s, cctx, params, a.warmup, a.steps)[0]
     cctx.close()
     e_forms = float(np.linalg.norm(states_cu[-1] - states_ex[-1]) / np.linalg.norm(states_ex[-1] - s["x0"]))
     print(json.dumps({
@@ -747,7 +807,7 @@ def main():
     params = ms.solver_defaults(precision=prec, preconditioner=pc, forcing=1, pcg_eta_max=a.eta_max,
                                 pcg_eta_min=a.eta_min, coarse_every=a.coarse_every, coarse_move=a.coarse_move,
                                 mixed_endgame_fp64=a.endgame_fp64, endgame_ratio=a.endgame_ratio,
-                                integrator=1 if a.integrator == "bdf2" else 0)
+                                newton_tol=a.newton_tol, integrator=1 if a.integrator == "bdf2" else 0)
     value, elapsed, stats, states, ctx, basis_s = run(dev, s, params, a.warmup, a.steps,
                                                       handles=a.handles if pc != ms.PC_BLOCK_JACOBI else 0,
                                                       oversample=a.oversample, lattice=a.lattice)
@@ -770,7 +830,7 @@ def main():
     tparams = ms.solver_defaults(precision=prec, preconditioner=pc, forcing=1, pcg_eta_max=a.eta_max,
                                  pcg_eta_min=a.eta_min, coarse_every=a.coarse_every, coarse_move=a.coarse_move,
                                  mixed_endgame_fp64=a.endgame_fp64, endgame_ratio=a.endgame_ratio, time_kernels=1,
-                                 integrator=1 if a.integrator == "bdf2" else 0)
+                                 newton_tol=a.newton_tol, integrator=1 if a.integrator == "bdf2" else 0)
     tstat = ctx.ms_step(s["dt"], tparams)
     k_us, k_bytes = ctx.ms_time_kernel(0, kprec, 0)
     # slice height of the chosen layout, from the byte count of the product
@@ -783,8 +843,8 @@ def main():
     kernel_name = f"k_cg_spmv<{'double' if vb == 8 else 'float'}, {S}>"
     achieved = k_bytes / (k_us * 1e-6) / 1e9
     # the per-step check solves single steps from given states: implicit Euler only
-    accuracy = None if (a.no_accuracy or a.integrator == "bdf2") else step_errors(dev, s, ctx, params, a.warmup,
-                                                                                   a.steps)
+    accuracy, check = (None, None) if (a.no_accuracy or a.integrator == "bdf2") else \
+        step_errors(dev, s, ctx, params, a.warmup, a.steps)
     basis = ctx.ms_get_basis() if pc != ms.PC_BLOCK_JACOBI else None
     ctx.close()
 
@@ -833,7 +893,8 @@ def main():
                    "precision": a.precision, "preconditioner": a.pc,
                    "handles": a.handles if pc != ms.PC_BLOCK_JACOBI else None, "pcg_eta_max": a.eta_max,
                    "coarse_every": a.coarse_every, "coarse_move": a.coarse_move, "endgame_fp64": a.endgame_fp64,
-                   "endgame_ratio": a.endgame_ratio, "pcg_eta_min": a.eta_min, "integrator": a.integrator,
+                   "endgame_ratio": a.endgame_ratio, "pcg_eta_min": a.eta_min, "newton_tol": a.newton_tol,
+                   "integrator": a.integrator,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kernel_name, f"{a.scene}{a.grid}"),
@@ -856,7 +917,10 @@ def main():
         "accuracy": accuracy,
     }
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(a.scene, a.grid, len(s["tets"]))
+        if a.scene == "block" and check is not None:
+            out["cpu_baseline"], out["accuracy"]["oracle_check"] = cpu_baseline_on_workload(s, check)
+        else:
+            out["cpu_baseline"] = cpu_baseline(a.scene, a.grid, len(s["tets"]))
     print(json.dumps(out), flush=True)
 
 

@@ -511,10 +511,27 @@ double ms_mat_bytes(const ms_mat* A);
 void ms_mat_destroy(ms_mat* A);
 
 /* ---- batched scenes ------------------------------------------------------
- * Advance several independent contexts (same device and stream) by one
- * timestep each; the solver runs them as one block-diagonal system with
- * per-scene reductions, masks and line searches. per_scene may be NULL.
- * Results equal running ms_step on each context alone. */
+ * Many independent scenes advanced as one block-diagonal system with
+ * per-scene reductions, masks, line searches and convergence (the batched
+ * workload of uneven scenes; each scene's result equals ms_step on its own
+ * context).  Supported: plain implicit-Euler steps with block-Jacobi PCG,
+ * FP64 or mixed precision, no half-space contact.
+ *
+ * ms_batch_create: join the contexts scenes[n_scenes] (states set, one
+ * device, the same gravity, no context twice) into a batch *out; the union
+ * of their meshes is built here once.  The batch refers to the contexts,
+ * which must outlive it; their Dirichlet targets and states may change
+ * between steps, their meshes not.  Errors: MS_E_ARG, MS_E_ORDER (a scene
+ * without state), MS_E_NOMEM, MS_E_DEVICE.
+ * ms_batch_advance: one timestep of every scene of the batch (per_scene
+ * [n_scenes] may be NULL).  Errors: as ms_step, and MS_E_ORDER if a scene's
+ * mesh changed since ms_batch_create.
+ * ms_batch_step: the same step on a list of contexts in one call (the union
+ * is cached on the first context and rebuilt when the list changes). */
+typedef struct ms_batch ms_batch;
+ms_status ms_batch_create(ms_ctx* const* scenes, int32_t n_scenes, ms_batch** out);
+ms_status ms_batch_advance(ms_batch* b, double dt, const ms_solver_params* p, ms_step_stats* per_scene);
+void ms_batch_destroy(ms_batch* b);
 ms_status ms_batch_step(ms_ctx* const* scenes, int32_t n_scenes, double dt, const ms_solver_params* p,
                         ms_step_stats* per_scene);
 

@@ -20,9 +20,9 @@ Sec. 3.9):
      energy parts) the truncated step is taken as is.
   3b. Once ||d||_inf < 1e-6 L_bbox the exact (unprojected) Hessian is used,
      falling back to the projected one if it yields no descent direction.
-  4. Stop when a full step has ||d||_inf <= 1e-12 L_bbox, or when ||d||_inf
-     has not decreased for 3 iterations (round-off floor); at most 100
-     iterations.
+  4. Stop when a full step has ||d||_inf <= 1e-12 L_bbox, or when, in the
+     endgame (||d||_inf below 1e-6 L_bbox), ||d||_inf has not decreased for
+     3 iterations (the round-off floor); at most 100 iterations.
   5. v^{t+1} = (x^{t+1} - x^t) / h.
 A dense variant (numpy.linalg.solve) serves tiny meshes.
 
@@ -113,7 +113,9 @@ def newton_step(body: Body, x_t, v_t, h, gravity, dbc=None, dbc_target=None, hal
             break
         if dinf < best:
             best, stall = dinf, 0
-        else:
+        elif best < 1e-6 * L:
+            # stagnation counts only at the round-off floor of the endgame
+            # (far from the minimiser backtracking makes ||d|| non-monotone)
             stall += 1
             if stall >= 3:
                 break

