@@ -53,8 +53,17 @@ struct BatchPlan {
   double* d_sout = nullptr;       // [ns][8] their results
   int2* d_drange = nullptr;       // [ns] dot-partial range of each scene (blocks of 256 entries of 3n)
   int2* d_erange = nullptr;       // [ns] energy-partial range of each scene
-  hipGraphExec_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [precision][two-level]
   std::vector<double> h_sscal;
+  // two-level (additive) preconditioner: the union carries the transfer
+  // operators of the scenes' bases; each scene keeps its coarse matrix
+  bool tl_ready = false;
+  std::vector<int32_t> h0;        // first union handle of each scene
+  std::vector<int64_t> slot0;     // first union slot of each scene's slices
+  ms::GemvSeg* d_seg[2] = {nullptr, nullptr};  // GEMV blocks reading FP64 / FP32 inverses
+  int nseg = 0, rmax = 0;
+  std::vector<double> moved;      // per scene: movement since the last coarse rebuild
+  std::vector<const void*> tl_key;  // per scene: inverses and sizes the tables were built for
 };
 
 namespace ms {
@@ -336,8 +345,9 @@ __global__ void k_baxpy(int64_t n, const int32_t* __restrict__ ubscene, const do
 
 void free_plan(BatchPlan* B) {
   if (!B) return;
-  for (auto& g : B->graph)
-    if (g) (void)hipGraphExecDestroy(g);
+  for (auto& row : B->graph)
+    for (auto& g : row)
+      if (g) (void)hipGraphExecDestroy(g);
   if (B->u) ms_destroy(B->u);
   delete B;
 }
@@ -478,7 +488,128 @@ ms_status benergy(BatchPlan* B, const double* d, double h2, std::vector<double>&
   return sync(u);
 }
 
-void bcg_iteration(BatchPlan* B, int prec, int parity) {
+// Union basis for the two-level preconditioner: the scenes' bases side by
+// side (handles renumbered from each scene's first union handle), installed
+// as transfer operators only, and the block table of the block-diagonal
+// coarse GEMV.  Every scene needs an installed basis with the exact coarse
+// matrix and the same slice layout inside the union as in its own context.
+std::vector<const void*> two_level_key(const BatchPlan* B) {
+  std::vector<const void*> key;
+  for (ms_ctx* sc : B->scenes) {
+    key.push_back(sc->d_Ainv);
+    key.push_back(sc->d_Ainv32);
+    key.push_back(reinterpret_cast<const void*>(intptr_t(sc->r) << 32 | intptr_t(sc->rp)));
+  }
+  return key;
+}
+
+ms_status prepare_two_level(BatchPlan* B) {
+  if (B->tl_ready && two_level_key(B) == B->tl_key) return MS_OK;
+  // (re)build: a scene's basis was installed again since the tables were made
+  for (auto& row : B->graph)
+    if (row[1]) {
+      (void)hipGraphExecDestroy(row[1]);
+      row[1] = nullptr;
+    }
+  B->tl_ready = false;
+  ms_ctx* u = B->u;
+  ms_ctx* c0 = B->scenes[0];
+  const int ns = B->ns, S = u->pat.S;
+  Basis UB;
+  UB.vptr.assign(u->n + 1, 0);
+  B->h0.assign(ns, 0);
+  B->slot0.assign(ns, 0);
+  B->moved.assign(ns, 0.0);
+  int32_t m = 0;
+  for (int q = 0; q < ns; ++q) {
+    ms_ctx* sc = B->scenes[q];
+    if (!sc->has_basis) return fail(c0, MS_E_ORDER, "two-level batch: scene " + std::to_string(q) + " has no basis");
+    if (sc->coarse_mode != MS_COARSE_EXACT)
+      return fail(c0, MS_E_ARG, "two-level batch: scene " + std::to_string(q) + " integrates by cubature");
+    // the scene's slices are a contiguous run of the union's with the same widths
+    if (sc->pat.S != S) return fail(c0, MS_E_ARG, "two-level batch: scenes with another slice height");
+    const int64_t s0 = B->v0[q] / S;
+    const int64_t off = u->pat.h_slice_base[s0];
+    for (int64_t k = 0; k <= sc->pat.nslices; ++k)
+      if (u->pat.h_slice_base[s0 + k] - off != sc->pat.h_slice_base[k])
+        return fail(c0, MS_E_ARG, "two-level batch: scene " + std::to_string(q) + " has another slice layout");
+    B->slot0[q] = off;
+    B->h0[q] = m;
+    const Basis& D = sc->basis;
+    for (int i = 0; i < D.m; ++i)
+      for (int d = 0; d < 3; ++d) UB.origins.push_back(D.origins[3 * i + d]);
+    m += D.m;
+  }
+  UB.m = m;
+  for (int64_t v = 0, q = 0; v < u->n; ++v) {
+    while (q + 1 < ns && v >= B->v0[q + 1]) ++q;
+    const int64_t lv = v - B->v0[q];
+    ms_ctx* sc = B->scenes[q];
+    const Basis& D = sc->basis;
+    if (lv < sc->n)
+      for (int64_t k = D.vptr[lv]; k < D.vptr[lv + 1]; ++k) {
+        UB.vhandle.push_back(D.vhandle[k] + B->h0[q]);
+        UB.vphi.push_back(D.vphi[k]);
+      }
+    UB.vptr[v + 1] = int64_t(UB.vhandle.size());
+  }
+  ms_status st = install_transfer(u, UB);
+  if (st) return fail(c0, st, "two-level batch: " + u->err);
+  std::vector<GemvSeg> seg[2];
+  B->rmax = 0;
+  for (int q = 0; q < ns; ++q) {
+    ms_ctx* sc = B->scenes[q];
+    B->rmax = std::max(B->rmax, sc->r);
+    for (int row = 0; row < sc->r; row += kGemvRowsPerBlock)
+      for (int k = 0; k < 2; ++k) {
+        GemvSeg g{};
+        g.A = k == 0 ? static_cast<const void*>(sc->d_Ainv) : static_cast<const void*>(sc->d_Ainv32);
+        g.ld = sc->rp;
+        g.r = sc->r;
+        g.row0 = row;
+        g.h0 = B->h0[q];
+        g.scene = q;
+        seg[k].push_back(g);
+      }
+  }
+  B->nseg = int(seg[0].size());
+  for (int k = 0; k < 2; ++k)
+    if ((st = upload(u, &B->d_seg[k], seg[k].data(), seg[k].size()))) return fail(c0, st, "two-level batch: " + u->err);
+  B->tl_key = two_level_key(B);
+  B->tl_ready = true;
+  return MS_OK;
+}
+
+// u += U A_s^-1 U^T r for every scene (the additive coarse correction).
+void bcoarse_correction(BatchPlan* B, int prec) {
+  ms_ctx* u = B->u;
+  launch_restrict(u, u->d_r, nullptr, nullptr);
+  launch_coarse_gemv_seg(u, prec, B->d_seg[prec == MS_PREC_MIXED ? 1 : 0], B->nseg, B->rmax, B->d_sscal, kStride);
+  launch_prolong_add(u, u->d_u, nullptr);
+}
+
+// The coarse matrix of scene q from its segment of the union's Hessian, and
+// its inverse: the scene context's own Galerkin lists and factorisation,
+// run on the union's values and stream.
+ms_status scene_coarse_rebuild(BatchPlan* B, int q, int prec, double h2) {
+  ms_ctx* sc = B->scenes[q];
+  ms_ctx* u = B->u;
+  double* v64 = sc->d_vals;
+  float* v32 = sc->d_vals32;
+  hipStream_t st = sc->stream;
+  const int64_t off = 9 * B->slot0[q];
+  sc->d_vals = u->d_vals ? u->d_vals + off : nullptr;
+  sc->d_vals32 = u->d_vals32 ? u->d_vals32 + off : nullptr;
+  sc->stream = u->stream;
+  ms_status s = launch_galerkin(sc, prec, sc->d_x, h2);
+  if (!s) s = coarse_factor(sc);
+  sc->d_vals = v64;
+  sc->d_vals32 = v32;
+  sc->stream = st;
+  return s;
+}
+
+void bcg_iteration(BatchPlan* B, int prec, int parity, bool tl) {
   ms_ctx* u = B->u;
   const int64_t ns = u->pat.nslices;
   const double* st_in = B->d_sst + ST_N * B->ns * parity;
@@ -502,13 +633,14 @@ void bcg_iteration(BatchPlan* B, int prec, int parity) {
     k_bcg_update<float><<<unsigned(B->nub), 256, 0, u->stream>>>(u->n, B->d_ubscene, B->d_sinfo, u->d_part, st_in,
                                                                  st_out, u->d_p, u->d_s, u->d_d, u->d_r, u->d_u,
                                                                  u->d_w, u->d_Dinv32, B->d_sscal);
+  if (tl) bcoarse_correction(B, prec);
 }
 
 // PCG on every active scene at once; on return h_sscal holds each scene's
 // scalars (S_ITER, S_DONE: 1 converged, 2 iteration cap, 3 loss of positive
 // definiteness, 5 inactive).
 ms_status bpcg(BatchPlan* B, int prec, const ms_solver_params& P, const std::vector<uint8_t>& active,
-               const std::vector<uint8_t>& first) {
+               const std::vector<uint8_t>& first, bool tl) {
   ms_ctx* u = B->u;
   ms_ctx* const c = u;
   MS_HIP(hipMemcpyAsync(B->d_sactive, active.data(), active.size(), hipMemcpyHostToDevice, u->stream));
@@ -522,12 +654,13 @@ ms_status bpcg(BatchPlan* B, int prec, const ms_solver_params& P, const std::vec
   k_bcg_init_finish<<<unsigned(B->ns), 256, 0, u->stream>>>(B->d_sinfo, B->d_spart, B->d_sactive, B->d_sfirst,
                                                             P.pcg_eta_max, P.pcg_eta_min, P.forcing,
                                                             double(P.max_pcg), B->d_sst, B->d_sscal);
+  if (tl) bcoarse_correction(B, prec);  // u = S r + U A^-1 U^T r
   const int chunk = u->cg_chunk;
-  hipGraphExec_t& ge = B->graph[prec == MS_PREC_FP64 ? 0 : 1];
+  hipGraphExec_t& ge = B->graph[prec == MS_PREC_FP64 ? 0 : 1][tl ? 1 : 0];
   if (!ge && u->use_graphs) {
     hipGraph_t g;
     MS_HIP(hipStreamBeginCapture(u->stream, hipStreamCaptureModeThreadLocal));
-    for (int i = 0; i < chunk; ++i) bcg_iteration(B, prec, i & 1);
+    for (int i = 0; i < chunk; ++i) bcg_iteration(B, prec, i & 1, tl);
     MS_HIP(hipStreamEndCapture(u->stream, &g));
     MS_HIP(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
     (void)hipGraphDestroy(g);
@@ -537,7 +670,7 @@ ms_status bpcg(BatchPlan* B, int prec, const ms_solver_params& P, const std::vec
     if (u->use_graphs) {
       MS_HIP(hipGraphLaunch(ge, u->stream));
     } else {
-      for (int i = 0; i < chunk; ++i) bcg_iteration(B, prec, i & 1);
+      for (int i = 0; i < chunk; ++i) bcg_iteration(B, prec, i & 1, tl);
     }
     launched += chunk;
     MS_HIP(hipMemcpyAsync(B->h_sscal.data(), B->d_sscal, sizeof(double) * B->h_sscal.size(), hipMemcpyDeviceToHost,
@@ -559,6 +692,7 @@ ms_status batch_step(BatchPlan* B, double dt, const ms_solver_params& P, ms_step
   const double h2 = dt * dt;
   const int prec = P.precision == MS_PREC_MIXED ? MS_PREC_MIXED : MS_PREC_FP64;
   const int64_t n3 = 3 * u->n;
+  const bool tl = P.preconditioner == MS_PC_TWO_LEVEL_ADDITIVE;
   std::vector<ms_step_stats> S(ns);
   for (auto& st : S) st.min_alpha = 1.0;
   std::vector<uint8_t> active(ns, 1), first(ns, 1), proj(ns, 1), endgame(ns, 0), done(ns, 0);
@@ -593,7 +727,25 @@ ms_status batch_step(BatchPlan* B, double dt, const ms_solver_params& P, ms_step
     launch_gather_hess(u, u->d_x, h2, prec);
     launch_block_jacobi(u, prec);
     u->assembled[prec == MS_PREC_FP64 ? 0 : 1] = true;
-    if ((s = bpcg(B, prec, P, active, first))) break;
+    if (tl) {
+      // each scene's coarse operator, on the rule of its unbatched step:
+      // at the first iteration, then after it has moved coarse_move x its
+      // displacement (or every coarse_every iterations)
+      for (int q = 0; q < ns && !s; ++q) {
+        if (!active[q]) continue;
+        bool refresh = it == 0;
+        if (P.coarse_move > 0.0)
+          refresh = refresh || B->moved[q] > P.coarse_move * std::max(disp[q], P.abs_floor);
+        else
+          refresh = refresh || (P.coarse_every > 0 && it % P.coarse_every == 0);
+        if (!refresh) continue;
+        B->moved[q] = 0.0;
+        ++S[q].hessian_refreshes;
+        s = scene_coarse_rebuild(B, q, prec, h2);
+      }
+      if (s) break;
+    }
+    if ((s = bpcg(B, prec, P, active, first, tl))) break;
     std::vector<uint8_t> step(ns, 0);
     for (int q = 0; q < ns; ++q) {
       if (!active[q]) continue;
@@ -676,6 +828,7 @@ ms_status batch_step(BatchPlan* B, double dt, const ms_solver_params& P, ms_step
       if (!step[q]) continue;
       S[q].backtracks += nbt[q];
       S[q].min_alpha = std::min(S[q].min_alpha, alpha[q]);
+      if (tl) B->moved[q] += alpha[q] * dnorm[q];
       disp[q] = std::sqrt(h[8 * q + 2]);
       const double ref = std::max(disp[q], P.abs_floor);
       if (alpha[q] == 1.0 && (dnorm[q] <= P.newton_tol * ref || dnorm[q] <= xres[q])) {
@@ -722,8 +875,12 @@ ms_status batch_params(ms_ctx* c0, double dt, const ms_solver_params* pin, ms_so
     P = *pin;
   else
     ms_solver_defaults(&P);
-  if (P.mode != MS_MODE_PLAIN || P.preconditioner != MS_PC_BLOCK_JACOBI || P.warm_start || P.integrator != 0)
-    return fail(c0, MS_E_ARG, "batched steps support plain implicit-Euler mode with block-Jacobi PCG");
+  if (P.mode != MS_MODE_PLAIN || P.warm_start || P.integrator != 0 ||
+      (P.preconditioner != MS_PC_BLOCK_JACOBI && P.preconditioner != MS_PC_TWO_LEVEL_ADDITIVE))
+    return fail(c0, MS_E_ARG,
+                "batched steps support plain implicit-Euler mode with block-Jacobi or additive two-level PCG");
+  if (P.precision == MS_PREC_MIXED && P.mixed_endgame_fp64)
+    return fail(c0, MS_E_ARG, "batched steps keep one Hessian precision per step (no FP64 endgame)");
   return MS_OK;
 }
 
@@ -777,6 +934,10 @@ ms_status batch_run(ms_ctx* const* scenes, int n_scenes, BatchPlan* B, double dt
   }
   u->stage = 3;
   for (int q = 0; q < n_scenes; ++q) scenes[q]->has_prev = false;  // no BDF2 history across batched steps
+  if (P.preconditioner == MS_PC_TWO_LEVEL_ADDITIVE) {
+    if ((s = prepare_two_level(B))) return s;
+    for (int q = 0; q < n_scenes; ++q) set_coarse_f32(scenes[q], P.precision == MS_PREC_MIXED);
+  }
   s = batch_step(B, dt, P, per_scene);
   if (s) return fail(c0, s, "batch: " + u->err);
   for (int q = 0; q < n_scenes; ++q) {

@@ -110,11 +110,52 @@ __global__ void __launch_bounds__(kRThreads) k_restrict(const int4* __restrict__
 // pieces of each lane's share of the row are loaded before the flag test
 // and the formation of c, so their latency overlaps both.
 constexpr int kGemvRows = 16;
+static_assert(kGemvRows == kGemvRowsPerBlock, "the batched GEMV tables assume this row count");
 constexpr int kGemvPre = 10;
 // direct != 0: every handle's restriction is a single chunk and chunk i is
 // handle i, so the partials are the coarse right-hand side itself; they are
 // then loaded together with the matrix rows, before the flag test.
 constexpr int kGemvPart = 3;  // direct loads per thread (r <= 3 * 64 * kGemvRows)
+template <typename AT>
+using V16T = typename std::conditional<sizeof(AT) == 4, float4, double2>::type;
+
+// The first kGemvPre 16-byte pieces of this lane's share of row a.
+template <typename AT>
+__device__ __forceinline__ void gemv_preload(const AT* __restrict__ a, int ld, int lane, V16T<AT> (&pre)[kGemvPre]) {
+  constexpr int VW = 16 / sizeof(AT);  // elements per 16-byte load
+  constexpr int STRIDE = 64 * VW;
+#pragma unroll
+  for (int p = 0; p < kGemvPre; ++p) {
+    const int j = VW * lane + STRIDE * p;
+    pre[p] = j < ld ? *reinterpret_cast<const V16T<AT>*>(a + j) : V16T<AT>{};
+  }
+}
+
+// sum_j a_j c_j over the r columns of one row, by one wave: the preloaded
+// pieces first, then the rest of the lane's share, then a fixed-order wave
+// reduction.
+template <typename AT>
+__device__ __forceinline__ double gemv_row(const AT* __restrict__ a, int r, int lane,
+                                           const V16T<AT> (&pre)[kGemvPre], const double* sc) {
+  constexpr int VW = 16 / sizeof(AT);
+  constexpr int STRIDE = 64 * VW;
+  double s = 0.0;
+#pragma unroll
+  for (int p = 0; p < kGemvPre; ++p) {
+    const int j = VW * lane + STRIDE * p;
+    const AT* pv = reinterpret_cast<const AT*>(&pre[p]);
+#pragma unroll
+    for (int q = 0; q < VW; ++q)
+      if (j + q < r) s += double(pv[q]) * sc[j + q];
+  }
+  for (int j = VW * lane + STRIDE * kGemvPre; j < r; j += STRIDE) {
+#pragma unroll
+    for (int q = 0; q < VW; ++q)
+      if (j + q < r) s += double(a[j + q]) * sc[j + q];
+  }
+  return wave_sum(s);
+}
+
 template <typename AT>
 __global__ void __launch_bounds__(64 * kGemvRows) k_coarse_gemv(int r, int ld, const AT* __restrict__ A,
                                                       const int2* __restrict__ hinfo,
@@ -125,9 +166,6 @@ __global__ void __launch_bounds__(64 * kGemvRows) k_coarse_gemv(int r, int ld, c
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
   const int row = blockIdx.x * kGemvRows + wave;
   const AT* a = A + int64_t(row < r ? row : 0) * ld;
-  constexpr int VW = 16 / sizeof(AT);  // elements per 16-byte load
-  constexpr int STRIDE = 64 * VW;
-  using V16 = typename std::conditional<sizeof(AT) == 4, float4, double2>::type;
   double pc[kGemvPart];
   if (direct) {
 #pragma unroll
@@ -136,12 +174,8 @@ __global__ void __launch_bounds__(64 * kGemvRows) k_coarse_gemv(int r, int ld, c
       pc[u] = idx < r ? part[idx] : 0.0;
     }
   }
-  V16 pre[kGemvPre];
-#pragma unroll
-  for (int p = 0; p < kGemvPre; ++p) {
-    const int j = VW * lane + STRIDE * p;
-    pre[p] = j < ld ? *reinterpret_cast<const V16*>(a + j) : V16{};
-  }
+  V16T<AT> pre[kGemvPre];
+  gemv_preload<AT>(a, ld, lane, pre);
   if (done != 0.0) return;  // the flag is the same for the whole grid
   if (direct) {
 #pragma unroll
@@ -160,22 +194,59 @@ __global__ void __launch_bounds__(64 * kGemvRows) k_coarse_gemv(int r, int ld, c
   }
   __syncthreads();
   if (row >= r) return;
-  double s = 0.0;
-#pragma unroll
-  for (int p = 0; p < kGemvPre; ++p) {
-    const int j = VW * lane + STRIDE * p;
-    const AT* pv = reinterpret_cast<const AT*>(&pre[p]);
-#pragma unroll
-    for (int q = 0; q < VW; ++q)
-      if (j + q < r) s += double(pv[q]) * sc[j + q];
-  }
-  for (int j = VW * lane + STRIDE * kGemvPre; j < r; j += STRIDE) {
-#pragma unroll
-    for (int q = 0; q < VW; ++q)
-      if (j + q < r) s += double(a[j + q]) * sc[j + q];
-  }
-  s = wave_sum(s);
+  const double s = gemv_row<AT>(a, r, lane, pre, sc);
   if (lane == 0) e[row] = s;
+}
+
+// Block-diagonal e = A c over several scenes (the batched two-level
+// preconditioner): block b serves kGemvRows rows of one scene, whose inverse
+// (leading dimension ld, coarse size r) and handles (from union handle h0)
+// its descriptor gives; c comes from the union's restriction partials.  The
+// row arithmetic is k_coarse_gemv's, so every scene gets the values of its
+// own unbatched preconditioner.
+template <typename AT>
+__global__ void __launch_bounds__(64 * kGemvRows) k_coarse_gemv_seg(const GemvSeg* __restrict__ seg,
+                                                          const int2* __restrict__ hinfo,
+                                                          const double* __restrict__ part, double* __restrict__ e,
+                                                          const double* __restrict__ sscal, int sstride, int direct) {
+  extern __shared__ double sc[];
+  const GemvSeg g = seg[blockIdx.x];
+  const double done = sscal ? sscal[int64_t(sstride) * g.scene + S_DONE] : 0.0;
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  const int row = g.row0 + wave;
+  const AT* A = static_cast<const AT*>(g.A);
+  const AT* a = A + int64_t(row < g.r ? row : 0) * g.ld;
+  V16T<AT> pre[kGemvPre];
+  gemv_preload<AT>(a, g.ld, lane, pre);
+  if (done != 0.0) return;  // the flag is the same for every block of the scene
+  for (int idx = t; idx < g.r; idx += blockDim.x) {
+    if (direct) {
+      sc[idx] = part[12 * int64_t(g.h0) + idx];  // union chunk i is union handle i
+    } else {
+      const int2 hi = hinfo[g.h0 + idx / 12];
+      const int q = idx % 12;
+      double s = 0.0;
+      for (int k = 0; k < hi.y; ++k) s += part[12 * int64_t(hi.x + k) + q];
+      sc[idx] = s;
+    }
+  }
+  __syncthreads();
+  if (row >= g.r) return;
+  const double s = gemv_row<AT>(a, g.r, lane, pre, sc);
+  if (lane == 0) e[12 * int64_t(g.h0) + row] = s;
+}
+
+void launch_coarse_gemv_seg(ms_ctx* u, int prec, const GemvSeg* seg, int nblocks_seg, int rmax, const double* sscal,
+                            int sstride) {
+  Basis& D = u->basis;
+  const int direct = D.nrchunks == D.m ? 1 : 0;
+  const size_t lds = size_t(rmax) * sizeof(double);
+  if (prec == MS_PREC_MIXED)
+    k_coarse_gemv_seg<float><<<unsigned(nblocks_seg), 64 * kGemvRows, lds, u->stream>>>(seg, D.d_hinfo, D.d_rpart,
+                                                                                       u->d_e, sscal, sstride, direct);
+  else
+    k_coarse_gemv_seg<double><<<unsigned(nblocks_seg), 64 * kGemvRows, lds, u->stream>>>(seg, D.d_hinfo, D.d_rpart,
+                                                                                        u->d_e, sscal, sstride, direct);
 }
 
 // e = A c for a dense row-major r x r matrix (leading dimension ld), one
@@ -418,6 +489,85 @@ __global__ void __launch_bounds__(256) k_cub_z(int64_t nz, const int4* __restric
 // ---------------------------------------------------------------------------
 static inline unsigned nblocks(int64_t n, int b) { return unsigned((n + b - 1) / b); }
 
+// Transfer operators of a basis: per-vertex weights W = phi [1, x - o]
+// (prolongation), the transpose in handle order (vertices ascending) and the
+// restriction chunks (handle i's entries in runs of at most kRChunk).
+struct TransferLists {
+  std::vector<int32_t> vptr, hptr, hv, hk;
+  std::vector<double> vw, hw;
+  std::vector<int4> chunk_info;
+  std::vector<int2> hinfo;
+};
+
+static void transfer_lists(const ms_ctx* c, const Basis& B, TransferLists& T) {
+  const int64_t n = c->n, nnz = B.vptr[n];
+  const int m = B.m;
+  T.vptr.assign(n + 1, 0);
+  for (int64_t v = 0; v <= n; ++v) T.vptr[v] = int32_t(B.vptr[v]);
+  T.vw.assign(4 * nnz, 0.0);
+  for (int64_t v = 0; v < n; ++v)
+    for (int64_t k = B.vptr[v]; k < B.vptr[v + 1]; ++k) {
+      const int i = B.vhandle[k];
+      T.vw[4 * k] = B.vphi[k];
+      for (int d = 0; d < 3; ++d) T.vw[4 * k + 1 + d] = B.vphi[k] * (c->h_rest[3 * v + d] - B.origins[3 * i + d]);
+    }
+  T.hptr.assign(m + 1, 0);
+  T.hv.assign(nnz, 0);
+  T.hk.assign(nnz, 0);
+  for (int64_t k = 0; k < nnz; ++k) T.hptr[B.vhandle[k] + 1]++;
+  for (int i = 0; i < m; ++i) T.hptr[i + 1] += T.hptr[i];
+  {
+    std::vector<int32_t> fill(T.hptr.begin(), T.hptr.end() - 1);
+    for (int64_t v = 0; v < n; ++v)
+      for (int64_t k = B.vptr[v]; k < B.vptr[v + 1]; ++k) {
+        const int32_t pos = fill[B.vhandle[k]]++;
+        T.hv[pos] = int32_t(v);
+        T.hk[pos] = int32_t(k);
+      }
+  }
+  T.hw.assign(4 * size_t(std::max<int64_t>(nnz, 1)), 0.0);
+  for (int64_t e = 0; e < nnz; ++e)
+    for (int l = 0; l < 4; ++l) T.hw[4 * e + l] = T.vw[4 * size_t(T.hk[e]) + l];
+  T.chunk_info.clear();
+  T.hinfo.assign(m, make_int2(0, 0));
+  for (int i = 0; i < m; ++i) {
+    const int nchk = std::max(1, (T.hptr[i + 1] - T.hptr[i] + kRChunk - 1) / kRChunk);
+    T.hinfo[i] = make_int2(int(T.chunk_info.size()), nchk);
+    for (int q = 0; q < nchk; ++q) {
+      const int e0 = T.hptr[i] + q * kRChunk;
+      T.chunk_info.push_back(make_int4(i, e0, std::min(T.hptr[i + 1], e0 + kRChunk), 0));
+    }
+  }
+}
+
+// Installs only the transfer operators of B on c (prolongation rows,
+// restriction chunks, coarse vector): the batched two-level preconditioner
+// uses them on the union of the scenes' meshes while every scene keeps its
+// own coarse matrix and inverse.  has_basis stays false on c.
+ms_status install_transfer(ms_ctx* c, const Basis& B) {
+  const int64_t n = c->n;
+  if (B.m < 1 || int64_t(B.vptr.size()) != n + 1 || B.vptr[0] != 0 || B.vptr[n] < 1)
+    return fail(c, MS_E_ARG, "bad transfer basis");
+  TransferLists T;
+  transfer_lists(c, B, T);
+  Basis& D = c->basis;
+  const int64_t nnz = B.vptr[n];
+  const int32_t nrchunks = int32_t(T.chunk_info.size());
+  ms_status s;
+  if ((s = upload(c, &D.d_vptr, T.vptr.data(), T.vptr.size())) || (s = upload(c, &D.d_vh, B.vhandle.data(), nnz)) ||
+      (s = upload(c, &D.d_vw, T.vw.data(), T.vw.size())) || (s = upload(c, &D.d_hv, T.hv.data(), nnz)) ||
+      (s = upload(c, &D.d_hw, T.hw.data(), T.hw.size())) ||
+      (s = upload(c, &D.d_chunk_info, T.chunk_info.data(), T.chunk_info.size())) ||
+      (s = alloc_n(c, &D.d_rpart, 12 * size_t(nrchunks))) || (s = upload(c, &D.d_hinfo, T.hinfo.data(), T.hinfo.size())) ||
+      (s = alloc_n(c, &c->d_e, 12 * size_t(B.m))))
+    return s;
+  D.nrchunks = nrchunks;
+  D.m = B.m;
+  D.nnz = nnz;
+  c->r = 12 * B.m;
+  return sync(c);
+}
+
 ms_status install_basis(ms_ctx* c, Basis&& B) {
   const int64_t n = c->n;
   const int m = B.m;
@@ -430,43 +580,16 @@ ms_status install_basis(ms_ctx* c, Basis&& B) {
   for (int64_t k = 0; k < nnz; ++k)
     if (B.vhandle[k] < 0 || B.vhandle[k] >= m || !std::isfinite(B.vphi[k]))
       return fail(c, MS_E_ARG, "bad basis entry");
-  // per-vertex weights W = phi [1, x - o]
-  std::vector<int32_t> vptr(n + 1);
-  for (int64_t v = 0; v <= n; ++v) vptr[v] = int32_t(B.vptr[v]);
-  std::vector<double> vw(4 * nnz);
-  for (int64_t v = 0; v < n; ++v)
-    for (int64_t k = B.vptr[v]; k < B.vptr[v + 1]; ++k) {
-      const int i = B.vhandle[k];
-      vw[4 * k] = B.vphi[k];
-      for (int d = 0; d < 3; ++d) vw[4 * k + 1 + d] = B.vphi[k] * (c->h_rest[3 * v + d] - B.origins[3 * i + d]);
-    }
-  // transpose (per handle, vertices ascending)
-  std::vector<int32_t> hptr(m + 1, 0), hv(nnz), hk(nnz);
-  for (int64_t k = 0; k < nnz; ++k) hptr[B.vhandle[k] + 1]++;
-  for (int i = 0; i < m; ++i) hptr[i + 1] += hptr[i];
-  {
-    std::vector<int32_t> fill(hptr.begin(), hptr.end() - 1);
-    for (int64_t v = 0; v < n; ++v)
-      for (int64_t k = B.vptr[v]; k < B.vptr[v + 1]; ++k) {
-        const int32_t pos = fill[B.vhandle[k]]++;
-        hv[pos] = int32_t(v);
-        hk[pos] = int32_t(k);
-      }
-  }
-  // restriction chunks: handle i's entries split into runs of kRChunk
-  std::vector<double> hw(4 * size_t(std::max<int64_t>(nnz, 1)));
-  for (int64_t e = 0; e < nnz; ++e)
-    for (int l = 0; l < 4; ++l) hw[4 * e + l] = vw[4 * size_t(hk[e]) + l];
-  std::vector<int4> chunk_info;
-  std::vector<int2> hinfo(m);
-  for (int i = 0; i < m; ++i) {
-    const int nchk = std::max(1, (hptr[i + 1] - hptr[i] + kRChunk - 1) / kRChunk);
-    hinfo[i] = make_int2(int(chunk_info.size()), nchk);
-    for (int q = 0; q < nchk; ++q) {
-      const int e0 = hptr[i] + q * kRChunk;
-      chunk_info.push_back(make_int4(i, e0, std::min(hptr[i + 1], e0 + kRChunk), 0));
-    }
-  }
+  TransferLists T;
+  transfer_lists(c, B, T);
+  std::vector<int32_t>& vptr = T.vptr;
+  std::vector<double>& vw = T.vw;
+  std::vector<int32_t>& hptr = T.hptr;
+  std::vector<int32_t>& hv = T.hv;
+  std::vector<int32_t>& hk = T.hk;
+  std::vector<double>& hw = T.hw;
+  std::vector<int4>& chunk_info = T.chunk_info;
+  std::vector<int2>& hinfo = T.hinfo;
   const int32_t nrchunks = int32_t(chunk_info.size());
   // Galerkin stage-1 lists: for each vertex v the handles reachable through
   // its Hessian row, h'(v) = union of h(w) for w in N(v)

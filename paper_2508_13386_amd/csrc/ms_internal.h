@@ -62,6 +62,17 @@ struct Cubature {
   int32_t* d_pair_ent = nullptr; // [L2][2] (k_v, z)
 };
 
+// One block of the block-diagonal coarse GEMV of a batch: kGemvRows rows of
+// one scene's coarse inverse.
+struct GemvSeg {
+  const void* A;  // the scene's inverse (float in mixed precision, else double)
+  int ld, r;      // its leading dimension and coarse size
+  int row0;       // first scene row of the block
+  int h0;         // first union handle of the scene
+  int scene;
+  int pad[2];
+};
+
 struct CubatureParams {
   double tol;
   int32_t n_init, n_add, max_rounds;
@@ -292,6 +303,10 @@ double time_spmv_layout(ms_ctx* c, int S, const int32_t* d_slice_base, const int
                         int64_t nslots, int reps);
 ms_status build_basis_host(ms_ctx* c, const ms_basis_params& P, Basis& B);
 ms_status install_basis(ms_ctx* c, Basis&& B);
+ms_status install_transfer(ms_ctx* c, const Basis& B);
+void launch_coarse_gemv_seg(ms_ctx* u, int prec, const GemvSeg* seg, int nblocks_seg, int rmax, const double* sscal,
+                            int sstride);
+constexpr int kGemvRowsPerBlock = 16;  // rows per block of the coarse GEMV kernels
 ms_status coarse_coordinates(ms_ctx* c, const double* x_dev, double* q_host, double* q_dev);
 
 // kernel launchers (kernels_*.hip) -------------------------------------------

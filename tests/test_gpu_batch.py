@@ -57,6 +57,49 @@ def test_batch_equals_unbatched(dev, prec_name, forcing):
         c.close()
 
 
+@pytest.mark.parametrize("prec_name,coarse_move", [("fp64", 0.2), ("mixed", 0.2), ("mixed", 0.0)])
+def test_batch_two_level_equals_unbatched(dev, prec_name, coarse_move):
+    """The additive two-level preconditioner in a batch: each scene keeps its
+    own basis, coarse matrix and inverse (formed from its segment of the
+    union's Hessian, on its own rebuild rule), the union carries the
+    scenes' transfer operators, and a block-diagonal GEMV applies the
+    inverses.  Every scene equals its own ms_step bitwise (states, PCG and
+    Newton counts, coarse rebuilds) and reaches the oracle's minimiser."""
+    from paper_2508_13386_amd import ms
+    prec = ms.PREC_MIXED if prec_name == "mixed" else ms.PREC_FP64
+    scs = scenes.batch_scenes(4, seed=5, t_lo=500, t_hi=4000)
+    say("two-level batch sizes", [len(s["tets"]) for s in scs], prec_name, "coarse_move", coarse_move)
+    ref = _contexts(dev, scs)
+    bat = _contexts(dev, scs)
+    for c in ref + bat:
+        c.ms_build_basis(n_handles=6, seed=2)
+    params = ms.solver_defaults(precision=prec, preconditioner=ms.PC_TWO_LEVEL_ADDITIVE, forcing=1,
+                                pcg_eta_max=0.1, pcg_eta_min=1e-4, coarse_move=coarse_move)
+    dt = scs[0]["dt"]
+    bodies = [fem.Body(s["rest"], s["tets"], s["E"], s["nu"], s["rho"]) for s in scs]
+    for step in range(1, 3):
+        starts = [c.ms_get_state() for c in bat]
+        st_ref = [c.ms_step(dt, params) for c in ref]
+        st_bat = ms.ms_batch_step(bat, dt, params)
+        for q in range(len(scs)):
+            xr, vr = ref[q].ms_get_state()
+            xb, vb = bat[q].ms_get_state()
+            x0, v0 = starts[q]
+            sc = scs[q]
+            xo, _, _ = newton.newton_step(bodies[q], x0, v0, dt, sc["gravity"], sc["dirichlet"],
+                                          sc["dbc_targets"](step))
+            err = e_rel(xb, xo, x0)
+            say("step", step, "scene", q, "newton", st_ref[q]["newton_iters"], st_bat[q]["newton_iters"], "pcg",
+                st_ref[q]["pcg_iters"], st_bat[q]["pcg_iters"], "rebuilds", st_ref[q]["hessian_refreshes"],
+                st_bat[q]["hessian_refreshes"], "max |dx|", float(np.abs(xr - xb).max()), "oracle e_rel", err)
+            assert st_ref[q]["pcg_iters"] == st_bat[q]["pcg_iters"]
+            assert st_ref[q]["hessian_refreshes"] == st_bat[q]["hessian_refreshes"]
+            assert np.array_equal(xr, xb) and np.array_equal(vr, vb)
+            assert err <= 1e-6
+    for c in ref + bat:
+        c.close()
+
+
 def test_created_batch_equals_unbatched(dev):
     """ms_batch_create / ms_batch_advance: the union built once, stepped
     three times, equals each context's own ms_step bitwise; a context whose
