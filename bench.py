@@ -333,9 +333,14 @@ def step_errors(dev, s, ctx, params, warmup, steps):
 
 def batch_main(a):
     """64 uneven scenes (cubes / ellipsoids, 1e3-5e4 tets each, E log-uniform
-    in [1e5, 1e9], bottom layer pinned, gravity) advanced by ms_batch_step;
-    the same scenes stepped one after another by ms_step are the reference
-    form (identical results)."""
+    in [1e5, 1e9], bottom layer pinned, gravity) advanced by ms_batch_create /
+    ms_batch_advance with the additive two-level preconditioner (a basis per
+    scene, about one handle per 1,500 tets, at least four; basis builds are
+    excluded from the timing) or block-Jacobi (--pc jacobi).  Reference
+    forms: the same scenes stepped one after another by ms_step with the
+    same preconditioner (bitwise the same states), and the batch with
+    block-Jacobi.  Accuracy: the last step of every 16th scene against the
+    oracle's minimiser from the same start state."""
     import torch
 
     import scenes
@@ -343,32 +348,82 @@ def batch_main(a):
     scs = scenes.batch_scenes(64, seed=0)
     dev = ms.TorchDevice(0)
     prec = ms.PREC_MIXED if a.precision == "mixed" else ms.PREC_FP64
-    params = ms.solver_defaults(precision=prec, forcing=1, pcg_eta_max=a.eta_max)
+    two_level = a.pc != "jacobi"
+    jac = ms.solver_defaults(precision=prec, forcing=1, pcg_eta_max=a.eta_max, pcg_eta_min=a.eta_min)
+    tl = ms.solver_defaults(precision=prec, forcing=1, pcg_eta_max=a.eta_max, pcg_eta_min=a.eta_min,
+                            preconditioner=ms.PC_TWO_LEVEL_ADDITIVE, coarse_move=a.coarse_move)
+    params = tl if two_level else jac
     dt = scs[0]["dt"]
+    handles = [max(4, int(round(len(s["tets"]) / 1500))) for s in scs]
 
-    def timed(step_all):
+    def contexts(with_basis):
         ctxs = [ms.context_from_scene(dev, s) for s in scs]
+        t0 = time.perf_counter()
+        if with_basis:
+            for c, m in zip(ctxs, handles):
+                c.ms_build_basis(n_handles=m, seed=1)
+        return ctxs, time.perf_counter() - t0
+
+    def timed(step_all, with_basis, keep_last=False):
+        ctxs, basis_s = contexts(with_basis)
         for _ in range(a.warmup):
             step_all(ctxs)
         dev.stream.synchronize()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        stats = [step_all(ctxs) for _ in range(a.steps)]
+        stats = []
+        starts = None
+        for k in range(a.steps):
+            if keep_last and k == a.steps - 1:
+                starts = [c.ms_get_state() for c in ctxs]
+            stats.append(step_all(ctxs))
         dev.stream.synchronize()
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         xs = [c.ms_get_state()[0] for c in ctxs]
-        for c in ctxs:
-            c.close()
-        return a.steps / el, el, stats, xs
+        return a.steps / el, el, stats, xs, starts, basis_s, ctxs
 
-    value, elapsed, stats, xb = timed(lambda cs: ms.ms_batch_step(cs, dt, params))
+    def batched(ctxs, p, holder={}):
+        if "b" not in holder or holder["ctxs"] is not ctxs:
+            holder["b"], holder["ctxs"] = ms.Batch(ctxs), ctxs
+        return holder["b"].advance(dt, p)
+
+    value, elapsed, stats, xb, starts, basis_s, bctxs = timed(lambda cs: batched(cs, params), two_level,
+                                                              keep_last=True)
+    accuracy = None
+    if not a.no_accuracy:
+        from oracle import fem, newton
+        errs = {}
+        for q in range(0, len(scs), 16):
+            s = scs[q]
+            x0, v0 = starts[q]
+            body = fem.Body(s["rest"], s["tets"], s["E"], s["nu"], s["rho"])
+            xo, _, _ = newton.newton_step(body, x0, v0, dt, s["gravity"], s["dirichlet"],
+                                          s["dbc_targets"](a.warmup + a.steps), x_start=xb[q])
+            err, disp, xn = (float(np.linalg.norm(xb[q] - xo)), float(np.linalg.norm(xo - x0)),
+                             float(np.linalg.norm(xo)))
+            errs[q] = {"e_rel": err / disp, "disp_m": disp, "abs_err_m": err, "abs_err_over_x": err / xn,
+                       "ok": bool(err <= 1e-6 * disp or err <= 1e-12 * xn)}
+        accuracy = {"check": "last timed step of every 16th scene against the oracle's minimiser (FP64 Newton + "
+                             "SuperLU) from the same start state; a step passes with e_rel <= 1e-6 or, for an "
+                             "almost static step, an error below 1e-12 ||x|| (the resolution of FP64 positions)",
+                    "per_scene": errs, "all_ok": bool(all(v["ok"] for v in errs.values()))}
+    for c in bctxs:
+        c.close()
     ref = None
     if not a.no_reference:
-        rv, _, _, xr = timed(lambda cs: [c.ms_step(dt, params) for c in cs])
-        ref = {"form": "the same 64 scenes stepped one after another (ms_step)", "value": rv,
+        rv, _, rstats, xr, _, _, rctxs = timed(lambda cs: [c.ms_step(dt, params) for c in cs], two_level)
+        for c in rctxs:
+            c.close()
+        ref = {"form": "the same 64 scenes stepped one after another (ms_step), same preconditioner", "value": rv,
                "unit": "batch timesteps/s", "speedup": value / rv,
                "bitwise_equal_states": bool(all(np.array_equal(p, q) for p, q in zip(xb, xr)))}
+        if two_level:
+            jv, _, jstats, _, _, _, jctxs = timed(lambda cs: batched(cs, jac), False)
+            for c in jctxs:
+                c.close()
+            ref["batched_block_jacobi"] = {"value": jv, "speedup_of_two_level": value / jv,
+                                           "max_pcg_iters": [max(st["pcg_iters"] for st in step) for step in jstats]}
     out = {
         "metric": "batched Newton-PCG timesteps/s (all 64 scenes per step)",
         "value": value, "unit": "batch timesteps/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
@@ -376,9 +431,11 @@ def batch_main(a):
         "vs_baseline": None, "dtype": "f64" if a.precision == "fp64" else "f32+f64", "data": "synthetic",
         "config": {"workload": "64 uneven scenes, seed 0", "n_tets": int(sum(len(s["tets"]) for s in scs)),
                    "n_verts": int(sum(len(s["rest"]) for s in scs)), "precision": a.precision,
-                   "preconditioner": "jacobi", "parallelism": "single GPU"},
+                   "preconditioner": "additive two-level" if two_level else "jacobi",
+                   "handles_total": int(sum(handles)) if two_level else None, "parallelism": "single GPU"},
         "solver": {"max_newton_iters": [max(st["newton_iters"] for st in step) for step in stats],
-                   "max_pcg_iters": [max(st["pcg_iters"] for st in step) for step in stats]},
+                   "max_pcg_iters": [max(st["pcg_iters"] for st in step) for step in stats],
+                   "basis_build_s": basis_s},
         "reference_form": ref,
         "accuracy": accuracy,
     }
