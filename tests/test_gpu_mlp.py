@@ -84,15 +84,17 @@ def test_mlp_first_gradients_match_oracle(dev):
         say("grad", k, "max err / scale", float(err.max()), "bound", 10 * 2.0 ** -8)
         assert err.max() <= 10 * 2.0 ** -8
         # Adam's first step (bias-corrected m = g, v = g^2) moves each weight
-        # by -lr g / (|g| + 1e-8), about -lr sign(g); checked wherever the GPU
-        # gradient's sign is the oracle's (its error is below half the
-        # gradient), up to float32 rounding of the weights
+        # by -lr g / (|g| + 1e-8) with the gradient it computed (checked
+        # above): about -lr sign(g), in the oracle's direction wherever the
+        # GPU gradient's sign is the oracle's; up to float32 rounding
         sure = (np.abs(go[k]) > 2 * np.abs(g[k] - go[k])) & (np.abs(go[k]) > 1e-6)
         say("   adam first step checked on", int(sure.sum()), "of", sure.size)
         if sure.any():
             step = (p1[k] - p[k])[sure].astype(np.float64)
-            expect = -lr * go[k][sure] / (np.abs(go[k][sure]) + 1e-8)
-            tol = 1e-4 * lr + 4 * np.finfo(np.float32).eps * np.abs(p[k][sure])
+            gk = g[k][sure].astype(np.float64)
+            expect = -lr * gk / (np.abs(gk) + 1e-8)
+            assert (np.sign(expect) == -np.sign(go[k][sure])).all()
+            tol = 1e-5 * lr + 4 * np.finfo(np.float32).eps * np.abs(p[k][sure])
             assert (np.abs(step - expect) <= tol).all()
 
 
