@@ -229,7 +229,8 @@ ms_status ms_set_gravity(ms_ctx* c, const double g[3]);
 ms_status ms_set_dirichlet(ms_ctx* c, int64_t n, const int32_t* verts, const double* target_xyz);
 
 /* A rigid half-space {y : normal . y >= offset} in contact with every
- * vertex through the IPC log barrier b(d) = -(d - dhat)^2 ln(d/dhat) on
+ * vertex of positive lumped mass (a vertex of no tet carries no contact)
+ * through the IPC log barrier b(d) = -(d - dhat)^2 ln(d/dhat) on
  * d = normal . x - offset (Eq. IP, term B), scaled by kappa (N/m).  The line
  * search keeps every vertex strictly inside the half-space.  normal need not
  * be unit length (it is normalised).  At most one half-space. */
@@ -514,8 +515,13 @@ void ms_mat_destroy(ms_mat* A);
  * Many independent scenes advanced as one block-diagonal system with
  * per-scene reductions, masks, line searches and convergence (the batched
  * workload of uneven scenes; each scene's result equals ms_step on its own
- * context).  Supported: plain implicit-Euler steps with block-Jacobi PCG,
- * FP64 or mixed precision, no half-space contact.
+ * context).  Supported: plain implicit-Euler steps with block-Jacobi or
+ * the additive two-level preconditioner (every scene with an installed
+ * basis and the exact coarse matrix; each keeps its own coarse operator),
+ * FP64 or mixed precision (one Hessian precision per step: no FP64
+ * endgame), and the IPC half-space barrier when every scene has the same
+ * half-space (no friction); each scene's line search starts from its own
+ * CCD bound.
  *
  * ms_batch_create: join the contexts scenes[n_scenes] (states set, one
  * device, the same gravity, no context twice) into a batch *out; the union

@@ -341,6 +341,41 @@ __global__ void k_baxpy(int64_t n, const int32_t* __restrict__ ubscene, const do
   for (int i = 0; i < 3; ++i) x[3 * v + i] += a * d[3 * v + i];
 }
 
+// Per-scene largest safe step toward the half-space (as k_ccd, over each
+// scene's vertex range): block minima of min(1, safety dist / (-n.d)) over
+// approaching vertices, then one block per scene takes the minimum of its
+// partials.  Minima are exact, so each scene gets its unbatched value.
+__global__ void __launch_bounds__(256) k_bccd(const int4* __restrict__ einfo, const double* __restrict__ x,
+                                              const double* __restrict__ d, HalfSpace hs, double safety,
+                                              double* __restrict__ part) {
+  const int sc = blockIdx.y;
+  const int4 in = einfo[sc];
+  const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  double a = 1.0;
+  if (j < in.w) {
+    const int64_t v = in.z + j;
+    const double dist = hs.n[0] * x[3 * v] + hs.n[1] * x[3 * v + 1] + hs.n[2] * x[3 * v + 2] - hs.off;
+    const double app = -(hs.n[0] * d[3 * v] + hs.n[1] * d[3 * v + 1] + hs.n[2] * d[3 * v + 2]);
+    if (app > 0.0) a = fmin(a, safety * dist / app);
+  }
+  __shared__ double sh[4];
+  a = wave_min(a);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = a;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = sh[0];
+    for (int w = 1; w < int(blockDim.x >> 6); ++w) m = fmin(m, sh[w]);
+    part[int64_t(sc) * gridDim.x + blockIdx.x] = m;
+  }
+}
+
+__global__ void k_bccd_finish(int nblk, const double* __restrict__ part, double* __restrict__ out) {
+  if (threadIdx.x != 0) return;
+  double m = 1.0;
+  for (int b = 0; b < nblk; ++b) m = fmin(m, part[int64_t(blockIdx.x) * nblk + b]);
+  out[8 * blockIdx.x] = m;
+}
+
 }  // namespace
 
 void free_plan(BatchPlan* B) {
@@ -399,7 +434,8 @@ ms_status build_plan(ms_ctx* const* scenes, int ns, BatchPlan*& out) {
   B->u = u;
   ms_ctx* const c = u;  // error reports of the HIP calls below
   if ((st = ms_upload_mesh(u, nv, rest.data(), nt, tets.data())) ||
-      (st = ms_upload_material(u, E.data(), nu.data(), rho.data())) || (st = ms_set_gravity(u, c0->gravity))) {
+      (st = ms_upload_material(u, E.data(), nu.data(), rho.data())) || (st = ms_set_gravity(u, c0->gravity)) ||
+      (c0->has_hs && (st = ms_add_halfspace(u, c0->hs_n, c0->hs_off, c0->hs_dhat, c0->hs_kappa)))) {
     const std::string msg = "batch: union mesh: " + u->err;
     ms_destroy(u);
     delete B;
@@ -452,7 +488,8 @@ ms_status build_plan(ms_ctx* const* scenes, int ns, BatchPlan*& out) {
     return fail(c0, st, msg);
   }
   MS_HIP(hipMemsetAsync(B->d_sscal, 0, sizeof(double) * kStride * ns, u->stream));
-  // padding vertices rest at the origin, at rest, massless and pinned there
+  // padding vertices rest at the origin, at rest, massless (so without
+  // contact terms) and pinned there
   MS_HIP(hipMemsetAsync(u->d_x, 0, sizeof(double) * 3 * u->n, u->stream));
   MS_HIP(hipMemsetAsync(u->d_v, 0, sizeof(double) * 3 * u->n, u->stream));
   B->h_sscal.assign(size_t(kStride) * ns, 0.0);
@@ -484,6 +521,20 @@ ms_status benergy(BatchPlan* B, const double* d, double h2, std::vector<double>&
                                                u->gravity[1], u->gravity[2], hs_of(u), B->d_spart);
   k_seg_finish<5><<<unsigned(B->ns), 256, 0, u->stream>>>(B->d_erange, B->d_spart, B->d_sout);
   h.resize(size_t(8) * B->ns);
+  MS_HIP(hipMemcpyAsync(h.data(), B->d_sout, sizeof(double) * 8 * B->ns, hipMemcpyDeviceToHost, u->stream));
+  return sync(u);
+}
+
+// Per-scene contact filter of the step d: h[8 s] = min(1, CCD bound) of
+// scene s (1 without a half-space).
+ms_status bccd(BatchPlan* B, const double* d, std::vector<double>& h) {
+  ms_ctx* u = B->u;
+  ms_ctx* const c = u;
+  h.assign(size_t(8) * B->ns, 1.0);
+  if (!u->has_hs) return MS_OK;
+  dim3 grid(unsigned(B->ebx), unsigned(B->ns));
+  k_bccd<<<grid, 256, 0, u->stream>>>(B->d_einfo, u->d_x, d, hs_of(u), 0.9, B->d_spart);
+  k_bccd_finish<<<unsigned(B->ns), 64, 0, u->stream>>>(int(B->ebx), B->d_spart, B->d_sout);
   MS_HIP(hipMemcpyAsync(h.data(), B->d_sout, sizeof(double) * 8 * B->ns, hipMemcpyDeviceToHost, u->stream));
   return sync(u);
 }
@@ -703,12 +754,13 @@ ms_status batch_step(BatchPlan* B, double dt, const ms_solver_params& P, ms_step
   launch_apply_dbc(u, int64_t(u->h_dbc.size()));
   if (P.predictor == 1) {  // inertial start, kept per scene where it lowers E
     launch_predictor_dir(u);
-    std::fill(alpha.begin(), alpha.end(), 1.0);
+    if ((s = bccd(B, u->d_d, he))) return s;
+    for (int q = 0; q < ns; ++q) alpha[q] = std::fmin(1.0, he[8 * q]);
     MS_HIP(hipMemcpyAsync(B->d_salpha, alpha.data(), sizeof(double) * ns, hipMemcpyHostToDevice, u->stream));
     if ((s = benergy(B, u->d_d, h2, he))) return s;
     for (int q = 0; q < ns; ++q) {
       double dE = he[8 * q] + he[8 * q + 1] + he[8 * q + 2] + he[8 * q + 3];
-      alpha[q] = (std::isfinite(dE) && dE < 0.0) ? 1.0 : 0.0;
+      alpha[q] = (std::isfinite(dE) && dE < 0.0) ? alpha[q] : 0.0;
     }
     MS_HIP(hipMemcpyAsync(B->d_salpha, alpha.data(), sizeof(double) * ns, hipMemcpyHostToDevice, u->stream));
     k_baxpy<<<nblk(u->n, 256), 256, 0, u->stream>>>(u->n, B->d_ubscene, B->d_salpha, u->d_d, u->d_x);
@@ -793,10 +845,11 @@ ms_status batch_step(BatchPlan* B, double dt, const ms_solver_params& P, ms_step
       }
     }
     if (s) break;
-    // line search, every stepping scene at its own alpha
+    // line search, every stepping scene at its own alpha, from the CCD bound
     std::vector<uint8_t> searching(step);
     std::vector<int> nbt(ns, 0);
-    for (int q = 0; q < ns; ++q) alpha[q] = step[q] ? 1.0 : 0.0;
+    if ((s = bccd(B, u->d_d, he))) break;
+    for (int q = 0; q < ns; ++q) alpha[q] = step[q] ? std::fmin(1.0, he[8 * q]) : 0.0;
     while (true) {
       bool any_search = false;
       for (int q = 0; q < ns; ++q) any_search = any_search || searching[q];
@@ -891,7 +944,13 @@ ms_status batch_scenes_ok(ms_ctx* const* scenes, int n_scenes) {
   for (int q = 0; q < n_scenes; ++q) {
     ms_ctx* sc = scenes[q];
     if (sc->stage < 3) return fail(c0, MS_E_ORDER, "scene " + std::to_string(q) + " has no state");
-    if (sc->has_hs) return fail(c0, MS_E_ARG, "batched steps do not support half-space contact");
+    if (sc->has_hs != c0->has_hs) return fail(c0, MS_E_ARG, "scenes with and without a half-space");
+    if (sc->has_hs) {
+      bool same = sc->hs_off == c0->hs_off && sc->hs_dhat == c0->hs_dhat && sc->hs_kappa == c0->hs_kappa;
+      for (int i = 0; i < 3; ++i) same = same && sc->hs_n[i] == c0->hs_n[i];
+      if (!same) return fail(c0, MS_E_ARG, "scenes with different half-spaces");
+      if (sc->hs_mu > 0.0) return fail(c0, MS_E_ARG, "batched steps do not support friction");
+    }
     if (sc->dev.device != c0->dev.device) return fail(c0, MS_E_ARG, "scenes on different devices");
     for (int i = 0; i < 3; ++i)
       if (sc->gravity[i] != c0->gravity[i]) return fail(c0, MS_E_ARG, "scenes with different gravity");

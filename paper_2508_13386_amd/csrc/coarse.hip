@@ -455,7 +455,7 @@ __global__ void __launch_bounds__(256) k_cub_z(int64_t nz, const int4* __restric
     const double m = mass[v];
 #pragma unroll
     for (int q = 0; q < 9; ++q) D[q] = (q % 4 == 0) ? m : 0.0;
-    if (hs.on) {
+    if (hs.on && m > 0.0) {
       const double y[3] = {x[3 * v], x[3 * v + 1], x[3 * v + 2]};
       double b, b1, b2;
       barrier_terms(hs.n[0] * y[0] + hs.n[1] * y[1] + hs.n[2] * y[2] - hs.off, hs.dhat, b, b1, b2);

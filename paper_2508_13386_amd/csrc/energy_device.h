@@ -74,7 +74,7 @@ __device__ __forceinline__ void vertex_energy_delta(int64_t i, const double* __r
   e[0] = m * (dot_xd + 0.5 * dd);
   e[2] = -h2 * m * (gx * dv[0] + gy * dv[1] + gz * dv[2]);
   e[4] += m * (fabs(dot_xd) + 0.5 * dd) + fabs(e[2]);
-  if (hs.on) {
+  if (hs.on && m > 0.0) {  // massless (isolated, padding) vertices carry no contact
     double b, b1, b2, bn, bn1, bn2;
     const double dist = hs.n[0] * x[3 * i] + hs.n[1] * x[3 * i + 1] + hs.n[2] * x[3 * i + 2] - hs.off;
     const double ddist = hs.n[0] * dv[0] + hs.n[1] * dv[1] + hs.n[2] * dv[2];

@@ -240,7 +240,7 @@ __global__ void k_gather_grad(int64_t n, const int32_t* __restrict__ vt_ptr, con
   double r0 = m * (x0 - xtilde[3 * v]) + h2 * (s0 - m * gx);
   double r1 = m * (x1 - xtilde[3 * v + 1]) + h2 * (s1 - m * gy);
   double r2 = m * (x2 - xtilde[3 * v + 2]) + h2 * (s2 - m * gz);
-  if (hs.on) {
+  if (hs.on && m > 0.0) {  // massless (isolated, padding) vertices carry no contact
     double b, b1, b2;
     barrier_terms(hs.n[0] * x0 + hs.n[1] * x1 + hs.n[2] * x2 - hs.off, hs.dhat, b, b1, b2);
     const double f = h2 * hs.kappa * b1;
@@ -300,7 +300,7 @@ __global__ void __launch_bounds__(64) k_gather_hess(int64_t n, int S, const int3
       acc[0] += m;
       acc[4] += m;
       acc[8] += m;
-      if (hs.on) {
+      if (hs.on && m > 0.0) {
         double b, b1, b2;
         barrier_terms(hs.n[0] * x[3 * row] + hs.n[1] * x[3 * row + 1] + hs.n[2] * x[3 * row + 2] - hs.off,
                       hs.dhat, b, b1, b2);
@@ -371,7 +371,7 @@ __global__ void __launch_bounds__(256) k_energy(int64_t T, int64_t n, const int3
     const double d0 = y[0] - xtilde[3 * i], d1 = y[1] - xtilde[3 * i + 1], d2 = y[2] - xtilde[3 * i + 2];
     e[0] = 0.5 * m * (d0 * d0 + d1 * d1 + d2 * d2);
     e[2] = -h2 * m * (gx * y[0] + gy * y[1] + gz * y[2]);
-    if (hs.on) {
+    if (hs.on && m > 0.0) {
       double b, b1, b2;
       barrier_terms(hs.n[0] * y[0] + hs.n[1] * y[1] + hs.n[2] * y[2] - hs.off, hs.dhat, b, b1, b2);
       e[3] = h2 * hs.kappa * b;
@@ -568,10 +568,10 @@ void launch_gather_hess(ms_ctx* c, const double* x, double h2, int prec) {
 // curvature that the gather kernel adds on diagonal slots).
 template <typename VT>
 __global__ void k_diag_barrier(int64_t n, int S, const int32_t* __restrict__ diag_slot,
-                               const double* __restrict__ x, HalfSpace hs, double h2, double sign,
-                               VT* __restrict__ vals) {
+                               const double* __restrict__ x, const double* __restrict__ mass, HalfSpace hs,
+                               double h2, double sign, VT* __restrict__ vals) {
   const int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (v >= n) return;
+  if (v >= n || !(mass[v] > 0.0)) return;  // as the gather: no contact on massless vertices
   double b, b1, b2;
   barrier_terms(hs.n[0] * x[3 * v] + hs.n[1] * x[3 * v + 1] + hs.n[2] * x[3 * v + 2] - hs.off, hs.dhat, b, b1, b2);
   if (b2 == 0.0) return;
@@ -586,11 +586,11 @@ __global__ void k_diag_barrier(int64_t n, int S, const int32_t* __restrict__ dia
 void launch_diag_barrier(ms_ctx* c, int prec, void* vals, const double* x, double h2, double sign) {
   if (!c->has_hs) return;
   if (prec == MS_PREC_FP64)
-    k_diag_barrier<double><<<nblocks(c->n, 256), 256, 0, c->stream>>>(c->n, c->pat.S, c->pat.d_diag_slot, x, hs_of(c),
-                                                                      h2, sign, static_cast<double*>(vals));
+    k_diag_barrier<double><<<nblocks(c->n, 256), 256, 0, c->stream>>>(c->n, c->pat.S, c->pat.d_diag_slot, x, c->d_mass,
+                                                                      hs_of(c), h2, sign, static_cast<double*>(vals));
   else
-    k_diag_barrier<float><<<nblocks(c->n, 256), 256, 0, c->stream>>>(c->n, c->pat.S, c->pat.d_diag_slot, x, hs_of(c),
-                                                                     h2, sign, static_cast<float*>(vals));
+    k_diag_barrier<float><<<nblocks(c->n, 256), 256, 0, c->stream>>>(c->n, c->pat.S, c->pat.d_diag_slot, x, c->d_mass,
+                                                                     hs_of(c), h2, sign, static_cast<float*>(vals));
 }
 
 void launch_energy(ms_ctx* c, const double* x, const double* d, double alpha, double h2) {

@@ -100,6 +100,54 @@ def test_batch_two_level_equals_unbatched(dev, prec_name, coarse_move):
         c.close()
 
 
+@pytest.mark.parametrize("pc_name", ["jacobi", "additive"])
+def test_batch_contact_equals_unbatched(dev, pc_name):
+    """Half-space contact in a batch: gyroid spheres of three resolutions
+    dropped onto the slab (one shared half-space; the barrier stiffness set
+    equal), each scene's line search starting from its own CCD bound.  Every
+    scene equals its own ms_step bitwise and reaches the oracle's
+    minimiser; the first steps bring the spheres into the barrier's range."""
+    from paper_2508_13386_amd import ms
+    scs = [scenes.gyroid_sphere(res=r) for r in (8, 10, 12)]
+    kappa = scs[1]["halfspace"]["kappa"]
+    for sc in scs:
+        sc["halfspace"] = dict(sc["halfspace"], kappa=kappa)
+    say("contact batch", [len(sc["tets"]) for sc in scs], pc_name)
+    ref = _contexts(dev, scs)
+    bat = _contexts(dev, scs)
+    pc = ms.PC_BLOCK_JACOBI
+    if pc_name == "additive":
+        pc = ms.PC_TWO_LEVEL_ADDITIVE
+        for c in ref + bat:
+            c.ms_build_basis(n_handles=6, seed=2)
+    params = ms.solver_defaults(precision=ms.PREC_MIXED, preconditioner=pc, forcing=1, pcg_eta_max=0.1,
+                                pcg_eta_min=1e-4, coarse_move=0.2)
+    dt = scs[0]["dt"]
+    bodies = [fem.Body(sc["rest"], sc["tets"], sc["E"], sc["nu"], sc["rho"]) for sc in scs]
+    b = ms.Batch(bat)
+    for step in range(1, 4):
+        starts = [c.ms_get_state() for c in bat]
+        st_ref = [c.ms_step(dt, params) for c in ref]
+        st_bat = b.advance(dt, params)
+        for q, sc in enumerate(scs):
+            xr, vr = ref[q].ms_get_state()
+            xb, vb = bat[q].ms_get_state()
+            x0, v0 = starts[q]
+            xo, _, _ = newton.newton_step(bodies[q], x0, v0, dt, sc["gravity"], sc["dirichlet"],
+                                          sc["dbc_targets"](step), halfspace=sc["halfspace"])
+            err = e_rel(xb, xo, x0)
+            gap = float(xb[:, 2].min())
+            say("step", step, "scene", q, "newton", st_ref[q]["newton_iters"], st_bat[q]["newton_iters"], "pcg",
+                st_ref[q]["pcg_iters"], st_bat[q]["pcg_iters"], "min alpha", st_bat[q]["min_alpha"],
+                "lowest z", gap, "oracle e_rel", err)
+            assert np.array_equal(xr, xb) and np.array_equal(vr, vb)
+            assert err <= 1e-6
+    assert min(float(c.ms_get_state()[0][:, 2].min()) for c in bat) < scs[0]["halfspace"]["dhat"]
+    b.close()
+    for c in ref + bat:
+        c.close()
+
+
 def test_created_batch_equals_unbatched(dev):
     """ms_batch_create / ms_batch_advance: the union built once, stepped
     three times, equals each context's own ms_step bitwise; a context whose
@@ -135,7 +183,7 @@ def test_batch_rejects_unsupported(dev):
     assert e.value.code == ms.MS_E_ARG
     g = scenes.gyroid_sphere(res=8)
     bat.append(ms.context_from_scene(dev, g))
-    with pytest.raises(ms.MSError) as e:
+    with pytest.raises(ms.MSError) as e:  # scenes with and without a half-space
         ms.ms_batch_step(bat, scs[0]["dt"])
     assert e.value.code == ms.MS_E_ARG
     for c in bat:
