@@ -190,12 +190,20 @@ def friction_f2(y, eh):
 class StepProblem:
     """E(x) of one implicit Euler step (Eq. IP with alpha = 1)."""
 
-    def __init__(self, body: Body, x_t, v_t, h, gravity, halfspace=None, prev=None):
+    def __init__(self, body: Body, x_t, v_t, h, gravity, halfspace=None, prev=None, selfcontact=None):
         """prev = (x^{t-1}, v^{t-1}) selects BDF2: x~ = 4/3 x^t - 1/3 x^{t-1} +
         8/9 h v^t - 2/9 h v^{t-1} and the weight alpha = 4/9 on the h^2 terms
         (Sec. 3.1 names BDF2 beside implicit Euler; the scheme is the standard
-        second-order backward difference in x and v).  None: implicit Euler."""
+        second-order backward difference in x and v).  None: implicit Euler.
+        selfcontact = dict(dhat, kappa) adds IPC self-contact between the
+        body's surface primitives (term C: h^2 kappa times the pair barriers
+        of oracle.selfcontact over the pairs closer than dhat at x)."""
         self.b = body
+        self.sc = None
+        if selfcontact is not None:
+            from . import selfcontact as scm
+            self.sc = dict(dhat=float(selfcontact["dhat"]), kappa=float(selfcontact["kappa"]),
+                           surf=scm.surface(body.tets))
         self.h = float(h)
         self.x_t = np.asarray(x_t, dtype=np.float64)
         v_t = np.asarray(v_t, dtype=np.float64)
@@ -235,11 +243,25 @@ class StepProblem:
         if self.fric is not None:
             y = np.linalg.norm((x - self.x_t) @ self.fric["P"], axis=1)
             Dv = float((self.fric["mulam"] * friction_f0(y, self.fric["eh"])).sum())
-        return dict(K=K, Psi=h2 * Psi, G=h2 * G, B=h2 * Bv, D=h2 * Dv)
+        Cv = 0.0
+        if self.sc is not None:
+            Cv = self._contact(x, project=True)[0]
+        return dict(K=K, Psi=h2 * Psi, G=h2 * G, B=h2 * Bv, D=h2 * Dv, C=h2 * Cv)
+
+    def _contact(self, x, project=True, derivatives=0):
+        """(kappa-scaled energy, gradient, Hessian) of the self-contact pairs
+        active at x: derivatives 0 energy only, 1 with the gradient, 2 with
+        the gradient and the Hessian."""
+        from . import selfcontact as scm
+        pairs = scm.active_pairs_filtered(x, self.sc["surf"], self.sc["dhat"])
+        if not derivatives:
+            return self.sc["kappa"] * scm.pairs_energy(x, self.b.rest, pairs, self.sc["dhat"]), None, None
+        return scm.contact_terms_sparse(x, self.b.rest, pairs, self.sc["dhat"], self.sc["kappa"], project,
+                                        hessian=derivatives == 2)
 
     def energy(self, x):
         p = self.energy_parts(x)
-        return p["K"] + p["Psi"] + p["G"] + p["B"] + p["D"]
+        return p["K"] + p["Psi"] + p["G"] + p["B"] + p["D"] + p["C"]
 
     def energy_scale(self, x):
         p = self.energy_parts(x)
@@ -265,6 +287,8 @@ class StepProblem:
             f1 = friction_f1(y, self.fric["eh"])
             c1 = np.where(y > 0, f1 / np.where(y > 0, y, 1.0), 2.0 / self.fric["eh"])  # f1(y)/y, 2/eh at 0
             g += h2 * (self.fric["mulam"] * c1)[:, None] * u
+        if self.sc is not None:
+            g += h2 * self._contact(x, derivatives=1)[1]
         return g
 
     def element_hessians(self, x, project=True):
@@ -301,6 +325,8 @@ class StepProblem:
             H = H + _block_diag3(blk)
         if self.fric is not None:
             H = H + _block_diag3(h2 * self.friction_blocks(x))
+        if self.sc is not None:
+            H = H + h2 * self._contact(x, project=project, derivatives=2)[2]
         return H.tocsr()
 
     def friction_blocks(self, x):

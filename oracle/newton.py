@@ -13,8 +13,9 @@ Sec. 3.9):
   2. Newton iteration: g = grad E(x), H = hess E(x) (PSD-projected elastic
      blocks), solve H_ff d_f = -g_f with SuperLU (scipy.sparse.linalg.splu).
   3. Filtered line search: the step is first truncated so that no vertex
-     reaches the half-space (point-plane time of impact, 0.9 safety factor),
-     then backtracked by halving until the Armijo condition
+     reaches the half-space (point-plane time of impact, 0.9 safety factor)
+     and, with self-contact, so that additive CCD certifies every surface
+     pair along it (Sec. 4), then backtracked by halving until the Armijo condition
      E(x + a d) <= E(x) + 1e-4 a g.d holds.  When the predicted decrease
      -g.d is below the round-off level of E (1e-12 of the sum of the absolute
      energy parts) the truncated step is taken as is.
@@ -56,13 +57,16 @@ def ccd_bound(x, d, halfspace, safety=0.9):
 
 
 def newton_step(body: Body, x_t, v_t, h, gravity, dbc=None, dbc_target=None, halfspace=None,
-                dense=False, max_iter=100, tol=1e-12, project=True, record=None, prev=None, x_start=None):
+                dense=False, max_iter=100, tol=1e-12, project=True, record=None, prev=None, x_start=None,
+                selfcontact=None):
     """One timestep; prev = (x^{t-1}, v^{t-1}) selects BDF2, else implicit
     Euler.  x_start (default x^t) is the first Newton iterate: the minimiser
     does not depend on it as long as it lies in the same basin, so a start
-    near the answer only saves iterations."""
+    near the answer only saves iterations.  selfcontact = dict(dhat, kappa)
+    adds the IPC self-contact barrier of the body's surface; every step is
+    then also truncated by the additive-CCD bound of the surface pairs."""
     x_t = np.asarray(x_t, dtype=np.float64)
-    prob = StepProblem(body, x_t, v_t, h, gravity, halfspace, prev)
+    prob = StepProblem(body, x_t, v_t, h, gravity, halfspace, prev, selfcontact)
     x = (x_t if x_start is None else np.asarray(x_start, dtype=np.float64)).copy()
     n = body.n
     free = np.ones((n, 3), dtype=bool)
@@ -97,6 +101,9 @@ def newton_step(body: Body, x_t, v_t, h, gravity, dbc=None, dbc_target=None, hal
             best = np.inf
             continue
         alpha = ccd_bound(x, d, halfspace)
+        if prob.sc is not None:
+            from . import selfcontact as scm
+            alpha = min(alpha, scm.ccd_bound(x, d, prob.sc["surf"]))
         if -gd > 1e-12 * prob.energy_scale(x):
             k = 0
             while prob.energy(x + alpha * d) > E0 + 1e-4 * alpha * gd:

@@ -46,6 +46,15 @@ Parity status (tests/test_oracle_selfcontact.py)
                                separated at the returned time, a hit
                                whenever toi finds one, translations of the
                                whole pair ignored
+  candidate_pairs              pinned: the box filter loses no pair closer
+                               than d_hat (equal to the brute-force set)
+  ccd_bound                    pinned: never beyond the first impact of any
+                               pair along the motion (dense sampling)
+  in the Newton step           pinned (tests/test_oracle_newton.py): the
+                               assembled gradient and Hessian against central
+                               differences of the step energy, momentum
+                               conservation in a collision of two free
+                               bodies, separation kept along the steps
 """
 from __future__ import annotations
 
@@ -145,12 +154,14 @@ def pair_energy(kind, x12, dhat, eps_x=None):
     return e
 
 
-def pair_derivatives(kind, x12, dhat, eps_x=None, project=True):
-    """(energy, gradient [12], Hessian [12,12]) of one pair."""
+def pair_derivatives(kind, x12, dhat, eps_x=None, project=True, hessian=True):
+    """(energy, gradient [12], Hessian [12,12] or None) of one pair."""
     x = torch.tensor(np.asarray(x12, dtype=np.float64), dtype=torch_f64)
     f = lambda y: pair_energy(kind, y, dhat, eps_x)
     e = float(f(x))
     g = torch.autograd.functional.jacobian(f, x).numpy()
+    if not hessian:
+        return e, g, None
     H = torch.autograd.functional.hessian(f, x).numpy()
     H = 0.5 * (H + H.T)
     if project:
@@ -187,6 +198,114 @@ def active_pairs(x, surf, dhat):
             if float(ee_dist2(x12)) < dhat * dhat:
                 ees.append((int(a[0]), int(a[1]), int(b[0]), int(b[1])))
     return pts, ees
+
+
+def candidate_pairs(x, surf, pad, x2=None):
+    """PT and EE pairs (incident ones excluded) whose axis-aligned boxes come
+    within `pad` of each other: a superset of every pair closer than pad
+    (a pair's distance is never below the gap between its boxes).
+    With x2 the boxes span both positions (the motion x -> x2 is linear, so
+    every pair that can meet on the way is kept).  Returns (pts, ees) as
+    vertex quadruples in the order of active_pairs."""
+    tris, edges, verts = surf
+    x = np.asarray(x, dtype=np.float64)
+    lo, hi = x.copy(), x.copy()
+    if x2 is not None:
+        x2 = np.asarray(x2, dtype=np.float64)
+        lo, hi = np.minimum(x, x2), np.maximum(x, x2)
+
+    def boxes(idx):
+        return lo[idx].min(axis=1), hi[idx].max(axis=1)
+
+    def near(alo, ahi, blo, bhi):
+        gap = np.maximum(0.0, np.maximum(alo[:, None, :] - bhi[None, :, :], blo[None, :, :] - ahi[:, None, :]))
+        return np.sqrt((gap * gap).sum(axis=2)) <= pad
+
+    pts, ees = [], []
+    vlo, vhi = lo[verts], hi[verts]
+    tlo, thi = boxes(np.asarray(tris))
+    for a, b in zip(*np.nonzero(near(vlo, vhi, tlo, thi))):
+        v, f = int(verts[a]), tris[b]
+        if v not in f:
+            pts.append((v, int(f[0]), int(f[1]), int(f[2])))
+    elo, ehi = boxes(np.asarray(edges))
+    m = near(elo, ehi, elo, ehi)
+    for i, j in zip(*np.nonzero(np.triu(m, 1))):
+        a, b = edges[i], edges[j]
+        if len({a[0], a[1], b[0], b[1]}) == 4:
+            ees.append((int(a[0]), int(a[1]), int(b[0]), int(b[1])))
+    return pts, ees
+
+
+def active_pairs_filtered(x, surf, dhat):
+    """active_pairs restricted to the box-filtered candidates (same result:
+    a pair closer than d_hat always passes the filter)."""
+    x = np.asarray(x, dtype=np.float64)
+    cpt, cee = candidate_pairs(x, surf, dhat)
+    pts = [q for q in cpt if float(pt_dist2(torch.tensor(x[list(q)].ravel(), dtype=torch_f64))) < dhat * dhat]
+    ees = [q for q in cee if float(ee_dist2(torch.tensor(x[list(q)].ravel(), dtype=torch_f64))) < dhat * dhat]
+    return pts, ees
+
+
+def ccd_bound(x, d, surf, s=0.1):
+    """Largest step in [0, 1] along x + t d that additive CCD certifies for
+    every pair of the surface: the minimum over the pairs whose swept boxes
+    meet of accd's time (pairs that cannot meet before t = 1 do not bound)."""
+    x = np.asarray(x, dtype=np.float64)
+    d = np.asarray(d, dtype=np.float64)
+    cpt, cee = candidate_pairs(x, surf, 0.0, x + d)
+    t = 1.0
+    for kind, lst in (("pt", cpt), ("ee", cee)):
+        for q in lst:
+            idx = list(q)
+            hit, tq = accd(kind, x[idx].ravel(), d[idx].ravel(), s=s, t_max=1.0)
+            if hit:
+                t = min(t, tq)
+    return t
+
+
+def pairs_energy(x, rest, pairs, dhat):
+    """kappa-free energy summed over the given pairs (pts, ees)."""
+    x = np.asarray(x, dtype=np.float64)
+    E = 0.0
+    for kind, lst in (("pt", pairs[0]), ("ee", pairs[1])):
+        for q in lst:
+            eps = eps_x_rest(rest, *q) if kind == "ee" else None
+            E += float(pair_energy(kind, torch.tensor(x[list(q)].ravel(), dtype=torch_f64), dhat, eps))
+    return E
+
+
+def contact_terms_sparse(x, rest, pairs, dhat, kappa, project=True, hessian=True):
+    """kappa-scaled energy, gradient [n,3] and sparse Hessian (CSR,
+    3n x 3n; None without `hessian`) over the given pairs (pts, ees):
+    contact_terms without the dense matrix."""
+    x = np.asarray(x, dtype=np.float64)
+    n = len(x)
+    E = 0.0
+    g = np.zeros(3 * n)
+    rows, cols, vals = [], [], []
+    for kind, lst in (("pt", pairs[0]), ("ee", pairs[1])):
+        for q in lst:
+            eps = eps_x_rest(rest, *q) if kind == "ee" else None
+            x12 = np.concatenate([x[k] for k in q])
+            e, gp, Hp = pair_derivatives(kind, x12, dhat, eps, project, hessian)
+            dof = (3 * np.asarray(q)[:, None] + np.arange(3)[None, :]).ravel()
+            E += kappa * e
+            g[dof] += kappa * gp
+            if not hessian:
+                continue
+            rows.append(np.repeat(dof, 12))
+            cols.append(np.tile(dof, 12))
+            vals.append(kappa * Hp.ravel())
+    import scipy.sparse as sp
+    if not hessian:
+        return E, g.reshape(n, 3), None
+    if rows:
+        H = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                          shape=(3 * n, 3 * n)).tocsr()
+    else:
+        H = sp.csr_matrix((3 * n, 3 * n))
+    return E, g.reshape(n, 3), H
 
 
 def contact_terms(x, rest, pairs, dhat, kappa, project=True):

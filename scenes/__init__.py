@@ -18,6 +18,8 @@ Every scene is a plain dict of numpy arrays / scalars:
   dirichlet int32 [nd]   prescribed vertices (may be empty)
   dbc_targets callable k -> float64 [nd,3] targets for step k (k = 1, 2, ...)
   halfspace None or dict(normal, offset, dhat, kappa)
+  selfcontact (optional) dict(dhat, kappa): IPC contact between the mesh's
+              own surface primitives
   x0, v0 float64 [n,3]
   dt float, steps int, name str
 """
@@ -220,6 +222,44 @@ def sliding_cube(N: int = 6, size: float = 0.2, E: float = 1e6, nu: float = 0.4,
                 dbc_targets=lambda k: np.zeros((0, 3)),
                 halfspace=dict(normal=np.array([0.0, 0.0, 1.0]), offset=0.0, dhat=dhat, kappa=kappa, mu=mu,
                                eps_v=eps_v),
+                x0=rest.copy(), v0=v0, dt=dt, steps=steps)
+
+
+def stacked_cubes(N: int = 3, size: float = 0.1, top: float = 0.08, twist_deg: float = 15.0, gap: float = 1e-3,
+                  dhat: float = 2e-3, E: float = 1e5, nu: float = 0.4, rho: float = 1000.0, speed: float = 0.5,
+                  dt: float = 1.0 / 100.0, steps: int = 10, free: bool = False):
+    """Self-contact scene: two Kuhn N^3 cubes in one mesh.  The lower one
+    (edge `size`) has its bottom face pinned; the upper one (edge `top`),
+    turned by twist_deg about the vertical axis so that edges cross at an
+    angle, centred a little off the lower one's centre line, starts `gap` above the lower one's
+    top face and moves down at `speed` m/s under gravity.  The two bodies
+    meet only through IPC self-contact (selfcontact = dict(dhat, kappa)).
+    With free=True nothing is pinned, there is no gravity and the lower cube
+    moves up at `speed` (a head-on collision of two free bodies)."""
+    r0, t0, _, _ = kuhn_cube(N, size)
+    r1, t1, _, _ = kuhn_cube(N, top)
+    a = math.radians(twist_deg)
+    rot = np.array([[math.cos(a), -math.sin(a), 0.0], [math.sin(a), math.cos(a), 0.0], [0.0, 0.0, 1.0]])
+    c1 = np.array([top / 2, top / 2, 0.0])
+    # centred slightly off the lower cube's centre line, so that no vertex
+    # of one surface lies exactly above a vertex or edge of the other
+    r1 = (r1 - c1) @ rot.T + np.array([0.511 * size, 0.493 * size, size + gap])
+    rest = np.concatenate([r0, r1])
+    tets = np.concatenate([t0, t1 + len(r0)]).astype(np.int32)
+    T = len(tets)
+    v0 = np.zeros_like(rest)
+    v0[len(r0):, 2] = -speed
+    h = size / N
+    kappa = E * h  # barrier stiffness: contact modulus x cell edge length
+    if free:
+        v0[:len(r0), 2] = speed
+        dbc, grav = _empty_dbc(), np.zeros(3)
+    else:
+        dbc, grav = np.nonzero(rest[:, 2] <= 1e-12)[0].astype(np.int32), GRAVITY.copy()
+    tgt = rest[dbc].copy()
+    return dict(name=f"stacked_cubes_{N}", rest=rest, tets=tets, E=np.full(T, E), nu=np.full(T, nu),
+                rho=np.full(T, rho), gravity=grav, dirichlet=dbc, dbc_targets=lambda k, t=tgt: t,
+                halfspace=None, selfcontact=dict(dhat=dhat, kappa=kappa), n_lower=len(r0),
                 x0=rest.copy(), v0=v0, dt=dt, steps=steps)
 
 
