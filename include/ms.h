@@ -246,6 +246,29 @@ ms_status ms_add_halfspace(ms_ctx* c, const double normal[3], double offset, dou
  * mu < 0 or eps_v <= 0. */
 ms_status ms_set_friction(ms_ctx* c, double mu, double eps_v);
 
+/* IPC self-contact between the mesh's own surface primitives (Sec. 4; the
+ * paper's contact model and its CCD-filtered line search, Sec. 3.9): every
+ * point-triangle pair (surface vertex, surface triangle not containing it)
+ * and edge-edge pair (surface edges sharing no vertex) closer than dhat adds
+ * kappa b(d) to the h^2-weighted terms of Eq. IP, with b the log barrier of
+ * ms_add_halfspace in the unsigned distance d between the closed primitives,
+ * times IPC's mollifier of nearly parallel edges for edge-edge pairs (eps_x
+ * = 1e-3 |A1 - A0|^2 |B1 - B0|^2 at rest).  The surface is the set of tet
+ * faces that belong to one tet only.  Every search direction is truncated
+ * by additive CCD (gap fraction 0.1) of the pairs whose swept boxes meet.
+ * The constraint set is recomputed at every assembly and energy
+ * evaluation; its curvature enters the Hessian in the Gauss-Newton form
+ * kappa h^2 m b''(d) grad d grad d^T (positive semi-definite; the minimiser
+ * is that of the exact energy).  Each surface vertex reserves `slots`
+ * Hessian blocks for couplings outside its mesh neighbourhood; an assembly
+ * that needs more fails with MS_E_ARG.  The two-level preconditioners'
+ * coarse matrix omits the self-contact terms.  Plain mode only (not paper
+ * mode, not the smoothed two-level preconditioner, not batched steps).
+ * The state must be free of intersections.  Call between ms_upload_mesh and
+ * ms_upload_material.  Errors: MS_E_ORDER, MS_E_ARG (dhat or kappa not
+ * positive, slots outside [1, 64]). */
+ms_status ms_set_self_contact(ms_ctx* c, double dhat, double kappa, int32_t slots);
+
 /* Set positions x [n][3] and velocities v [n][3].  With a half-space every
  * vertex must lie strictly inside it.  Errors: MS_E_NONFINITE, MS_E_ARG. */
 ms_status ms_set_state(ms_ctx* c, const double* x, const double* v);

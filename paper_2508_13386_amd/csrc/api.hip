@@ -183,17 +183,23 @@ ms_status assemble(ms_ctx* c, const double* x, double h2, int prec, bool project
   launch_element(c, x, h2, prec, true, project);
   launch_gather_grad(c, x, h2, c->d_g);
   launch_gather_hess(c, x, h2, prec);
+  // the coarse matrix is formed before the self-contact terms join the
+  // Hessian: it stays the (SPD) Galerkin operator of the rest
+  if (need_pc && two_level(pc) && (refresh_coarse || !c->coarse_valid)) {
+    ms_status s = launch_galerkin(c, prec, x, h2);
+    if (s) return s;
+    s = coarse_factor(c);
+    if (s) return s;
+  }
+  if (c->sc.on) {
+    ms_status s = sc_assemble(c, x, h2, prec);
+    if (s) return s;
+  }
   if (need_pc) {
     if (pc == MS_PC_TWO_LEVEL_VCYCLE)
       launch_block_jacobi_l1(c, prec);
     else
       launch_block_jacobi(c, prec);
-    if (two_level(pc) && (refresh_coarse || !c->coarse_valid)) {
-      ms_status s = launch_galerkin(c, prec, x, h2);
-      if (s) return s;
-      s = coarse_factor(c);
-      if (s) return s;
-    }
   }
   return MS_OK;
 }
@@ -205,6 +211,12 @@ ms_status energy_delta(ms_ctx* c, const double* x, const double* d, double alpha
   if (s) return s;
   *dE = c->h_scal[S_DE0] + c->h_scal[S_DE1] + c->h_scal[S_DE2] + c->h_scal[S_DE3];
   *err = c->h_scal[S_DE4];
+  if (c->sc.on) {
+    double dc, ec;
+    if ((s = sc_energy_delta(c, x, d, alpha, h2, &dc, &ec))) return s;
+    *dE += dc;
+    *err += ec;
+  }
   return MS_OK;
 }
 
@@ -213,6 +225,18 @@ ms_status energy(ms_ctx* c, const double* x, const double* d, double alpha, doub
   ms_status s = read_scal(c);
   if (s) return s;
   for (int k = 0; k < 4; ++k) parts[k] = c->h_scal[S_E0 + k];
+  if (c->sc.on) {
+    const double* y = x;
+    if (d) {
+      launch_fill(c, c->sc.d_y, 0.0, 3 * c->n);
+      launch_axpy(c, c->sc.d_y, x, 1.0, 3 * c->n);
+      launch_axpy(c, c->sc.d_y, d, alpha, 3 * c->n);
+      y = c->sc.d_y;
+    }
+    double e;
+    if ((s = sc_energy(c, y, h2, &e))) return s;
+    parts[3] += e;
+  }
   return MS_OK;
 }
 
@@ -391,6 +415,20 @@ ms_status ms_add_halfspace(ms_ctx* c, const double nrm[3], double off, double dh
   return MS_OK;
 }
 
+ms_status ms_set_self_contact(ms_ctx* c, double dhat, double kappa, int32_t slots) {
+  if (!c) return MS_E_ARG;
+  if (c->stage != 1) return fail(c, MS_E_ORDER, "self-contact is set between ms_upload_mesh and ms_upload_material");
+  if (!(dhat > 0.0) || !std::isfinite(dhat) || !(kappa > 0.0) || !std::isfinite(kappa) || slots < 1 || slots > 64)
+    return fail(c, MS_E_ARG, "need dhat > 0, kappa > 0 and 1 <= slots <= 64");
+  c->sc.on = true;
+  c->sc.dhat = dhat;
+  c->sc.kappa = kappa;
+  c->sc.spare = slots;
+  ms_status s = sc_setup(c);
+  if (s) c->sc.on = false;
+  return s;
+}
+
 ms_status ms_set_friction(ms_ctx* c, double mu, double eps_v) {
   if (!c) return MS_E_ARG;
   if (!c->has_hs) return fail(c, MS_E_ORDER, "add a half-space first");
@@ -489,6 +527,12 @@ ms_status ms_energy_difference(ms_ctx* c, const double* x, const double* d, doub
   ms_status s = read_scal(c);
   if (s) return s;
   for (int k = 0; k < 5; ++k) parts5[k] = c->h_scal[S_DE0 + k];
+  if (c->sc.on) {
+    double dc, ec;
+    if ((s = sc_energy_delta(c, c->d_xtrial, c->d_w, alpha, dt * dt, &dc, &ec))) return s;
+    parts5[3] += dc;
+    parts5[4] += ec;
+  }
   return MS_OK;
 }
 
@@ -531,6 +575,9 @@ ms_status ms_step(ms_ctx* c, double dt, const ms_solver_params* pin, ms_step_sta
   // the learned start is judged on the implicit Euler incremental potential
   if (P.integrator == 1 && P.warm_start && c->mlp)
     return fail(c, MS_E_ARG, "the learned warm start steps with implicit Euler");
+  if (c->sc.on && P.mode == MS_MODE_PAPER) return fail(c, MS_E_ARG, "paper mode has no self-contact");
+  if (c->sc.on && P.preconditioner == MS_PC_TWO_LEVEL)
+    return fail(c, MS_E_ARG, "the smoothed two-level preconditioner has no self-contact");
   if (P.mode == MS_MODE_PAPER) return paper_step(c, dt, P, st);
   // the smoothed (deflated) form projects with the coarse matrix and stays a
   // symmetric positive definite preconditioner only for the exact U^T H U

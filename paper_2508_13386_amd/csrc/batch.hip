@@ -937,8 +937,8 @@ ms_status batch_params(ms_ctx* c0, double dt, const ms_solver_params* pin, ms_so
   return MS_OK;
 }
 
-// Scenes a batch can hold: states set, no contact, one device, one gravity,
-// no repeats.
+// Scenes a batch can hold: states set, one shared half-space or none, no
+// friction, no self-contact, one device, one gravity, no repeats.
 ms_status batch_scenes_ok(ms_ctx* const* scenes, int n_scenes) {
   ms_ctx* c0 = scenes[0];
   for (int q = 0; q < n_scenes; ++q) {
@@ -951,6 +951,7 @@ ms_status batch_scenes_ok(ms_ctx* const* scenes, int n_scenes) {
       if (!same) return fail(c0, MS_E_ARG, "scenes with different half-spaces");
       if (sc->hs_mu > 0.0) return fail(c0, MS_E_ARG, "batched steps do not support friction");
     }
+    if (sc->sc.on) return fail(c0, MS_E_ARG, "batched steps do not support self-contact");
     if (sc->dev.device != c0->dev.device) return fail(c0, MS_E_ARG, "scenes on different devices");
     for (int i = 0; i < 3; ++i)
       if (sc->gravity[i] != c0->gravity[i]) return fail(c0, MS_E_ARG, "scenes with different gravity");

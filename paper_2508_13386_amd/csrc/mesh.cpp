@@ -162,7 +162,21 @@ ms_status build_pattern(ms_ctx* c) {
       if (best[q] < 0.97 * best[1] && best[q] < bt) bt = best[q], S = cands[q];
   }
   P.S = S;
-  slice_layout(n, P.h_row_ptr.data(), S, P.h_slice_base, P.maxw);
+  // self-contact reserves `spare` extra block columns in every surface row
+  // (contact slots, column -1 until a contact pair couples the row)
+  std::vector<int32_t> lay_ptr(P.h_row_ptr);
+  SelfContact& SC = c->sc;
+  SC.h_spare0.assign(n, -1);
+  if (SC.spare > 0) {
+    std::vector<uint8_t> surf(n, 0);
+    for (int32_t v : SC.h_verts) surf[v] = 1;
+    for (int64_t r = 0; r < n; ++r) {
+      const int32_t len = P.h_row_ptr[r + 1] - P.h_row_ptr[r];
+      if (surf[r]) SC.h_spare0[r] = len;
+      lay_ptr[r + 1] = lay_ptr[r] + len + (surf[r] ? SC.spare : 0);
+    }
+  }
+  slice_layout(n, lay_ptr.data(), S, P.h_slice_base, P.maxw);
   P.nslices = int64_t(P.h_slice_base.size()) - 1;
   P.nslots = P.h_slice_base[P.nslices];
   std::vector<int32_t> scol(P.nslots, -1), diag_slot(n);
@@ -207,6 +221,7 @@ ms_status build_pattern(ms_ctx* c) {
         }
   }
   ms_status s;
+  if (SC.spare > 0) SC.h_col = scol;
   if ((s = upload(c, &P.d_slice_base, P.h_slice_base.data(), P.nslices + 1))) return s;
   if ((s = upload(c, &P.d_col, scol.data(), P.nslots))) return s;
   if ((s = upload(c, &P.d_diag_slot, diag_slot.data(), n))) return s;

@@ -125,6 +125,32 @@ struct Basis {
 
 struct Mlp;
 
+namespace ms {
+// IPC self-contact between the mesh's own surface primitives (Sec. 4): the
+// surface, the contact slots reserved in the Hessian pattern, and the lists
+// of the current constraint set (rebuilt at every assembly).
+struct SelfContact {
+  bool on = false;
+  double dhat = 0.0, kappa = 0.0;
+  double cell = 0.0;  // broad-phase grid cell of the static constraint set
+  int spare = 0;      // contact slots reserved per surface row
+  std::vector<int32_t> h_tris, h_edges, h_verts;  // surface triangles [F][3], edges [E][2], vertices
+  int32_t *d_tris = nullptr, *d_edges = nullptr, *d_verts = nullptr;
+  std::vector<int32_t> h_spare0;  // [n] first contact slot (block column index) of each row, -1 none
+  std::vector<int32_t> h_col;     // host copy of every slot's column, contact slots included
+  double* d_y = nullptr;          // [3n] trial positions
+  // lists of the last assembly: pair quads, gradient and Hessian gathers
+  int64_t np = 0, ng = 0, nh = 0;
+  int32_t* d_quad = nullptr;  // [np][5] kind (0 point-triangle, 1 edge-edge), four vertex ids
+  double* d_pdat = nullptr;   // [np][24] energy, gradient [12], GN weight, coefficients [4], normal [3]
+  int32_t* d_glist = nullptr; // ng vertices, ng + 1 offsets, entries [2] (pair, local)
+  int32_t* d_hlist = nullptr; // nh slots, nh + 1 offsets, entries [3] (pair, local a, local b)
+  int32_t* d_aux = nullptr;   // quads of energy evaluations and CCD candidates
+  double* d_aux_out = nullptr;
+  int64_t cap_quad = 0, cap_pdat = 0, cap_glist = 0, cap_hlist = 0, cap_aux = 0, cap_aux_out = 0;
+};
+}  // namespace ms
+
 struct ms_ctx {
   ms_device dev{};
   hipStream_t stream = nullptr;
@@ -159,6 +185,7 @@ struct ms_ctx {
   double hs_n[3] = {0, 0, 1}, hs_off = 0, hs_dhat = 1e-3, hs_kappa = 0;
   double hs_mu = 0.0, hs_epsv = 1e-3;  // lagged friction against the half-space
   double step_h = 0.0;                 // timestep of the current step / evaluation
+  ms::SelfContact sc;
   // Dirichlet
   std::vector<int32_t> h_dbc;
   std::vector<double> h_dbc_tgt;
@@ -392,6 +419,14 @@ ms_status try_move(ms_ctx* c, double h2);
 void launch_predictor_dir(ms_ctx* c);
 ms_status record_coarse(ms_ctx* c);
 ms_status mat_build(struct ::ms_mat* A, int64_t n, const int32_t* row_ptr, const int32_t* col, const double* vals);
+
+// self-contact (selfcontact.hip)
+ms_status sc_setup(ms_ctx* c);
+ms_status sc_assemble(ms_ctx* c, const double* x, double h2, int prec);
+ms_status sc_energy(ms_ctx* c, const double* x, double h2, double* e);
+ms_status sc_energy_delta(ms_ctx* c, const double* x, const double* d, double alpha, double h2, double* dE,
+                          double* err);
+ms_status sc_ccd(ms_ctx* c, const double* x, const double* d, double* t);
 void mat_spmv(struct ::ms_mat* A, const void* x, void* y);
 
 }  // namespace ms

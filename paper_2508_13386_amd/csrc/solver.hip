@@ -3,7 +3,8 @@
 // Per Newton iteration: element kernel + atomic-free gathers assemble g
 // (FP64) and H (FP64 or FP32) at x; PCG (block-Jacobi or two-level) solves
 // H d = -g to the forcing tolerance eta = min(eta_max, sqrt(||g|| / ||g_0||));
-// the step is truncated by the half-space CCD bound and backtracked until the
+// the step is truncated by the contact filters (the half-space bound and the
+// additive CCD of the self-contact pairs) and backtracked until the
 // Armijo condition holds on the FP64 energy difference (evaluated term by
 // term, with a round-off allowance).  The iteration stops after a
 // full step with ||d|| <= newton_tol * max(||x - x^t||, abs_floor) or with
@@ -43,6 +44,11 @@ ms_status line_search(ms_ctx* c, double h2, double gd, int max_bt, double* alpha
     if ((s = read_scal(c))) return s;
     alpha = std::fmin(1.0, c->h_scal[S_CCD]);
   }
+  if (c->sc.on) {
+    double t;
+    if ((s = sc_ccd(c, c->d_x, c->d_d, &t))) return s;
+    alpha = std::fmin(alpha, t);
+  }
   int k = 0;
   while (true) {
     double dE, err;
@@ -72,6 +78,11 @@ ms_status try_move(ms_ctx* c, double h2) {
     launch_ccd(c, c->d_x, c->d_d);
     if ((s = read_scal(c))) return s;
     alpha = std::fmin(1.0, c->h_scal[S_CCD]);
+  }
+  if (c->sc.on) {
+    double t;
+    if ((s = sc_ccd(c, c->d_x, c->d_d, &t))) return s;
+    alpha = std::fmin(alpha, t);
   }
   double dE, err;
   if ((s = energy_delta(c, c->d_x, c->d_d, alpha, h2, &dE, &err))) return s;

@@ -91,6 +91,7 @@ def lib():
             "ms_set_dirichlet": [vp, i64, ip, dp],
             "ms_add_halfspace": [vp, dp, d, d, d],
             "ms_set_friction": [vp, d, d],
+            "ms_set_self_contact": [vp, d, d, i32],
             "ms_set_state": [vp, dp, dp],
             "ms_get_state": [vp, dp, dp],
             "ms_build_basis": [vp, C.POINTER(ms_basis_params)],
@@ -275,6 +276,9 @@ class Context:
 
     def ms_set_friction(self, mu, eps_v=1e-3):
         self._check(self.L.ms_set_friction(self.h, float(mu), float(eps_v)))
+
+    def ms_set_self_contact(self, dhat, kappa, slots=16):
+        self._check(self.L.ms_set_self_contact(self.h, float(dhat), float(kappa), int(slots)))
 
     def ms_set_state(self, x, v):
         x, v = _f64(x), _f64(v)
@@ -652,6 +656,8 @@ def context_from_scene(dev: TorchDevice, s, step: int = 1):
     """Create a context and upload a scene dict from the `scenes` generators."""
     c = Context(dev)
     c.ms_upload_mesh(s["rest"], s["tets"])
+    if s.get("selfcontact") is not None:
+        c.ms_set_self_contact(s["selfcontact"]["dhat"], s["selfcontact"]["kappa"])
     c.ms_upload_material(s["E"], s["nu"], s["rho"])
     c.ms_set_gravity(s["gravity"])
     if len(s["dirichlet"]):
