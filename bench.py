@@ -43,7 +43,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=8)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--grid", type=int, default=32)
-    ap.add_argument("--scene", choices=["block", "gyroid", "sliding"], default="block",
+    ap.add_argument("--scene", choices=["block", "gyroid", "sliding", "stacked"], default="block",
                     help="block: the heterogeneous block (--grid); gyroid: the contact scene, a gyroid-lattice "
                          "sphere voxelized at --grid^3 falling at 5 m/s onto a rigid half-space; sliding: a "
                          "--grid^3 cube sliding on the half-space with lagged friction (mu = 0.5)")
@@ -117,7 +117,10 @@ def cpu_baseline(scene="block", grid=32, n_tets=None):
     import scenes
     from oracle import fem, newton
     g = max(4, (3 * grid) // 8 if scene == "gyroid" else grid // 2)
-    if scene == "gyroid":
+    if scene == "stacked":  # the oracle's per-pair derivatives are costly: the smallest cubes
+        g = 2
+        s = scenes.stacked_cubes(N=g, steps=1)
+    elif scene == "gyroid":
         s = scenes.gyroid_sphere(res=g)
     elif scene == "sliding":
         s = scenes.sliding_cube(g, steps=1)
@@ -127,7 +130,7 @@ def cpu_baseline(scene="block", grid=32, n_tets=None):
         t0 = time.perf_counter()
         body = fem.Body(s["rest"], s["tets"], s["E"], s["nu"], s["rho"])
         newton.newton_step(body, s["x0"], s["v0"], s["dt"], s["gravity"], s["dirichlet"], s["dbc_targets"](1),
-                           halfspace=s["halfspace"])
+                           halfspace=s["halfspace"], selfcontact=s.get("selfcontact"))
         dt = time.perf_counter() - t0
     ratio = (n_tets or 8 * len(s["tets"])) / len(s["tets"])
     return dict(value=1.0 / (dt * ratio), unit="timesteps/s", cores=1, kind="oracle", cpu=cpu_model(),
@@ -844,7 +847,12 @@ def main():
     import scenes
     from paper_2508_13386_amd import ms
 
-    if a.scene == "sliding":
+    if a.scene == "stacked":
+        s = scenes.stacked_cubes(N=a.grid, steps=a.warmup + a.steps)
+        wname = (f"two cubes of {a.grid}^3 hexes x 6 tets (0.1 m and 0.08 m, E=1e5, nu=0.4), the upper one turned "
+                 f"15 degrees and falling at 0.5 m/s onto the pinned lower one, IPC self-contact "
+                 f"(point-triangle and edge-edge) d_hat=2e-3, dt=1/100")
+    elif a.scene == "sliding":
         s = scenes.sliding_cube(a.grid, steps=a.warmup + a.steps)
         wname = (f"cube {a.grid}^3 hexes x 6 tets (0.2 m, E=1e6, nu=0.4) sliding at 1.1 m/s on a rigid half-space, "
                  f"IPC barrier d_hat=1e-3, lagged friction mu=0.5, eps_v=1e-3, dt=1/100")

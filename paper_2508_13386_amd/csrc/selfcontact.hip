@@ -26,6 +26,7 @@
 #include <array>
 #include <cmath>
 #include <iterator>
+#include <string>
 #include <vector>
 
 #include <hipcub/hipcub.hpp>
@@ -977,17 +978,39 @@ ms_status sc_assemble(ms_ctx* c, const double* x, double h2, int prec) {
   std::vector<std::array<int64_t, 4>> hent;  // (slot, pair, a, b)
   gent.reserve(4 * np);
   hent.reserve(16 * np);
+  int64_t over = 0;  // couplings beyond the reserved slots
   for (int64_t p = 0; p < np; ++p)
     for (int a = 0; a < 4; ++a) {
       const int32_t va = q[5 * p + 1 + a];
       gent.push_back({va, int32_t(p), a});
       for (int b = 0; b < 4; ++b) {
         int64_t sl;
-        if (!slot_of(va, q[5 * p + 1 + b], &sl))
-          return fail(c, MS_E_ARG, "a surface vertex couples to more vertices than the reserved contact slots");
+        if (!slot_of(va, q[5 * p + 1 + b], &sl)) {
+          ++over;
+          continue;
+        }
         hent.push_back({sl, p, a, b});
       }
     }
+  if (over) {
+    int most = 0;  // the largest number of contact couplings of one row
+    std::vector<std::vector<int32_t>> cols(c->n);
+    for (int64_t p = 0; p < np; ++p)
+      for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b) {
+          const int32_t va = q[5 * p + 1 + a], vb = q[5 * p + 1 + b];
+          const int32_t* lo = &P.h_col[P.h_row_ptr[va]];
+          const int32_t* hi = &P.h_col[P.h_row_ptr[va + 1]];
+          if (!std::binary_search(lo, hi, vb)) cols[va].push_back(vb);
+        }
+    for (auto& v : cols) {
+      std::sort(v.begin(), v.end());
+      most = std::max(most, int(std::unique(v.begin(), v.end()) - v.begin()));
+    }
+    return fail(c, MS_E_ARG, "a surface vertex couples to " + std::to_string(most) +
+                                 " vertices outside its mesh neighbourhood; " + std::to_string(S.spare) +
+                                 " contact slots are reserved (ms_set_self_contact)");
+  }
   std::sort(gent.begin(), gent.end());
   std::sort(hent.begin(), hent.end());
   std::vector<int32_t> gl, hl;

@@ -277,7 +277,7 @@ class Context:
     def ms_set_friction(self, mu, eps_v=1e-3):
         self._check(self.L.ms_set_friction(self.h, float(mu), float(eps_v)))
 
-    def ms_set_self_contact(self, dhat, kappa, slots=16):
+    def ms_set_self_contact(self, dhat, kappa, slots=32):
         self._check(self.L.ms_set_self_contact(self.h, float(dhat), float(kappa), int(slots)))
 
     def ms_set_state(self, x, v):
@@ -657,7 +657,7 @@ def context_from_scene(dev: TorchDevice, s, step: int = 1):
     c = Context(dev)
     c.ms_upload_mesh(s["rest"], s["tets"])
     if s.get("selfcontact") is not None:
-        c.ms_set_self_contact(s["selfcontact"]["dhat"], s["selfcontact"]["kappa"])
+        c.ms_set_self_contact(s["selfcontact"]["dhat"], s["selfcontact"]["kappa"], s["selfcontact"].get("slots", 32))
     c.ms_upload_material(s["E"], s["nu"], s["rho"])
     c.ms_set_gravity(s["gravity"])
     if len(s["dirichlet"]):
