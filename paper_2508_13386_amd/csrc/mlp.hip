@@ -5,8 +5,8 @@
 // x^t + U (q_hat - q^t) when that lowers the energy.
 //
 // Dense products run on the matrix cores: 64x64 output tiles per block of
-// four waves, each wave a 32x32 quadrant of 2x2 MFMA 16x16x16 bf16 tiles
-// with FP32 accumulation; operands are FP32 in memory and rounded to bf16
+// four waves, each wave a 32x32 quadrant of 2x2 MFMA 16x16x32 bf16 tiles
+// (gfx950) with FP32 accumulation; operands are FP32 in memory and rounded to bf16
 // (nearest even) as they are staged through LDS.  Training is Adam on FP32
 // master weights over caller-given minibatches (deterministic: no atomics,
 // fixed reduction orders).
@@ -18,7 +18,7 @@
 #include "ms_internal.h"
 
 typedef float v4f __attribute__((ext_vector_type(4)));
-typedef short v4s __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
 struct Mlp {
   int in = 0, w = 0, out = 0;
@@ -43,13 +43,17 @@ __device__ __forceinline__ unsigned short to_bf16(float f) {
 
 // C[m][n] = sum_k opA[m][k] opB[k][n] (+ bias[n]) (+ C[m][n] if accumulate).
 // TA: A stored [K][M] (else [M][K]); BNK: B stored [N][K] (else [K][N]).
+// Each k-step stages a 64 x 32 slab of both operands in LDS as bf16 and
+// feeds gfx950's 16x16x32 bf16 MFMA: lane l holds row (or column) l % 16 of
+// its tile and the 8 consecutive k of group l / 16, one 16-byte LDS read.
 template <bool TA, bool BNK>
 __global__ void __launch_bounds__(256) k_gemm_bf16(int M, int N, int K, const float* __restrict__ A, int lda,
                                                    const float* __restrict__ B, int ldb, float* __restrict__ C,
                                                    int ldc, const float* __restrict__ bias, int accumulate) {
-  constexpr int LDK = 20;  // bf16 elements per LDS row (16 + 4: 8-byte aligned rows)
-  __shared__ unsigned short As[64][LDK];
-  __shared__ unsigned short Bs[64][LDK];
+  constexpr int KT = 32;   // k per step
+  constexpr int LDK = 40;  // bf16 per LDS row (32 + 8: 80-byte rows keep the 16-byte reads aligned)
+  __shared__ __align__(16) unsigned short As[64][LDK];
+  __shared__ __align__(16) unsigned short Bs[64][LDK];
   const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
@@ -58,17 +62,17 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(int M, int N, int K, const fl
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < K; k0 += 16) {
+  for (int k0 = 0; k0 < K; k0 += KT) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < 8; ++r) {
       const int e = t + 256 * r;
       int mm, kk;
       if (TA) {
         kk = e / 64;
         mm = e % 64;
       } else {
-        mm = e / 16;
-        kk = e % 16;
+        mm = e / KT;
+        kk = e % KT;
       }
       const int gm = m0 + mm, gk = k0 + kk;
       float va = 0.f;
@@ -76,8 +80,8 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(int M, int N, int K, const fl
       As[mm][kk] = to_bf16(va);
       int nn;
       if (BNK) {
-        nn = e / 16;
-        kk = e % 16;
+        nn = e / KT;
+        kk = e % KT;
       } else {
         kk = e / 64;
         nn = e % 64;
@@ -88,19 +92,17 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(int M, int N, int K, const fl
       Bs[nn][kk] = to_bf16(vb);
     }
     __syncthreads();
-    v4s a[2], b[2];
-    const int kq = 4 * (lane >> 4), rr = lane & 15;
+    v8bf a[2], b[2];
+    const int kq = 8 * (lane >> 4), rr = lane & 15;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      a[i] = __builtin_bit_cast(v8bf, *reinterpret_cast<const uint4*>(&As[wm + 16 * i + rr][kq]));
+      b[i] = __builtin_bit_cast(v8bf, *reinterpret_cast<const uint4*>(&Bs[wn + 16 * i + rr][kq]));
+    }
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        a[i][q] = static_cast<short>(As[wm + 16 * i + rr][kq + q]);
-        b[i][q] = static_cast<short>(Bs[wn + 16 * i + rr][kq + q]);
-      }
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+      for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
     __syncthreads();
   }
   // lane holds rows 4 (lane / 16) + q, column lane % 16 of each 16x16 tile

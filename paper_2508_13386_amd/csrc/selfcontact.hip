@@ -29,7 +29,9 @@
 #include <string>
 #include <vector>
 
-#include <hipcub/hipcub.hpp>
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_scan.hpp>
+#include <rocprim/device/device_select.hpp>
 
 #include "contact.h"
 #include "ms_internal.h"
@@ -350,10 +352,13 @@ ms_status find_pairs(Pool& pool, hipStream_t st, bool ee, int64_t np_a, const in
   };
   auto exclusive_scan = [&](const int64_t* in, int64_t* out, int64_t n) -> ms_status {
     size_t tmp = 0;
-    if (hipcub::DeviceScan::ExclusiveSum(nullptr, tmp, in, out, int(n), st) != hipSuccess) return MS_E_DEVICE;
+    if (rocprim::exclusive_scan(nullptr, tmp, in, out, int64_t(0), size_t(n), rocprim::plus<int64_t>(), st) !=
+        hipSuccess)
+      return MS_E_DEVICE;
     void* t = pool.get<char>(tmp);
     if (!t) return MS_E_NOMEM;
-    if (hipcub::DeviceScan::ExclusiveSum(t, tmp, in, out, int(n), st) != hipSuccess) return MS_E_DEVICE;
+    if (rocprim::exclusive_scan(t, tmp, in, out, int64_t(0), size_t(n), rocprim::plus<int64_t>(), st) != hipSuccess)
+      return MS_E_DEVICE;
     return MS_OK;
   };
   // entries: a-primitives, then b-primitives (tagged)
@@ -380,11 +385,11 @@ ms_status find_pairs(Pool& pool, hipStream_t st, bool ee, int64_t np_a, const in
                                           keys, vals);
   {
     size_t tmp = 0;
-    if (hipcub::DeviceRadixSort::SortPairs(nullptr, tmp, keys, skeys, vals, svals, int(ne), 0, 64, st) != hipSuccess)
+    if (rocprim::radix_sort_pairs(nullptr, tmp, keys, skeys, vals, svals, ne, 0, 64, st) != hipSuccess)
       return MS_E_DEVICE;
     void* t = pool.get<char>(tmp);
     if (!t) return MS_E_NOMEM;
-    if (hipcub::DeviceRadixSort::SortPairs(t, tmp, keys, skeys, vals, svals, int(ne), 0, 64, st) != hipSuccess)
+    if (rocprim::radix_sort_pairs(t, tmp, keys, skeys, vals, svals, ne, 0, 64, st) != hipSuccess)
       return MS_E_DEVICE;
   }
   k_cell_end<<<blocks(ne), 256, 0, st>>>(ne, skeys, cend);
@@ -408,19 +413,20 @@ ms_status find_pairs(Pool& pool, hipStream_t st, bool ee, int64_t np_a, const in
                                            cand);
   {
     size_t tmp = 0;
-    if (hipcub::DeviceRadixSort::SortKeys(nullptr, tmp, cand, scand, int(nc), 0, 64, st) != hipSuccess)
+    if (rocprim::radix_sort_keys(nullptr, tmp, cand, scand, nc, 0, 64, st) != hipSuccess)
       return MS_E_DEVICE;
     void* t = pool.get<char>(tmp);
     if (!t) return MS_E_NOMEM;
-    if (hipcub::DeviceRadixSort::SortKeys(t, tmp, cand, scand, int(nc), 0, 64, st) != hipSuccess) return MS_E_DEVICE;
+    if (rocprim::radix_sort_keys(t, tmp, cand, scand, nc, 0, 64, st) != hipSuccess) return MS_E_DEVICE;
   }
   {
     size_t tmp = 0;
-    if (hipcub::DeviceSelect::Unique(nullptr, tmp, scand, ucand, nu_d, int(nc), st) != hipSuccess)
+    if (rocprim::unique(nullptr, tmp, scand, ucand, nu_d, size_t(nc), rocprim::equal_to<int64_t>(), st) != hipSuccess)
       return MS_E_DEVICE;
     void* t = pool.get<char>(tmp);
     if (!t) return MS_E_NOMEM;
-    if (hipcub::DeviceSelect::Unique(t, tmp, scand, ucand, nu_d, int(nc), st) != hipSuccess) return MS_E_DEVICE;
+    if (rocprim::unique(t, tmp, scand, ucand, nu_d, size_t(nc), rocprim::equal_to<int64_t>(), st) != hipSuccess)
+      return MS_E_DEVICE;
   }
   int64_t nu = 0;
   if (!sync_read(nu_d, &nu)) return MS_E_DEVICE;
