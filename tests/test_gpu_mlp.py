@@ -138,3 +138,66 @@ def test_warm_started_steps_match_oracle(dev):
         x, v = xg, vg  # continue from the GPU state: the coarse history is the GPU's
     assert used[0] == 0 and sum(used[1:3]) >= 1
     c.close()
+
+
+def test_trained_warm_start_on_heldout_seeds(dev):
+    """What the trained network gains over the method without it, measured on
+    held-out trajectories: a network trained on the coarse states of solver
+    trajectories (one fixed block, drives varying by seed, one shared basis)
+    predicts the next coarse state; each held-out step is run with and
+    without it.  Both forms reach the same minimiser at every step; the
+    Newton and PCG counts of both and the steps where the learned start was
+    taken are reported.  No gain is asserted: on this workload the learned
+    coarse start rarely beats the inertial predictor."""
+    from paper_2508_13386_amd import ms
+    N, steps = 8, 10
+    basis = {}
+    form = dict(precision=ms.PREC_MIXED, preconditioner=ms.PC_TWO_LEVEL_ADDITIVE, forcing=1, pcg_eta_max=0.1,
+                pcg_eta_min=1e-4, coarse_move=0.2, max_newton=100)
+
+    def run(seed, warm=None):
+        sc = scenes.learned_drive_scene(seed, N=N, steps=steps)
+        c = ms.context_from_scene(dev, sc)
+        if not basis:
+            c.ms_build_basis(n_handles=8, seed=1)
+            basis.update(c.ms_get_basis())
+        else:
+            c.ms_set_basis(basis["origins"], basis["vptr"], basis["vhandle"], basis["vphi"])
+        r = 12 * basis["m"]
+        if warm is not None:
+            c.ms_set_warmstart(*warm)
+        qs, stats, xs = [c.ms_get_coarse(r)], [], []
+        for k in range(1, steps + 1):
+            c.ms_set_dirichlet(sc["dirichlet"], sc["dbc_targets"](k))
+            stats.append(c.ms_step(sc["dt"], ms.solver_defaults(warm_start=1 if warm else 0, **form)))
+            qs.append(c.ms_get_coarse(r))
+            xs.append(c.ms_get_state()[0])
+        c.close()
+        return np.array(qs), stats, xs, sc
+
+    train = [run(sd) for sd in scenes.TRAIN_SEEDS[:8]]
+    r = 12 * basis["m"]
+    X = np.array([np.concatenate([q[k - 1], q[k]]) for q, _, _, _ in train for k in range(1, len(q) - 1)])
+    Y = np.array([q[k + 1] - (2 * q[k] - q[k - 1]) for q, _, _, _ in train for k in range(1, len(q) - 1)])
+    mean = X.mean(axis=0)
+    std = np.full(X.shape[1], (X - mean).std() + 1e-30)
+    osc = np.full(Y.shape[1], Y.std() + 1e-30)
+    Xn, Yn = ((X - mean) / std).astype(np.float32), (Y / osc).astype(np.float32)
+    order = scenes.minibatch_order(len(Xn), 32, 400, seed=1)
+    params, losses, _ = ms.ms_mlp_train(dev, scenes.mlp_init(2 * r, 64, r, seed=0), Xn, Yn, order, lr=1e-3)
+    say("training samples", len(Xn), "loss", float(np.mean(losses[:20])), "->", float(np.mean(losses[-20:])))
+    assert np.mean(losses[-20:]) < np.mean(losses[:20])
+    warm = (params, mean, std, osc)
+    tot = np.zeros((2, 2), dtype=np.int64)  # [without, with] x [newton, pcg]
+    taken = 0
+    for sd in scenes.HELDOUT_SEEDS[:2]:
+        _, s0, x0, sc = run(sd)
+        _, s1, x1, _ = run(sd, warm)
+        for k in range(steps):
+            u = np.linalg.norm(x0[k] - sc["rest"])
+            assert np.linalg.norm(x1[k] - x0[k]) <= 1e-6 * u, (sd, k)
+        tot[0] += [sum(s["newton_iters"] for s in s0), sum(s["pcg_iters"] for s in s0)]
+        tot[1] += [sum(s["newton_iters"] for s in s1), sum(s["pcg_iters"] for s in s1)]
+        taken += sum(s["warm_start_used"] for s in s1)
+    say("held-out steps", 2 * steps, "learned start taken", taken, "| newton without/with", tot[0][0], tot[1][0],
+        "| pcg without/with", tot[0][1], tot[1][1], "| pcg ratio", tot[1][1] / max(1, tot[0][1]))
