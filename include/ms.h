@@ -194,6 +194,9 @@ typedef struct {
                               indices across meshes of the same shape)              */
   uint64_t seed;
   int32_t n_threads;       /* host threads (0 = hardware concurrency)                */
+  int32_t gpu_min_unknowns; /* ms_build_basis: local solves with at least this many
+                               unknowns run as dense Cholesky on the GPU (0 = none;
+                               default 4096); ms_basis_compute solves on the host */
 } ms_basis_params;
 
 void ms_solver_defaults(ms_solver_params* p);
@@ -280,10 +283,17 @@ ms_status ms_get_state(const ms_ctx* c, double* x, double* v);
  * computes its geodesics by the heat method, Sec. 3.6.1) with the jump
  * penalty and pruning, local stiffness-weighted biharmonic solves on each
  * partition's face-neighbour subdomain, clipping, partition of unity, and
- * the Dirichlet-compatible variant when Dirichlet vertices exist.  Uploads
+ * the Dirichlet-compatible variant when Dirichlet vertices exist.  Local
+ * solves with at least p->gpu_min_unknowns unknowns run as a dense blocked
+ * Cholesky on the GPU (the rest on host threads meanwhile).  Uploads
  * the basis for the two-level preconditioner and paper mode.
  * Errors: MS_E_ORDER (no mesh/material), MS_E_ARG. */
 ms_status ms_build_basis(ms_ctx* c, const ms_basis_params* p);
+
+/* The last ms_build_basis: how many local solves ran on the GPU (dense
+ * Cholesky, p->gpu_min_unknowns) and its host wall time in seconds (either
+ * pointer may be NULL). */
+ms_status ms_get_basis_stats(const ms_ctx* c, int32_t* gpu_solves, double* seconds);
 
 /* Install an externally computed basis: m handles with origins [m][3]; for
  * each vertex v the handles vhandle[vptr[v] .. vptr[v+1]) with weights vphi

@@ -290,6 +290,7 @@ void ms_basis_defaults(ms_basis_params* p) {
   p->lattice_seeding = 0;
   p->seed = 0;
   p->n_threads = 0;
+  p->gpu_min_unknowns = 4096;
 }
 
 ms_status ms_create(const ms_device* dev, ms_ctx** out) {

@@ -33,6 +33,7 @@
 #include <atomic>
 #include <cmath>
 #include <map>
+#include <mutex>
 #include <numeric>
 #include <queue>
 #include <random>
@@ -366,7 +367,11 @@ void bilaplacian_system(const Csr& L, const std::vector<double>& mv, const std::
 struct LocalResult {
   std::vector<int64_t> verts;  // global vertex ids
   std::vector<double> u;       // clipped values
+  ms_status err = MS_OK;       // device failure of a GPU solve
+  bool gpu = false;            // solved on the GPU
 };
+
+std::mutex g_gpu_solve;  // one dense GPU solve at a time (worker threads share the context's stream)
 
 // Solves the constrained biharmonic on a set of tets: u = val on `ones`
 // (value 1) and zero on `zeros` plus the internal boundary.
@@ -437,9 +442,24 @@ LocalResult local_biharmonic(const ms_ctx* c, const std::vector<int64_t>& tets, 
   bilaplacian_system(L, mv, fixed, uval, K, rhs, fidx);
   std::vector<double> u(uval);
   if (K.n > 0) {
-    EnvelopeCholesky ch;
-    ch.factor(K);
-    ch.solve(rhs);
+    bool done = false;
+    if (c->basis_gpu_min > 0 && K.n >= c->basis_gpu_min) {
+      // large subdomain: dense Cholesky on the GPU (falls back to the host
+      // factorisation if a pivot is not positive)
+      std::vector<double> x(rhs);
+      bool ok = false;
+      std::lock_guard<std::mutex> lk(g_gpu_solve);
+      R.err = dense_spd_solve(const_cast<ms_ctx*>(c), K.n, K.ptr.data(), K.idx.data(), K.val.data(), x.data(), &ok);
+      if (!R.err && ok) {
+        rhs.swap(x);
+        done = R.gpu = true;
+      }
+    }
+    if (!done && !R.err) {
+      EnvelopeCholesky ch;
+      ch.factor(K);
+      ch.solve(rhs);
+    }
     for (int r = 0; r < K.n; ++r) u[fidx[r]] = rhs[r];
   }
   R.u.resize(nl);
@@ -589,6 +609,11 @@ ms_status build_basis_host(ms_ctx* c, const ms_basis_params& P, Basis& B) {
       for (int q = next++; q < ntask; q = next++) task(order[q]);
     });
   for (auto& th : pool) th.join();
+  c->basis_gpu_solves = 0;
+  for (auto& rr : res) {
+    if (rr.err) return fail(c, rr.err, "local basis solve on the GPU failed");
+    c->basis_gpu_solves += rr.gpu ? 1 : 0;
+  }
   // 6. partition of unity
   std::vector<double> denom(n, 0.0);
   for (int i = 0; i < ntask; ++i)

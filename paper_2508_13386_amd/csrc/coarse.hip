@@ -17,6 +17,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <chrono>
 #include <map>
 #include <type_traits>
 
@@ -1016,9 +1017,20 @@ ms_status ms_build_basis(ms_ctx* c, const ms_basis_params* p) {
     ms_basis_defaults(&P);
   if (P.n_handles < 1 || P.n_handles > c->n) return fail(c, MS_E_ARG, "n_handles out of range");
   Basis B;
+  const auto t0 = std::chrono::steady_clock::now();
+  c->basis_gpu_min = std::max(0, P.gpu_min_unknowns);
   ms_status s = build_basis_host(c, P, B);
+  c->basis_gpu_min = 0;
+  c->basis_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (s) return s;
   return install_basis(c, std::move(B));
+}
+
+ms_status ms_get_basis_stats(const ms_ctx* c, int32_t* gpu_solves, double* seconds) {
+  if (!c) return MS_E_ARG;
+  if (gpu_solves) *gpu_solves = c->basis_gpu_solves;
+  if (seconds) *seconds = c->basis_seconds;
+  return MS_OK;
 }
 
 ms_status ms_set_basis(ms_ctx* c, int32_t m, const double* origins, const int64_t* vptr, const int32_t* vhandle,

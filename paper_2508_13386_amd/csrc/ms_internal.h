@@ -186,6 +186,11 @@ struct ms_ctx {
   double hs_mu = 0.0, hs_epsv = 1e-3;  // lagged friction against the half-space
   double step_h = 0.0;                 // timestep of the current step / evaluation
   ms::SelfContact sc;
+  // basis build: local solves with at least this many unknowns run on the
+  // GPU (0: host only); solves done there in the last build
+  int basis_gpu_min = 0;
+  int basis_gpu_solves = 0;
+  double basis_seconds = 0.0;  // host wall time of the last ms_build_basis
   // Dirichlet
   std::vector<int32_t> h_dbc;
   std::vector<double> h_dbc_tgt;
@@ -419,6 +424,12 @@ ms_status try_move(ms_ctx* c, double h2);
 void launch_predictor_dir(ms_ctx* c);
 ms_status record_coarse(ms_ctx* c);
 ms_status mat_build(struct ::ms_mat* A, int64_t n, const int32_t* row_ptr, const int32_t* col, const double* vals);
+
+// dense SPD solve on the GPU (dense_chol.hip): A given as full symmetric
+// CSR (n rows), rhs [n] host, overwritten by the solution; *ok false when a
+// pivot was not positive (rhs then undefined)
+ms_status dense_spd_solve(ms_ctx* c, int n, const int* ptr, const int* idx, const double* val, double* rhs,
+                          bool* ok);
 
 // self-contact (selfcontact.hip)
 ms_status sc_setup(ms_ctx* c);

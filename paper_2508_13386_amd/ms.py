@@ -60,7 +60,7 @@ class ms_basis_params(C.Structure):
     _fields_ = [("n_handles", C.c_int32), ("oversample", C.c_double), ("jump_penalty", C.c_double),
                 ("prune_ratio", C.c_double), ("prune_every", C.c_int32), ("prune_n", C.c_int32),
                 ("max_lloyd", C.c_int32), ("lattice_seeding", C.c_int32), ("seed", C.c_uint64),
-                ("n_threads", C.c_int32)]
+                ("n_threads", C.c_int32), ("gpu_min_unknowns", C.c_int32)]
 
 
 _FP = C.POINTER(C.c_float)
@@ -95,6 +95,7 @@ def lib():
             "ms_set_state": [vp, dp, dp],
             "ms_get_state": [vp, dp, dp],
             "ms_build_basis": [vp, C.POINTER(ms_basis_params)],
+            "ms_get_basis_stats": [vp, C.POINTER(i32), C.POINTER(d)],
             "ms_set_basis": [vp, i32, dp, ip, ip, dp],
             "ms_get_basis_size": [vp, C.POINTER(i32), C.POINTER(i64)],
             "ms_get_basis": [vp, dp, ip, ip, dp, ip],
@@ -298,6 +299,12 @@ class Context:
     def ms_set_basis(self, origins, vptr, vhandle, vphi):
         o, vp, vh, w = _f64(origins), np.ascontiguousarray(vptr, dtype=np.int64), _i32(vhandle), _f64(vphi)
         self._check(self.L.ms_set_basis(self.h, len(o), _ptr(o), _ptr(vp), _ptr(vh), _ptr(w)))
+
+    def ms_get_basis_stats(self):
+        """(local solves of the last ms_build_basis that ran on the GPU, its seconds)."""
+        g, t = C.c_int32(), C.c_double()
+        self._check(self.L.ms_get_basis_stats(self.h, C.byref(g), C.byref(t)))
+        return g.value, t.value
 
     def ms_get_basis(self):
         m = C.c_int32()
