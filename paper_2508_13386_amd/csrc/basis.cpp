@@ -10,7 +10,9 @@
 //     across material jumps.  (The paper computes the distance with heat
 //     diffusion and a stiffness-weighted Laplacian; the graph metric is the
 //     same idea at a fraction of the cost -- see the design notes.)
-//  3. K-means by Lloyd relaxation under that metric, initialised by
+//  3. K-means by Lloyd relaxation under that metric (the nearest-seed
+//     searches by Dijkstra on the host, or by Jacobi sweeps on the GPU when
+//     the build has a device: the same labels and distances), initialised by
 //     kmeans++ with oversampling; every prune_every iterations the prune_n
 //     smallest clusters with median volume > prune_ratio x own volume are
 //     deleted (Sec. 3.6.3).  Tets take the label of the majority of their
@@ -31,6 +33,10 @@
 #include <algorithm>
 #include <array>
 #include <atomic>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
+#include <functional>
 #include <cmath>
 #include <map>
 #include <mutex>
@@ -121,9 +127,13 @@ void voronoi(const Graph& G, const std::vector<int>& seeds, std::vector<int>& la
 struct Partitioning {
   std::vector<int> tet_label;  // [T]
   int m = 0;
+  ms_status err = MS_OK;
 };
 
-Partitioning kmeans(const ms_ctx* c, const Graph& G, const ms_basis_params& P) {
+// nearest-seed labels and distances (host Dijkstra, or the device sweeps)
+using VoronoiFn = std::function<ms_status(const std::vector<int>&, std::vector<int>&, std::vector<double>&)>;
+
+Partitioning kmeans(const ms_ctx* c, const Graph& G, const ms_basis_params& P, const VoronoiFn& vor) {
   const int64_t n = c->n, T = c->T;
   std::mt19937_64 rng(P.seed);
   const int m_target = std::max(1, P.n_handles);
@@ -163,7 +173,11 @@ Partitioning kmeans(const ms_ctx* c, const Graph& G, const ms_basis_params& P) {
     const int k0 = std::max(m_target, int(std::ceil(P.oversample * m_target)));
     seeds.push_back(int(rng() % uint64_t(n)));
     while (int(seeds.size()) < std::min<int64_t>(k0, n)) {
-      voronoi(G, seeds, label, dist);
+      if (ms_status e = vor(seeds, label, dist)) {
+        Partitioning bad;
+        bad.err = e;
+        return bad;
+      }
       double tot = 0.0;
       for (int64_t v = 0; v < n; ++v) tot += std::isfinite(dist[v]) ? dist[v] * dist[v] : 0.0;
       if (!(tot > 0)) break;
@@ -182,8 +196,12 @@ Partitioning kmeans(const ms_ctx* c, const Graph& G, const ms_basis_params& P) {
   std::vector<int> tl(T, 0);
   // Voronoi cells of the seeds, then every tet takes the majority label of
   // its vertices (ties: the nearer vertex)
+  ms_status verr = MS_OK;
   auto label_tets = [&]() {
-    voronoi(G, seeds, label, dist);
+    if (ms_status e = vor(seeds, label, dist)) {
+      verr = e;
+      return;
+    }
     for (int64_t t = 0; t < T; ++t) {
       int best = -1, bc = 0;
       double bd = 1e300;
@@ -204,6 +222,7 @@ Partitioning kmeans(const ms_ctx* c, const Graph& G, const ms_basis_params& P) {
   bool labels_stale = false;  // tl refers to a seed set that pruning has since changed
   for (int it = 0; it < std::max(1, P.max_lloyd); ++it) {
     label_tets();
+    if (verr) break;
     labels_stale = false;
     const int k = int(seeds.size());
     std::vector<double> vol(k, 0.0), cen(3 * k, 0.0);
@@ -260,7 +279,12 @@ Partitioning kmeans(const ms_ctx* c, const Graph& G, const ms_basis_params& P) {
   }
   // the Lloyd budget can end right after a pruning round: label the tets
   // of the remaining seeds before compacting
-  if (labels_stale) label_tets();
+  if (labels_stale && !verr) label_tets();
+  if (verr) {
+    Partitioning bad;
+    bad.err = verr;
+    return bad;
+  }
   // compact labels (drop empty partitions)
   std::vector<int> remap(seeds.size(), -1);
   Partitioning out;
@@ -492,8 +516,26 @@ ms_status build_basis_host(ms_ctx* c, const ms_basis_params& P, Basis& B) {
   std::nth_element(sw.begin(), sw.begin() + T / 2, sw.end());
   const double wref = sw[T / 2];
   // 2-3. geodesic K-means partitioning
+  const auto t_part = std::chrono::steady_clock::now();
   Graph G = build_graph(c, wdist, wref);
-  Partitioning part = kmeans(c, G, P);
+  // with a device, the nearest-seed searches run on it (same result)
+  DevGraph dg;
+  const bool dev_vor = c->basis_gpu_min > 0;
+  if (dev_vor) {
+    if (ms_status e = dg.upload(c, G.ptr, G.idx, G.len)) {
+      dg.release(c);
+      return fail(c, e, "basis graph upload failed");
+    }
+  }
+  auto vor = [&](const std::vector<int>& sd, std::vector<int>& lab, std::vector<double>& dst) -> ms_status {
+    if (dev_vor) return dg.voronoi(c, sd, lab, dst);
+    voronoi(G, sd, lab, dst);
+    return MS_OK;
+  };
+  Partitioning part = kmeans(c, G, P, vor);
+  if (dev_vor) dg.release(c);
+  if (part.err) return fail(c, part.err, "geodesic Voronoi on the GPU failed");
+  const double part_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_part).count();
   const int m = part.m;
   // partition geometry: volume centroid and centroid vertex
   std::vector<double> pvol(m, 0.0), pcen(3 * m, 0.0);
@@ -609,6 +651,9 @@ ms_status build_basis_host(ms_ctx* c, const ms_basis_params& P, Basis& B) {
       for (int q = next++; q < ntask; q = next++) task(order[q]);
     });
   for (auto& th : pool) th.join();
+  if (std::getenv("MS_VERBOSE"))
+    std::fprintf(stderr, "[ms] basis: partitioning %.3f s, local solves %.3f s (%d tasks)\n", part_s,
+                 std::chrono::duration<double>(std::chrono::steady_clock::now() - t_part).count() - part_s, ntask);
   c->basis_gpu_solves = 0;
   for (auto& rr : res) {
     if (rr.err) return fail(c, rr.err, "local basis solve on the GPU failed");

@@ -431,6 +431,23 @@ ms_status mat_build(struct ::ms_mat* A, int64_t n, const int32_t* row_ptr, const
 ms_status dense_spd_solve(ms_ctx* c, int n, const int* ptr, const int* idx, const double* val, double* rhs,
                           bool* ok);
 
+// multi-source geodesic Voronoi on the device (geodesic.hip): the basis
+// build's edge graph (CSR with costs) and its sweep buffers
+struct DevGraph {
+  static constexpr int kSweepChunk = 8;  // sweeps between host looks at the change flags
+  int n = 0;
+  int *ptr = nullptr, *idx = nullptr;
+  double* len = nullptr;
+  double* d[2] = {nullptr, nullptr};
+  int* l[2] = {nullptr, nullptr};
+  int *flags = nullptr, *seeds = nullptr;
+  ms_status upload(ms_ctx* c, const std::vector<int>& ptr, const std::vector<int>& idx,
+                   const std::vector<double>& cost);
+  // label [n] (index into seeds, -1 unreached) and distance of the nearest seed
+  ms_status voronoi(ms_ctx* c, const std::vector<int>& seeds, std::vector<int>& label, std::vector<double>& dist);
+  void release(ms_ctx* c);
+};
+
 // self-contact (selfcontact.hip)
 ms_status sc_setup(ms_ctx* c);
 ms_status sc_assemble(ms_ctx* c, const double* x, double h2, int prec);

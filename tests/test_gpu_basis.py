@@ -62,7 +62,29 @@ def test_gpu_basis_of_the_bench_block_matches_host():
     c.close()
     say("bench block basis: GPU solves", g, "build", round(t_gpu, 2), "s | host only", round(t_host, 2), "s")
     assert g >= 1 and g0 == 0
+    assert np.array_equal(b["part"], h["part"])  # device and host nearest-seed searches agree
     assert np.array_equal(b["vptr"], h["vptr"]) and np.array_equal(b["vhandle"], h["vhandle"])
     err = np.abs(b["vphi"] - h["vphi"]).max()
     say("max weight difference", err)
     assert err <= 2e-5
+
+
+@pytest.mark.parametrize("kw", [dict(n_handles=40, seed=1, oversample=1.5), dict(n_handles=27, lattice_seeding=1)])
+def test_device_voronoi_partitioning_equals_host(kw):
+    """kmeans++ seeding with oversampling and pruning, and lattice seeding:
+    with the nearest-seed searches on the GPU (every local solve kept on the
+    host) the basis equals the host-only build exactly."""
+    from paper_2508_13386_amd import ms
+    dev = device()
+    s = scenes.inclusion_block(12, seed=3, steps=3)
+    c = ms.context_from_scene(dev, s)
+    c.ms_build_basis(gpu_min_unknowns=10 ** 9, n_threads=2, **kw)
+    g, secs = c.ms_get_basis_stats()
+    b = c.ms_get_basis()
+    c.close()
+    h = ms.ms_basis_compute(s["rest"], s["tets"], s["E"], s["dirichlet"], n_threads=2, **kw)
+    say(kw, "partitions", b["m"], "GPU solves", g, "build", round(secs, 3), "s")
+    assert g == 0
+    assert np.array_equal(b["part"], h["part"])
+    for k in ("vptr", "vhandle", "vphi", "origins"):
+        assert np.array_equal(b[k], h[k]), k
