@@ -143,3 +143,31 @@ def test_self_contact_rejections(dev):
             c3.ms_set_self_contact(*bad)
         assert e.value.code == ms.MS_E_ARG
     c3.close()
+
+
+def test_self_contact_with_half_space_matches_oracle(dev):
+    """Both contact models at once: the lower cube is not pinned but rests on
+    a rigid half-space half a millimetre below it (inside d_hat) while the
+    upper one falls onto it; two steps against the oracle with the same
+    half-space barrier and self-contact term."""
+    from paper_2508_13386_amd import ms
+    s = scenes.stacked_cubes(N=2)
+    s["dirichlet"] = np.zeros(0, np.int32)
+    s["dbc_targets"] = lambda k: np.zeros((0, 3))
+    s["halfspace"] = dict(normal=np.array([0.0, 0.0, 1.0]), offset=-0.5e-3, dhat=2e-3,
+                          kappa=s["selfcontact"]["kappa"])
+    c = ms.context_from_scene(dev, s)
+    body = fem.Body(s["rest"], s["tets"], s["E"], s["nu"], s["rho"])
+    x, v = c.ms_get_state()
+    for k in range(1, 3):
+        st = c.ms_step(s["dt"], precision=ms.PREC_MIXED, forcing=1, pcg_eta_max=0.1, pcg_eta_min=1e-4)
+        x1, v1 = c.ms_get_state()
+        xo, _, its = newton.newton_step(body, x, v, s["dt"], s["gravity"], halfspace=s["halfspace"],
+                                        selfcontact=s["selfcontact"], x_start=x1)
+        err = e_rel(x1, xo, x)
+        say("half-space + self-contact step", k, "newton", st["newton_iters"], "oracle its", its, "e_rel", err,
+            "lowest z", float(x1[:, 2].min()))
+        assert err <= 1e-6
+        assert x1[:, 2].min() > -0.5e-3
+        x, v = x1, v1
+    c.close()
