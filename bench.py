@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=8)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--grid", type=int, default=32)
+    ap.add_argument("--projection", choices=["clamp", "abs"], default="clamp",
+                    help="projected element Hessians: negative eigenvalues clamped to zero or made positive")
     ap.add_argument("--scene", choices=["block", "gyroid", "sliding", "stacked"], default="block",
                     help="block: the heterogeneous block (--grid); gyroid: the contact scene, a gyroid-lattice "
                          "sphere voxelized at --grid^3 falling at 5 m/s onto a rigid half-space; sliding: a "
@@ -872,7 +874,8 @@ def main():
     params = ms.solver_defaults(precision=prec, preconditioner=pc, forcing=1, pcg_eta_max=a.eta_max,
                                 pcg_eta_min=a.eta_min, coarse_every=a.coarse_every, coarse_move=a.coarse_move,
                                 mixed_endgame_fp64=a.endgame_fp64, endgame_ratio=a.endgame_ratio,
-                                newton_tol=a.newton_tol, integrator=1 if a.integrator == "bdf2" else 0)
+                                newton_tol=a.newton_tol, integrator=1 if a.integrator == "bdf2" else 0,
+                                projection=1 if a.projection == "abs" else 0)
     value, elapsed, stats, states, ctx, basis_s = run(dev, s, params, a.warmup, a.steps,
                                                       handles=a.handles if pc != ms.PC_BLOCK_JACOBI else 0,
                                                       oversample=a.oversample, lattice=a.lattice)
@@ -895,7 +898,8 @@ def main():
     tparams = ms.solver_defaults(precision=prec, preconditioner=pc, forcing=1, pcg_eta_max=a.eta_max,
                                  pcg_eta_min=a.eta_min, coarse_every=a.coarse_every, coarse_move=a.coarse_move,
                                  mixed_endgame_fp64=a.endgame_fp64, endgame_ratio=a.endgame_ratio, time_kernels=1,
-                                 newton_tol=a.newton_tol, integrator=1 if a.integrator == "bdf2" else 0)
+                                 newton_tol=a.newton_tol, integrator=1 if a.integrator == "bdf2" else 0,
+                                 projection=1 if a.projection == "abs" else 0)
     tstat = ctx.ms_step(s["dt"], tparams)
     k_us, k_bytes = ctx.ms_time_kernel(0, kprec, 0)
     # slice height of the chosen layout, from the byte count of the product
@@ -959,7 +963,7 @@ def main():
                    "handles": a.handles if pc != ms.PC_BLOCK_JACOBI else None, "pcg_eta_max": a.eta_max,
                    "coarse_every": a.coarse_every, "coarse_move": a.coarse_move, "endgame_fp64": a.endgame_fp64,
                    "endgame_ratio": a.endgame_ratio, "pcg_eta_min": a.eta_min, "newton_tol": a.newton_tol,
-                   "integrator": a.integrator,
+                   "integrator": a.integrator, "projection": a.projection,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kernel_name, f"{a.scene}{a.grid}"),
@@ -972,7 +976,10 @@ def main():
                      "timed_step_solves": int(tstat["newton_iters"]),
                      "replay_avg_launch_us": r_us,
                      "replay_frac": k_bytes / (r_us * 1e-6) / 1e9 / HBM_PEAK_GBS},
-        "solver": {"newton_iters": [st["newton_iters"] for st in stats],
+        "solver": {"pcg_us_per_iteration": 1e3 * sum(st["pcg_ms"] for st in stats) /
+                   max(1, sum(st["pcg_iters"] for st in stats)),
+                   "pcg_share_of_step": sum(st["pcg_ms"] for st in stats) / max(1e-9, 1e3 * elapsed),
+                   "newton_iters": [st["newton_iters"] for st in stats],
                    "pcg_iters": [st["pcg_iters"] for st in stats],
                    "pcg_iters_fp64": [st["pcg_iters_fp64"] for st in stats],
                    "coarse_rebuilds": [st["hessian_refreshes"] for st in stats],

@@ -154,6 +154,10 @@ typedef struct {
                               + x^{t-1}) / (2h), using the previous plain step of this
                               context (implicit Euler when there is none: the first
                               step after ms_set_state)                               */
+  int32_t projection;      /* plain mode, projected element Hessians: 0 negative
+                              eigenvalues of d2Psi/dF2 clamped to zero; 1 replaced by
+                              their absolute values (both positive semi-definite; the
+                              minimiser does not depend on the choice)               */
 } ms_solver_params;
 
 /* Statistics of the last ms_step. */
@@ -178,6 +182,9 @@ typedef struct {
                                  subspace solves, total over the step                   */
   int32_t refine_iters;       /* paper mode: refinement CG iterations per Newton iteration
                                  (refine_iters, or 20/40 from the hop diameters)         */
+  double pcg_ms;              /* plain mode: host wall time inside the PCG solves (graph
+                                 replays, launch gaps and the looks at the done flag
+                                 included)                                               */
 } ms_step_stats;
 
 /* Parameters of the basis construction (Sec. 3.5-3.6).  ms_basis_defaults()

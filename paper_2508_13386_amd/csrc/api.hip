@@ -572,6 +572,7 @@ ms_status ms_step(ms_ctx* c, double dt, const ms_solver_params* pin, ms_step_sta
   if (!(P.coarse_move >= 0.0) || P.mixed_max_newton < 0)
     return fail(c, MS_E_ARG, "coarse_move and mixed_max_newton must not be negative");
   if (P.integrator != 0 && P.integrator != 1) return fail(c, MS_E_ARG, "integrator must be 0 or 1");
+  if (P.projection != 0 && P.projection != 1) return fail(c, MS_E_ARG, "projection must be 0 or 1");
   if (P.integrator == 1 && P.mode == MS_MODE_PAPER) return fail(c, MS_E_ARG, "paper mode steps with implicit Euler");
   // the learned start is judged on the implicit Euler incremental potential
   if (P.integrator == 1 && P.warm_start && c->mlp)

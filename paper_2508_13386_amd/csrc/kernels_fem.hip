@@ -5,7 +5,8 @@
 //   k_element      one thread per tet: F = sum_a x_a beta_a^T, the energy
 //                  gradient (FP64) and the 12x12 Hessian V beta^T Pi beta,
 //                  where Pi is d2Psi/dF2 (9x9) with its negative eigenvalues
-//                  clamped to zero (cyclic Jacobi in registers); stores the
+//                  clamped to zero, or replaced by their absolute values
+//                  (cyclic Jacobi in registers); stores the
 //                  10 upper 3x3 blocks per tet (FP64 or FP32)
 //   k_gather_grad  one thread per vertex, sums its incident tets' gradient
 //                  blocks in tet order and adds inertia, gravity, barrier
@@ -178,7 +179,7 @@ __global__ void __launch_bounds__(64) k_element(int64_t T, const int32_t* __rest
     jacobi9(A, Q);
     double lp[9];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) lp[k] = fmax(A[ut(k, k)], 0.0);
+    for (int k = 0; k < 9; ++k) lp[k] = project == 2 ? fabs(A[ut(k, k)]) : fmax(A[ut(k, k)], 0.0);
 #pragma unroll
     for (int i = 0; i < 9; ++i)
 #pragma unroll
@@ -534,9 +535,10 @@ void launch_predictor_dir(ms_ctx* c) {
 void launch_velocity(ms_ctx* c, double inv_h) {
   k_velocity<<<nblocks(3 * c->n, 256), 256, 0, c->stream>>>(3 * c->n, c->d_x, c->d_xt, inv_h, c->d_v);
 }
-void launch_element(ms_ctx* c, const double* x, double /*h2*/, int prec, bool hess, bool project,
+void launch_element(ms_ctx* c, const double* x, double /*h2*/, int prec, bool hess, bool proj,
                     const int32_t* tscene, const uint8_t* sproj) {
   const unsigned nb = nblocks(c->T, 64);
+  const int project = proj ? (c->proj_mode == 1 ? 2 : 1) : 0;  // 2: absolute values
   if (!hess)
     k_element<false, double><<<nb, 64, 0, c->stream>>>(c->T, c->d_tets, c->d_Dminv, c->d_vol, c->d_mu, c->d_lam, x,
                                                       c->d_ge, c->d_He, project, tscene, sproj);

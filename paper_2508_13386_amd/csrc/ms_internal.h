@@ -185,6 +185,7 @@ struct ms_ctx {
   double hs_n[3] = {0, 0, 1}, hs_off = 0, hs_dhat = 1e-3, hs_kappa = 0;
   double hs_mu = 0.0, hs_epsv = 1e-3;  // lagged friction against the half-space
   double step_h = 0.0;                 // timestep of the current step / evaluation
+  int proj_mode = 0;                   // projected element Hessians: 0 clamp, 1 absolute value
   ms::SelfContact sc;
   // basis build: local solves with at least this many unknowns run on the
   // GPU (0: host only); solves done there in the last build

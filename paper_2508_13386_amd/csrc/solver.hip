@@ -105,6 +105,11 @@ ms_status plain_step(ms_ctx* c, double dt, const ms_solver_params& P, ms_step_st
     launch_predict(c, dt);
   launch_apply_dbc(c, int64_t(c->h_dbc.size()));
   c->timing = P.time_kernels != 0;
+  c->proj_mode = P.projection == 1 ? 1 : 0;
+  struct ProjReset {  // the eval and batch paths keep the clamp
+    ms_ctx* c;
+    ~ProjReset() { c->proj_mode = 0; }
+  } proj_reset{c};
   ms_step_stats S{};
   S.min_alpha = 1.0;
   ms_status s;
@@ -138,8 +143,11 @@ ms_status plain_step(ms_ctx* c, double dt, const ms_solver_params& P, ms_step_st
     const int prec_it = (prec == MS_PREC_MIXED && endgame && P.mixed_endgame_fp64) ? MS_PREC_FP64 : prec;
     if ((s = assemble(c, c->d_x, h2, prec_it, project, true, pc, refresh))) return restore(c, s);
     int iters = 0, code = 0;
+    if ((s = sync(c))) return restore(c, s);  // the assembly's kernels are not PCG time
+    const double tp = now_ms();
     if ((s = pcg_solve(c, prec_it, pc, P.pcg_eta_max, P.pcg_eta_min, first, P.max_pcg, &iters, &code, P.forcing)))
       return restore(c, s);
+    S.pcg_ms += now_ms() - tp;
     first = false;
     S.pcg_iters += iters;
     if (prec_it == MS_PREC_FP64) {

@@ -41,7 +41,7 @@ class ms_solver_params(C.Structure):
                 ("lag_min_gap", C.c_int32), ("forcing", C.c_int32), ("endgame_ratio", C.c_double),
                 ("coarse_every", C.c_int32), ("predictor", C.c_int32), ("time_kernels", C.c_int32),
                 ("coarse_move", C.c_double), ("mixed_max_newton", C.c_int32),
-                ("mixed_endgame_fp64", C.c_int32), ("integrator", C.c_int32)]
+                ("mixed_endgame_fp64", C.c_int32), ("integrator", C.c_int32), ("projection", C.c_int32)]
 
 
 class ms_step_stats(C.Structure):
@@ -50,7 +50,7 @@ class ms_step_stats(C.Structure):
                 ("precision_escalations", C.c_int32), ("pcg_iters_fp64", C.c_int32),
                 ("pcg_solves_fp64", C.c_int32), ("energy", C.c_double), ("last_dnorm", C.c_double), ("disp_norm", C.c_double),
                 ("min_alpha", C.c_double), ("time_ms", C.c_double), ("subspace_pcg_iters", C.c_int32),
-                ("refine_iters", C.c_int32)]
+                ("refine_iters", C.c_int32), ("pcg_ms", C.c_double)]
 
     def asdict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -165,10 +165,12 @@ def test_plain_cube_step_parity(dev):
     assert np.abs(vg - vo).max() <= 1e-6 * np.abs(vo).max() + 1e-12
 
 
-def test_inclusion_block_steps_from_identical_states(dev):
+@pytest.mark.parametrize("projection", [0, 1])
+def test_inclusion_block_steps_from_identical_states(dev, projection):
     """Heterogeneous block (E contrast 1e5, nu = 0.49) at 8^3: every step
     starts from the oracle's previous state, so each step is compared from
-    identical states."""
+    identical states; with the eigenvalue clamp and with absolute values in
+    the projected Hessians (the minimiser is the same)."""
     from paper_2508_13386_amd import ms
     s = scenes.inclusion_block(8, seed=0, steps=3)
     ref = _oracle_steps(s, 3)
@@ -177,8 +179,8 @@ def test_inclusion_block_steps_from_identical_states(dev):
         c.ms_set_dirichlet(s["dirichlet"], s["dbc_targets"](k))
         vt = s["v0"] if k == 1 else ref[k - 2][2]
         c.ms_set_state(xt, vt)
-        say("inclusion_block_8 step", k)
-        st = c.ms_step(s["dt"])
+        say("inclusion_block_8 step", k, "projection", projection)
+        st = c.ms_step(s["dt"], projection=projection)
         xg, _ = c.ms_get_state()
         err = e_rel(xg, xo, xt)
         say("step", k, "e_rel", err, st)
