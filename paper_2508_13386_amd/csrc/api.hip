@@ -299,6 +299,11 @@ ms_status ms_create(const ms_device* dev, ms_ctx** out) {
   ms_ctx* c = new ms_ctx();
   c->dev = *dev;
   if (const char* v = std::getenv("MS_VERBOSE")) c->verbose = std::atoi(v);
+  // PCG launch configuration: iterations per captured graph (and per look
+  // at the done flag; even, since iterations alternate two recurrence-state
+  // buffers), and graphs or plain stream launches
+  if (const char* v = std::getenv("MS_CG_CHUNK")) c->cg_chunk = std::min(256, std::max(2, std::atoi(v))) & ~1;
+  if (const char* v = std::getenv("MS_CG_GRAPHS")) c->use_graphs = std::atoi(v) != 0;
   if (dev->hip_stream) {
     c->stream = static_cast<hipStream_t>(dev->hip_stream);
   } else {
