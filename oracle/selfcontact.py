@@ -368,6 +368,37 @@ def toi(kind, x12, p12, tol=1e-9):
 # Additive CCD (Li et al., "Codimensional Incremental Potential Contact",
 # 2021): a conservative time of impact from distance evaluations only
 # ----------------------------------------------------------------------------
+def accd_margin(kind, x12, p12, s=0.1, t_max=1.0, max_iter=100000):
+    """The smallest relative margin by which accd's run clears one of its
+    decisions (the gap test |d - s d_0| / (s d_0) and the end test
+    |t - t_max| / t_max, over its iterations): a run whose margin is at
+    round-off level can end differently under another rounding order."""
+    x = np.asarray(x12, dtype=np.float64).reshape(4, 3).copy()
+    p = np.asarray(p12, dtype=np.float64).reshape(4, 3).copy()
+    p = p - p.mean(axis=0)
+    nrm = np.sqrt((p * p).sum(axis=1))
+    lp = nrm[0] + nrm[1:].max() if kind == "pt" else max(nrm[0], nrm[1]) + max(nrm[2], nrm[3])
+    if lp == 0.0:
+        return np.inf
+    dist = pt_dist2 if kind == "pt" else ee_dist2
+    d = float(np.sqrt(float(dist(torch.tensor(x.ravel(), dtype=torch_f64)))))
+    g = s * d
+    t, tl, margin = 0.0, (1.0 - s) * d / lp, np.inf
+    for _ in range(max_iter):
+        x = x + tl * p
+        d = float(np.sqrt(float(dist(torch.tensor(x.ravel(), dtype=torch_f64)))))
+        if t > 0.0:
+            margin = min(margin, abs(d - g) / g)
+        if t > 0.0 and d < g:
+            return margin
+        t += tl
+        margin = min(margin, abs(t - t_max) / t_max)
+        if t > t_max:
+            return margin
+        tl = 0.9 * d / lp
+    return margin
+
+
 def accd(kind, x12, p12, s=0.1, t_max=1.0, max_iter=100000):
     """(hit, t): advance along x + t p in steps that cannot close more than
     90% of the current gap (the first step (1 - s) of it), given the bound

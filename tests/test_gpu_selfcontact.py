@@ -1,5 +1,7 @@
 """GPU additive CCD of self-contact primitive pairs against the oracle: the
-same algorithm step for step (times within round-off, same hit flags), and
+same algorithm step for step (times within round-off, same hit flags;
+where the two end differently the oracle's run passes one of its decision
+thresholds within a round-off margin), and
 the properties that make it a filter: never later than the exact time of
 impact, the pair still separated at the returned time."""
 import numpy as np
@@ -42,6 +44,12 @@ def test_accd_matches_oracle_and_is_conservative(dev):
         oh, ot = sc.accd(k, X[q].ravel(), P[q].ravel(), s=0.1, t_max=1.0)
         if bool(hit[q]) == oh and abs(t[q] - ot) <= 1e-9 * max(ot, 1e-300):
             same += 1
+        else:
+            # a different end is allowed only where the oracle's own run
+            # clears one of its decisions by a round-off margin
+            margin = sc.accd_margin(k, X[q].ravel(), P[q].ravel(), s=0.1, t_max=1.0)
+            say("  pair", q, k, "GPU", bool(hit[q]), t[q], "oracle", oh, ot, "decision margin", margin)
+            assert margin <= 1e-9, q
         # the filter's guarantees hold for every pair
         exact = sc.toi(k, X[q].ravel(), P[q].ravel())
         if exact is not None:
@@ -52,7 +60,6 @@ def test_accd_matches_oracle_and_is_conservative(dev):
             dt = np.sqrt(float(dist(torch.tensor((X[q] + t[q] * P[q]).ravel()))))
             assert dt >= 0.1 * d0 * (1 - 1e-9)
     say("  same as the oracle step for step:", same, "of", len(kind), "| hits", int(hit.sum()))
-    assert same >= 0.98 * len(kind)
     assert hit[0] and 0.45 <= t[0] < 0.5
     assert not hit[1] and t[1] == 1.0
 
