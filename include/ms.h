@@ -490,7 +490,11 @@ ms_status ms_mlp_forward_noalloc(const ms_device* dev, int32_t in_dim, int32_t w
  * current state, return the energy parts e4 = {K, h^2 Psi, h^2 G, h^2 B},
  * the gradient grad [n][3] (Dirichlet DOFs NOT eliminated) and, if hess
  * is non-null, the PSD-projected Hessian as BSR3 values [nnzb][3][3] in the
- * pattern returned by ms_get_pattern.  prec selects the Hessian precision. */
+ * pattern returned by ms_get_pattern.  prec selects the Hessian precision.
+ * With self-contact, B includes its barrier and grad its forces; hess holds
+ * the blocks of the mesh pattern only (couplings of vertices that share no
+ * tet sit in the contact slots, outside it).  ms_energy_difference adds the
+ * self-contact difference to dB. */
 ms_status ms_get_pattern(const ms_ctx* c, int64_t* nnzb, int32_t* row_ptr, int32_t* col);
 ms_status ms_eval(ms_ctx* c, const double* x, double dt, int32_t prec, double* e4, double* grad,
                   double* hess);
