@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--pc", choices=["jacobi", "two_level", "additive", "vcycle"], default="additive")
     ap.add_argument("--handles", type=int, default=192)
     ap.add_argument("--oversample", type=float, default=1.0, help="k-means++ seed oversampling of the basis build")
+    ap.add_argument("--jump", type=float, default=0.25,
+                    help="jump penalty of the basis partitioning (stiffness factor on material interfaces)")
     ap.add_argument("--lattice", type=int, default=0, help="1: basis seeds on a fixed lattice (no pruning)")
     ap.add_argument("--eta-max", type=float, default=0.1, help="largest PCG forcing term (Eisenstat-Walker)")
     ap.add_argument("--eta-min", type=float, default=1e-4, help="smallest PCG forcing term")
@@ -267,7 +269,7 @@ def copy_probe(mib):
 
 
 def run(dev, s, params, warmup, steps, basis=None, handles=0, timed=True, oversample=1.0, lattice=0,
-        cubature=None):
+        cubature=None, jump=0.25):
     """Runs warmup + steps timesteps; returns (timesteps/s, per-step stats,
     states after each timed step, context, basis seconds).  cubature =
     (tets, weights) integrates the elastic part of the coarse matrix by
@@ -281,7 +283,7 @@ def run(dev, s, params, warmup, steps, basis=None, handles=0, timed=True, oversa
         ctx.ms_set_basis(basis["origins"], basis["vptr"], basis["vhandle"], basis["vphi"])
     elif handles:
         t0 = time.perf_counter()
-        ctx.ms_build_basis(n_handles=handles, oversample=oversample, lattice_seeding=lattice)
+        ctx.ms_build_basis(n_handles=handles, oversample=oversample, lattice_seeding=lattice, jump_penalty=jump)
         basis_s = time.perf_counter() - t0
     if cubature is not None:
         ctx.ms_set_cubature(*cubature)
@@ -878,7 +880,7 @@ def main():
                                 projection=1 if a.projection == "abs" else 0)
     value, elapsed, stats, states, ctx, basis_s = run(dev, s, params, a.warmup, a.steps,
                                                       handles=a.handles if pc != ms.PC_BLOCK_JACOBI else 0,
-                                                      oversample=a.oversample, lattice=a.lattice)
+                                                      oversample=a.oversample, lattice=a.lattice, jump=a.jump)
     # roofline of the dominant kernel, the PCG product fused with its dots:
     # one more timestep (outside the timed region) runs with every product
     # launch bracketed by HIP events on the library's stream, inside the real
