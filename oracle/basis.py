@@ -28,6 +28,12 @@ Sec. 3.5 describe them, with the readings listed in the design notes:
     lowest-indexed partition among its tets (keeps the partition of unity);
   * handle origins are the partitions' volume centroids.
 
+Optionally (rigid_contrast > 0, an option beside the paper's construction):
+on every connected set of tets with E >= rigid_contrast x min E the rows of
+the free vertices are replaced by their average over the set, the stiff
+limit of the material-aware weights (each handle then moves a stiff
+inclusion affinely).
+
 The partitioning itself (geodesic K-means with pruning, Sec. 3.6) is taken
 as an input here.
 
@@ -100,7 +106,7 @@ def constrained_biharmonic(L, mv, verts, fixed_vals):
     return u
 
 
-def basis_weights(rest, tets, E, dbc, part):
+def basis_weights(rest, tets, E, dbc, part, rigid_contrast=0.0):
     """Weights of every handle.  Returns dict(origins [m,3], rows: list per
     vertex of (handle, phi) sorted by handle, centre [m], nbr list)."""
     rest = np.asarray(rest, dtype=np.float64)
@@ -197,6 +203,31 @@ def basis_weights(rest, tets, E, dbc, part):
     for v in range(n):
         if not denom[v] > 0.0 and not is_dbc[v] and vparts[v]:
             rows[v].append((min(vparts[v]), 1.0))
+    if rigid_contrast > 0.0:
+        # stiff limit: on each connected set of tets with E >= rigid_contrast
+        # min E (connected through shared vertices) the free vertices take the
+        # average of their rows
+        E = np.asarray(E, dtype=np.float64)
+        st = np.nonzero(E >= rigid_contrast * E.min())[0]
+        import scipy.sparse as sps
+        from scipy.sparse.csgraph import connected_components
+        tv = np.asarray(tets)[st]
+        adj = sps.coo_matrix((np.ones(3 * len(st)), (np.repeat(tv[:, 0], 3), tv[:, 1:].ravel())), shape=(n, n))
+        _, comp = connected_components(adj, directed=False)
+        in_stiff = np.zeros(n, bool)
+        in_stiff[tv.ravel()] = True
+        groups = {}
+        for v in range(n):
+            if in_stiff[v] and not is_dbc[v]:
+                groups.setdefault(comp[v], []).append(v)
+        for vs in groups.values():
+            acc = {}
+            for v in vs:
+                for i, w in rows[v]:
+                    acc[i] = acc.get(i, 0.0) + w
+            avg = sorted((i, w / len(vs)) for i, w in acc.items())
+            for v in vs:
+                rows[v] = list(avg)
     for v in range(n):
         rows[v].sort()
     return dict(origins=cen, rows=rows, centre=centre, nbr=[sorted(s) for s in nbr],
