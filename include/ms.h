@@ -204,6 +204,12 @@ typedef struct {
   int32_t gpu_min_unknowns; /* ms_build_basis: local solves with at least this many
                                unknowns run as dense Cholesky on the GPU (0 = none;
                                default 4096); ms_basis_compute solves on the host */
+  double rigid_contrast;   /* > 0: on every connected set of tets with E >=
+                              rigid_contrast x min E (tets sharing a vertex are
+                              connected) the weights of the free vertices are replaced
+                              by their average over the set, so each handle moves the
+                              set affinely (the stiff limit of the material-aware
+                              weights; partition of unity kept); 0 = off (default) */
 } ms_basis_params;
 
 void ms_solver_defaults(ms_solver_params* p);

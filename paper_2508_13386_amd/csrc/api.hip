@@ -291,6 +291,7 @@ void ms_basis_defaults(ms_basis_params* p) {
   p->seed = 0;
   p->n_threads = 0;
   p->gpu_min_unknowns = 4096;
+  p->rigid_contrast = 0.0;
 }
 
 ms_status ms_create(const ms_device* dev, ms_ctx** out) {

@@ -677,6 +677,38 @@ ms_status build_basis_host(ms_ctx* c, const ms_basis_params& P, Basis& B) {
   for (int64_t v = 0; v < n; ++v)
     if (!(denom[v] > 0.0) && !is_dbc[v] && !vparts[v].empty())
       rows[v].push_back({*std::min_element(vparts[v].begin(), vparts[v].end()), 1.0});
+  // Optional stiff limit: constant weights on each connected set of stiff
+  // tets (the average over its free vertices, in vertex order), so that
+  // every handle moves a stiff inclusion affinely instead of bending it.
+  if (P.rigid_contrast > 0.0) {
+    std::vector<int64_t> root(n);
+    std::iota(root.begin(), root.end(), int64_t(0));
+    auto find = [&](int64_t a) {
+      while (root[a] != a) a = root[a] = root[root[a]];
+      return a;
+    };
+    std::vector<char> in_stiff(n, 0);
+    for (int64_t t = 0; t < T; ++t) {
+      if (!(c->h_E[t] >= P.rigid_contrast * emin)) continue;
+      const int32_t* tv = &c->h_tets[4 * t];
+      for (int a = 0; a < 4; ++a) in_stiff[tv[a]] = 1;
+      for (int a = 1; a < 4; ++a) {
+        const int64_t x = find(tv[0]), y = find(tv[a]);
+        if (x != y) root[std::max(x, y)] = std::min(x, y);
+      }
+    }
+    std::map<int64_t, std::vector<int64_t>> groups;  // root -> free vertices, ascending
+    for (int64_t v = 0; v < n; ++v)
+      if (in_stiff[v] && !is_dbc[v]) groups[find(v)].push_back(v);
+    for (auto& kv : groups) {
+      std::map<int, double> sum;
+      for (int64_t v : kv.second)
+        for (auto& pr : rows[v]) sum[pr.first] += pr.second;
+      std::vector<std::pair<int, double>> avg;
+      for (auto& hw : sum) avg.push_back({hw.first, hw.second / double(kv.second.size())});
+      for (int64_t v : kv.second) rows[v] = avg;
+    }
+  }
   B.m = m;
   B.origins = pcen;
   B.vptr.assign(n + 1, 0);

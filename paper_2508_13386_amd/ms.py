@@ -60,7 +60,7 @@ class ms_basis_params(C.Structure):
     _fields_ = [("n_handles", C.c_int32), ("oversample", C.c_double), ("jump_penalty", C.c_double),
                 ("prune_ratio", C.c_double), ("prune_every", C.c_int32), ("prune_n", C.c_int32),
                 ("max_lloyd", C.c_int32), ("lattice_seeding", C.c_int32), ("seed", C.c_uint64),
-                ("n_threads", C.c_int32), ("gpu_min_unknowns", C.c_int32)]
+                ("n_threads", C.c_int32), ("gpu_min_unknowns", C.c_int32), ("rigid_contrast", C.c_double)]
 
 
 _FP = C.POINTER(C.c_float)

@@ -186,3 +186,64 @@ def test_host_basis_when_pruning_meets_the_lloyd_budget(m):
     free = np.ones(len(s["rest"]), bool)
     free[s["dirichlet"]] = False
     assert sums[free].max() <= 1 + 1e-12
+
+
+def test_stiff_limit_weights_are_constant_on_stiff_sets_and_keep_unity():
+    """rigid_contrast: on every connected set of stiff tets the free
+    vertices share one row (the set's average), the rows still sum to one
+    where they did, stay non-negative, and the basis still reproduces affine
+    fields (every handle carrying the same affine map moves every vertex by
+    that map)."""
+    s = scenes.inclusion_block(8, seed=2, steps=1)
+    rest, tets, E = s["rest"], s["tets"], s["E"]
+    d = np.zeros(0, np.int32)
+    part = _octant_partition(rest, tets, 2)
+    base = basis.basis_weights(rest, tets, E, d, part)
+    out = basis.basis_weights(rest, tets, E, d, part, rigid_contrast=1e3)
+    stiff = np.nonzero(E >= 1e3 * E.min())[0]
+    import scipy.sparse as sps
+    from scipy.sparse.csgraph import connected_components
+    n = len(rest)
+    tv = tets[stiff]
+    adj = sps.coo_matrix((np.ones(3 * len(stiff)), (np.repeat(tv[:, 0], 3), tv[:, 1:].ravel())), shape=(n, n))
+    _, comp = connected_components(adj, directed=False)
+    sv = np.unique(tv)
+    assert len(sv) > 0
+    for c in np.unique(comp[sv]):
+        vs = sv[comp[sv] == c]
+        first = out["rows"][vs[0]]
+        for v in vs:
+            assert out["rows"][v] == first
+        # the average of the paper's rows over the set
+        acc = {}
+        for v in vs:
+            for i, w in base["rows"][v]:
+                acc[i] = acc.get(i, 0.0) + w
+        assert [i for i, _ in first] == sorted(acc)
+        assert np.allclose([w for _, w in first], [acc[i] / len(vs) for i in sorted(acc)], rtol=1e-14, atol=0)
+    for v in range(n):
+        ws = [w for _, w in out["rows"][v]]
+        assert all(w >= 0 for w in ws)
+        assert abs(sum(ws) - sum(w for _, w in base["rows"][v])) <= 1e-12 or v in set(sv)
+        if v in set(sv):
+            assert abs(sum(ws) - 1.0) <= 1e-12
+    # affine reproduction: x -> A x + b on every handle
+    A = np.array([[1.1, 0.2, -0.1], [0.05, 0.9, 0.3], [-0.2, 0.1, 1.2]])
+    b = np.array([0.3, -0.2, 0.1])
+    for v in range(n):
+        y = sum(w * (A @ (rest[v] - out["origins"][i]) + A @ out["origins"][i] + b) for i, w in out["rows"][v])
+        assert np.allclose(y, A @ rest[v] + b, atol=1e-12)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_host_basis_stiff_limit_matches_oracle():
+    from paper_2508_13386_amd import ms
+    s = scenes.inclusion_block(8, seed=2, steps=1)
+    d = s["dirichlet"]
+    b = ms.ms_basis_compute(s["rest"], s["tets"], s["E"], d, n_handles=10, seed=5, n_threads=2, rigid_contrast=1e3)
+    out = basis.basis_weights(s["rest"], s["tets"], s["E"], d, b["part"], rigid_contrast=1e3)
+    for v in range(len(s["rest"])):
+        lib_row = [(int(b["vhandle"][k]), float(b["vphi"][k])) for k in range(b["vptr"][v], b["vptr"][v + 1])]
+        orc_row = out["rows"][v]
+        assert [i for i, _ in lib_row] == [i for i, _ in orc_row], v
+        assert np.allclose([p for _, p in lib_row], [p for _, p in orc_row], rtol=0.0, atol=2e-5), v
