@@ -55,6 +55,9 @@ def parse():
     ap.add_argument("--pc", choices=["jacobi", "two_level", "additive", "vcycle"], default="additive")
     ap.add_argument("--handles", type=int, default=192)
     ap.add_argument("--oversample", type=float, default=1.0, help="k-means++ seed oversampling of the basis build")
+    ap.add_argument("--rigid", type=float, default=1e3,
+                    help="basis weights constant on connected sets of tets with E >= RIGID x min E (0: off; "
+                         "the heterogeneous block's inclusions are 1e5 x its matrix)")
     ap.add_argument("--jump", type=float, default=0.25,
                     help="jump penalty of the basis partitioning (stiffness factor on material interfaces)")
     ap.add_argument("--lattice", type=int, default=0, help="1: basis seeds on a fixed lattice (no pruning)")
@@ -269,7 +272,7 @@ def copy_probe(mib):
 
 
 def run(dev, s, params, warmup, steps, basis=None, handles=0, timed=True, oversample=1.0, lattice=0,
-        cubature=None, jump=0.25):
+        cubature=None, jump=0.25, rigid=0.0):
     """Runs warmup + steps timesteps; returns (timesteps/s, per-step stats,
     states after each timed step, context, basis seconds).  cubature =
     (tets, weights) integrates the elastic part of the coarse matrix by
@@ -283,7 +286,8 @@ def run(dev, s, params, warmup, steps, basis=None, handles=0, timed=True, oversa
         ctx.ms_set_basis(basis["origins"], basis["vptr"], basis["vhandle"], basis["vphi"])
     elif handles:
         t0 = time.perf_counter()
-        ctx.ms_build_basis(n_handles=handles, oversample=oversample, lattice_seeding=lattice, jump_penalty=jump)
+        ctx.ms_build_basis(n_handles=handles, oversample=oversample, lattice_seeding=lattice, jump_penalty=jump,
+                           rigid_contrast=rigid)
         basis_s = time.perf_counter() - t0
     if cubature is not None:
         ctx.ms_set_cubature(*cubature)
@@ -880,7 +884,8 @@ def main():
                                 projection=1 if a.projection == "abs" else 0)
     value, elapsed, stats, states, ctx, basis_s = run(dev, s, params, a.warmup, a.steps,
                                                       handles=a.handles if pc != ms.PC_BLOCK_JACOBI else 0,
-                                                      oversample=a.oversample, lattice=a.lattice, jump=a.jump)
+                                                      oversample=a.oversample, lattice=a.lattice, jump=a.jump,
+                                                      rigid=a.rigid)
     # roofline of the dominant kernel, the PCG product fused with its dots:
     # one more timestep (outside the timed region) runs with every product
     # launch bracketed by HIP events on the library's stream, inside the real
@@ -966,6 +971,7 @@ def main():
                    "coarse_every": a.coarse_every, "coarse_move": a.coarse_move, "endgame_fp64": a.endgame_fp64,
                    "endgame_ratio": a.endgame_ratio, "pcg_eta_min": a.eta_min, "newton_tol": a.newton_tol,
                    "integrator": a.integrator, "projection": a.projection,
+                   "basis": {"jump_penalty": a.jump, "oversample": a.oversample, "rigid_contrast": a.rigid},
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kernel_name, f"{a.scene}{a.grid}"),
