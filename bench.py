@@ -62,14 +62,16 @@ def parse():
                     help="jump penalty of the basis partitioning (stiffness factor on material interfaces)")
     ap.add_argument("--lattice", type=int, default=0, help="1: basis seeds on a fixed lattice (no pruning)")
     ap.add_argument("--eta-max", type=float, default=0.1, help="largest PCG forcing term (Eisenstat-Walker)")
-    ap.add_argument("--eta-min", type=float, default=1e-4, help="smallest PCG forcing term")
+    ap.add_argument("--eta-min", type=float, default=None,
+                    help="smallest PCG forcing term (default 1e-3 for the block, 1e-4 for the other workloads)")
     ap.add_argument("--coarse-every", type=int, default=1,
                     help="rebuild U^T H U and its inverse every this many Newton iterations (0: once per step)")
     ap.add_argument("--endgame-fp64", type=int, default=1, help="mixed precision: FP64 Hessian in the Newton endgame")
     ap.add_argument("--newton-tol", type=float, default=1e-9,
                     help="Newton stop: a full step with ||d|| <= newton_tol * ||x - x^t||")
-    ap.add_argument("--endgame-ratio", type=float, default=1e-3,
-                    help="endgame once ||d|| <= ratio * ||x - x^t|| (exact Hessian; FP64 with --endgame-fp64)")
+    ap.add_argument("--endgame-ratio", type=float, default=None,
+                    help="endgame once ||d|| <= ratio * ||x - x^t|| (exact Hessian; FP64 with --endgame-fp64); "
+                         "default 3e-2 for the block, 1e-3 for the other workloads")
     ap.add_argument("--no-accuracy", action="store_true",
                     help="skip the per-step error check against tightly converged FP64 steps")
     ap.add_argument("--coarse-move", type=float, default=0.2,
@@ -108,7 +110,14 @@ def parse():
                          "into their last N and the rest")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (scale for HBM byte counters)")
-    return ap.parse_args()
+    a = ap.parse_args()
+    # policy of the benchmarked block; the other workloads keep the policy they were measured with
+    block = a.workload == "block32" and a.scene == "block"
+    if a.eta_min is None:
+        a.eta_min = 1e-3 if block else 1e-4
+    if a.endgame_ratio is None:
+        a.endgame_ratio = 3e-2 if block else 1e-3
+    return a
 
 
 def cpu_baseline(scene="block", grid=32, n_tets=None):
