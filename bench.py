@@ -53,7 +53,8 @@ def parse():
     ap.add_argument("--integrator", choices=["euler", "bdf2"], default="euler",
                     help="implicit Euler or BDF2 (first step implicit Euler) for every form in the run")
     ap.add_argument("--pc", choices=["jacobi", "two_level", "additive", "vcycle"], default="additive")
-    ap.add_argument("--handles", type=int, default=192)
+    ap.add_argument("--handles", type=int, default=None,
+                    help="basis handles (176 on the benchmarked block, else 192)")
     ap.add_argument("--oversample", type=float, default=1.0, help="k-means++ seed oversampling of the basis build")
     ap.add_argument("--rigid", type=float, default=1e3,
                     help="basis weights constant on connected sets of tets with E >= RIGID x min E (0: off; "
@@ -114,9 +115,11 @@ def parse():
     # policy of the benchmarked block; the other workloads keep the policy they were measured with
     block = a.workload == "block32" and a.scene == "block"
     if a.eta_min is None:
-        a.eta_min = 1e-3 if block else 1e-4
+        a.eta_min = 3e-2 if block else 1e-4
     if a.endgame_ratio is None:
-        a.endgame_ratio = 3e-2 if block else 1e-3
+        a.endgame_ratio = 1e-1 if block else 1e-3
+    if a.handles is None:
+        a.handles = 176 if block else 192
     return a
 
 
