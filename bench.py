@@ -67,7 +67,8 @@ def parse():
                     help="smallest PCG forcing term (default 1e-3 for the block, 1e-4 for the other workloads)")
     ap.add_argument("--coarse-every", type=int, default=1,
                     help="rebuild U^T H U and its inverse every this many Newton iterations (0: once per step)")
-    ap.add_argument("--endgame-fp64", type=int, default=1, help="mixed precision: FP64 Hessian in the Newton endgame")
+    ap.add_argument("--endgame-fp64", type=int, default=None,
+                    help="mixed precision: FP64 Hessian in the Newton endgame (0 on the benchmarked block, else 1)")
     ap.add_argument("--newton-tol", type=float, default=1e-9,
                     help="Newton stop: a full step with ||d|| <= newton_tol * ||x - x^t||")
     ap.add_argument("--endgame-ratio", type=float, default=None,
@@ -120,6 +121,8 @@ def parse():
         a.endgame_ratio = 1e-1 if block else 1e-3
     if a.handles is None:
         a.handles = 176 if block else 192
+    if a.endgame_fp64 is None:
+        a.endgame_fp64 = 0 if block else 1
     return a
 
 
