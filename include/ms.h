@@ -158,6 +158,15 @@ typedef struct {
                               eigenvalues of d2Psi/dF2 clamped to zero; 1 replaced by
                               their absolute values (both positive semi-definite; the
                               minimiser does not depend on the choice)               */
+  int32_t smoother;        /* plain mode, block-Jacobi or additive two-level PCG, no
+                              self-contact: the block part of the preconditioner.
+                              0: inverses of the 3x3 vertex blocks of H (Sec. 3.7.1's
+                              block-Jacobi); 1: exact inverses of the 24 x 24 diagonal
+                              blocks of H over vertex aggregates of at most 8 (rest
+                              positions binned into cubes of twice the shortest edge:
+                              2 x 2 x 2 vertices on a regular grid), formed in FP64
+                              each Newton iteration and applied in the Hessian's
+                              precision.  MS_E_ARG otherwise; batched steps take 0    */
 } ms_solver_params;
 
 /* Statistics of the last ms_step. */

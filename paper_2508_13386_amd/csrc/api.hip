@@ -126,8 +126,13 @@ void set_coarse_f32(ms_ctx* c, bool on) {
 ms_status pcg_solve(ms_ctx* c, int prec, int pc, double eta_max, double eta_min, bool first, int max_it, int* iters,
                     int* code, int forcing) {
   launch_cg_init(c, prec, eta_max, eta_min, first, max_it, forcing);
+  if (c->smoother) launch_agg_apply(c, prec);  // u = B^-1 r in place of the 3x3 blocks' S r
   if (pc == MS_PC_TWO_LEVEL) launch_coarse_start(c, prec);
   launch_precond_apply(c, prec, pc);
+  if (c->cg_graph_smoother != c->smoother) {  // graphs hold the update kernel of one smoother
+    destroy_graphs(c);
+    c->cg_graph_smoother = c->smoother;
+  }
   const int chunk = c->cg_chunk;
   hipGraphExec_t& ge = c->cg_graph[prec][pc];
   if (!ge && c->use_graphs) {
@@ -200,6 +205,7 @@ ms_status assemble(ms_ctx* c, const double* x, double h2, int prec, bool project
       launch_block_jacobi_l1(c, prec);
     else
       launch_block_jacobi(c, prec);
+    if (c->smoother) launch_agg_invert(c, prec);
   }
   return MS_OK;
 }
@@ -275,6 +281,7 @@ void ms_solver_defaults(ms_solver_params* p) {
   p->mixed_max_newton = 20;
   p->mixed_endgame_fp64 = 0;
   p->integrator = 0;
+  p->smoother = 0;
 }
 
 void ms_basis_defaults(ms_basis_params* p) {
@@ -579,6 +586,12 @@ ms_status ms_step(ms_ctx* c, double dt, const ms_solver_params* pin, ms_step_sta
     return fail(c, MS_E_ARG, "coarse_move and mixed_max_newton must not be negative");
   if (P.integrator != 0 && P.integrator != 1) return fail(c, MS_E_ARG, "integrator must be 0 or 1");
   if (P.projection != 0 && P.projection != 1) return fail(c, MS_E_ARG, "projection must be 0 or 1");
+  if (P.smoother != 0 && P.smoother != 1) return fail(c, MS_E_ARG, "smoother must be 0 or 1");
+  if (P.smoother == 1 && (P.mode != MS_MODE_PLAIN || c->sc.on ||
+                          (P.preconditioner != MS_PC_BLOCK_JACOBI && P.preconditioner != MS_PC_TWO_LEVEL_ADDITIVE)))
+    return fail(c, MS_E_ARG,
+                "the aggregate smoother runs in plain mode with block-Jacobi or additive two-level PCG, "
+                "without self-contact");
   if (P.integrator == 1 && P.mode == MS_MODE_PAPER) return fail(c, MS_E_ARG, "paper mode steps with implicit Euler");
   // the learned start is judged on the implicit Euler incremental potential
   if (P.integrator == 1 && P.warm_start && c->mlp)

@@ -934,6 +934,7 @@ ms_status batch_params(ms_ctx* c0, double dt, const ms_solver_params* pin, ms_so
                 "batched steps support plain implicit-Euler mode with block-Jacobi or additive two-level PCG");
   if (P.precision == MS_PREC_MIXED && P.mixed_endgame_fp64)
     return fail(c0, MS_E_ARG, "batched steps keep one Hessian precision per step (no FP64 endgame)");
+  if (P.smoother != 0) return fail(c0, MS_E_ARG, "batched steps smooth with 3x3 vertex blocks (smoother 0)");
   return MS_OK;
 }
 

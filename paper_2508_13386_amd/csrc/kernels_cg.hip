@@ -522,7 +522,10 @@ void launch_cg_iteration(ms_ctx* c, int prec, int pc, int parity, hipEvent_t ev0
     else
       go(k_cg_spmv<float, S>, (const float*)c->d_vals32);
   });
-  launch_cg_update(c, prec, parity);
+  if (c->smoother)
+    launch_cg_update_agg(c, prec, parity);
+  else
+    launch_cg_update(c, prec, parity);
   launch_precond_apply(c, prec, pc);
 }
 

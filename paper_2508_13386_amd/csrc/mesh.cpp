@@ -98,6 +98,7 @@ ms_status build_pattern(ms_ctx* c) {
   const int64_t n = c->n, T = c->T;
   Pattern& P = c->pat;
   P.n = n;
+  c->agg.built = false;  // its block slots follow the pattern
   // adjacency (including self), sorted per row
   std::vector<std::vector<int32_t>> adj(n);
   for (int64_t v = 0; v < n; ++v) adj[v].push_back(int32_t(v));

@@ -186,6 +186,18 @@ struct ms_ctx {
   double hs_mu = 0.0, hs_epsv = 1e-3;  // lagged friction against the half-space
   double step_h = 0.0;                 // timestep of the current step / evaluation
   int proj_mode = 0;                   // projected element Hessians: 0 clamp, 1 absolute value
+  int smoother = 0;                    // PCG block smoother of this step: 0 3x3 vertex blocks, 1 aggregates
+  int cg_graph_smoother = 0;           // smoother the captured PCG graphs were recorded with
+  // vertex aggregates of the aggregate block-Jacobi smoother (built from the
+  // rest positions and the mesh pattern; stale once the pattern is rebuilt)
+  struct Aggregates {
+    bool built = false;
+    int nagg = 0;
+    int32_t* d_vert = nullptr;  // [nagg][kAggV] vertex ids, -1 padding
+    int32_t* d_slot = nullptr;  // [nagg][kAggV][kAggV] slot of block (i, j), -1 none
+    double* d_inv64 = nullptr;  // [nagg][kAggN][kAggN] inverse of the aggregate's diagonal block
+    float* d_inv32 = nullptr;   // FP32 copy (mixed precision)
+  } agg;
   ms::SelfContact sc;
   // basis build: local solves with at least this many unknowns run on the
   // GPU (0: host only); solves done there in the last build
@@ -377,6 +389,12 @@ inline bool two_level(int pc) {
   return pc == MS_PC_TWO_LEVEL || pc == MS_PC_TWO_LEVEL_ADDITIVE || pc == MS_PC_TWO_LEVEL_VCYCLE;
 }
 constexpr int kUpdBlock = 256;  // vertices per PCG update block
+constexpr int kAggV = 8;                // vertices per aggregate (at most)
+constexpr int kAggN = 3 * kAggV;        // DOFs per aggregate
+ms_status build_aggregates(ms_ctx* c);
+void launch_agg_invert(ms_ctx* c, int prec);
+void launch_agg_apply(ms_ctx* c, int prec);
+void launch_cg_update_agg(ms_ctx* c, int prec, int parity);
 void launch_coarse_gemv(ms_ctx* c, int prec, const double* scal);
 void launch_prolong_add(ms_ctx* c, double* target, const double* scal);
 void launch_diag_barrier(ms_ctx* c, int prec, void* vals, const double* x, double h2, double sign);

@@ -106,10 +106,18 @@ ms_status plain_step(ms_ctx* c, double dt, const ms_solver_params& P, ms_step_st
   launch_apply_dbc(c, int64_t(c->h_dbc.size()));
   c->timing = P.time_kernels != 0;
   c->proj_mode = P.projection == 1 ? 1 : 0;
-  struct ProjReset {  // the eval and batch paths keep the clamp
+  c->smoother = P.smoother == 1 ? 1 : 0;
+  struct ProjReset {  // the eval and batch paths keep the clamp and the 3x3 blocks
     ms_ctx* c;
-    ~ProjReset() { c->proj_mode = 0; }
+    ~ProjReset() {
+      c->proj_mode = 0;
+      c->smoother = 0;
+    }
   } proj_reset{c};
+  if (c->smoother) {
+    ms_status sa = build_aggregates(c);
+    if (sa) return restore(c, sa);
+  }
   ms_step_stats S{};
   S.min_alpha = 1.0;
   ms_status s;

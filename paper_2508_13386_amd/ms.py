@@ -41,7 +41,8 @@ class ms_solver_params(C.Structure):
                 ("lag_min_gap", C.c_int32), ("forcing", C.c_int32), ("endgame_ratio", C.c_double),
                 ("coarse_every", C.c_int32), ("predictor", C.c_int32), ("time_kernels", C.c_int32),
                 ("coarse_move", C.c_double), ("mixed_max_newton", C.c_int32),
-                ("mixed_endgame_fp64", C.c_int32), ("integrator", C.c_int32), ("projection", C.c_int32)]
+                ("mixed_endgame_fp64", C.c_int32), ("integrator", C.c_int32), ("projection", C.c_int32),
+                ("smoother", C.c_int32)]
 
 
 class ms_step_stats(C.Structure):
