@@ -67,6 +67,9 @@ def parse():
                     help="smallest PCG forcing term (default 1e-3 for the block, 1e-4 for the other workloads)")
     ap.add_argument("--coarse-every", type=int, default=1,
                     help="rebuild U^T H U and its inverse every this many Newton iterations (0: once per step)")
+    ap.add_argument("--smoother", type=int, default=None, choices=[0, 1],
+                    help="block part of the preconditioner: 0 3x3 vertex blocks, 1 vertex aggregates of up to 8 "
+                         "(1 on the benchmarked block, else 0)")
     ap.add_argument("--endgame-fp64", type=int, default=None,
                     help="mixed precision: FP64 Hessian in the Newton endgame (0 on the benchmarked block, else 1)")
     ap.add_argument("--newton-tol", type=float, default=1e-9,
@@ -123,6 +126,8 @@ def parse():
         a.handles = 176 if block else 192
     if a.endgame_fp64 is None:
         a.endgame_fp64 = 0 if block else 1
+    if a.smoother is None:
+        a.smoother = 1 if block else 0
     return a
 
 
@@ -896,7 +901,7 @@ def main():
                                 pcg_eta_min=a.eta_min, coarse_every=a.coarse_every, coarse_move=a.coarse_move,
                                 mixed_endgame_fp64=a.endgame_fp64, endgame_ratio=a.endgame_ratio,
                                 newton_tol=a.newton_tol, integrator=1 if a.integrator == "bdf2" else 0,
-                                projection=1 if a.projection == "abs" else 0)
+                                projection=1 if a.projection == "abs" else 0, smoother=a.smoother)
     value, elapsed, stats, states, ctx, basis_s = run(dev, s, params, a.warmup, a.steps,
                                                       handles=a.handles if pc != ms.PC_BLOCK_JACOBI else 0,
                                                       oversample=a.oversample, lattice=a.lattice, jump=a.jump,
@@ -921,7 +926,7 @@ def main():
                                  pcg_eta_min=a.eta_min, coarse_every=a.coarse_every, coarse_move=a.coarse_move,
                                  mixed_endgame_fp64=a.endgame_fp64, endgame_ratio=a.endgame_ratio, time_kernels=1,
                                  newton_tol=a.newton_tol, integrator=1 if a.integrator == "bdf2" else 0,
-                                 projection=1 if a.projection == "abs" else 0)
+                                 projection=1 if a.projection == "abs" else 0, smoother=a.smoother)
     tstat = ctx.ms_step(s["dt"], tparams)
     k_us, k_bytes = ctx.ms_time_kernel(0, kprec, 0)
     # slice height of the chosen layout, from the byte count of the product
@@ -957,7 +962,7 @@ def main():
             # same basis: isolates what the mixed-precision form gains
             p64 = ms.solver_defaults(precision=ms.PREC_FP64, preconditioner=pc, forcing=1, pcg_eta_max=a.eta_max,
                                      pcg_eta_min=a.eta_min, coarse_every=a.coarse_every, coarse_move=a.coarse_move,
-                                     integrator=1 if a.integrator == "bdf2" else 0)
+                                     integrator=1 if a.integrator == "bdf2" else 0, smoother=a.smoother)
             fv, _, fstats, fstates, fctx, _ = run(dev, s, p64, a.warmup, a.steps, basis=basis)
             fctx.close()
             ref["fp64_same_preconditioner"] = {
@@ -984,6 +989,7 @@ def main():
                    "precision": a.precision, "preconditioner": a.pc,
                    "handles": a.handles if pc != ms.PC_BLOCK_JACOBI else None, "pcg_eta_max": a.eta_max,
                    "coarse_every": a.coarse_every, "coarse_move": a.coarse_move, "endgame_fp64": a.endgame_fp64,
+                   "smoother": ["3x3 vertex blocks", "vertex aggregates"][a.smoother],
                    "endgame_ratio": a.endgame_ratio, "pcg_eta_min": a.eta_min, "newton_tol": a.newton_tol,
                    "integrator": a.integrator, "projection": a.projection,
                    "basis": {"jump_penalty": a.jump, "oversample": a.oversample, "rigid_contrast": a.rigid},
