@@ -208,10 +208,14 @@ ms_status plain_step(ms_ctx* c, double dt, const ms_solver_params& P, ms_step_st
     if (dnorm <= P.endgame_ratio * ref) endgame = true;
     // Mixed precision: a timestep that has not converged after
     // mixed_max_newton iterations (the FP32 Hessian can limit the
-    // contraction on ill-conditioned systems) is finished in FP64.
+    // contraction on ill-conditioned systems) is finished in FP64, with the
+    // FP64 coarse inverse too: rounded to FP32 the inverse of an
+    // ill-conditioned coarse matrix can lose positive definiteness, which
+    // the continuation must not inherit.
     if (prec == MS_PREC_MIXED && P.mixed_max_newton > 0 && it + 1 >= P.mixed_max_newton) {
       prec = MS_PREC_FP64;
       escalated = true;
+      set_coarse_f32(c, false);  // FP64 throughout, the coarse inverse included
       ++S.precision_escalations;
       if (c->verbose) std::fprintf(stderr, "[ms] it %d: continuing in FP64\n", it);
     }
