@@ -160,8 +160,9 @@ typedef struct {
                               minimiser does not depend on the choice)               */
   int32_t smoother;        /* plain mode, block-Jacobi or additive two-level PCG, no
                               self-contact: the block part of the preconditioner.
-                              0: inverses of the 3x3 vertex blocks of H (Sec. 3.7.1's
-                              block-Jacobi); 1: exact inverses of the 24 x 24 diagonal
+                              0: inverses of the 3x3 vertex blocks of H (block-Jacobi,
+                              as the paper's subspace solves use per handle, Sec.
+                              3.7.1); 1: exact inverses of the 24 x 24 diagonal
                               blocks of H over vertex aggregates of at most 8 (rest
                               positions binned into cubes of twice the shortest edge:
                               2 x 2 x 2 vertices on a regular grid), formed in FP64

@@ -1,5 +1,6 @@
 // Aggregate block-Jacobi smoother for the Newton PCG (an option beside the
-// 3x3 vertex blocks of Sec. 3.7.1's block-Jacobi preconditioner).
+// 3x3 vertex blocks of the full-space block-Jacobi preconditioner; the
+// paper's subspace solves use block-Jacobi per handle, Sec. 3.7.1).
 //
 // The stiff-contrast, nearly incompressible blocks this solver targets keep
 // strong couplings between neighbouring vertices that 3x3 vertex blocks
