@@ -345,6 +345,20 @@ ms_status ms_basis_get(const ms_basis* b, int32_t* m, int64_t* nnz, double* orig
                        int32_t* vhandle, double* vphi, int32_t* part);
 void ms_basis_free(ms_basis* b);
 
+/* Vertex aggregates of the aggregate block-Jacobi smoother (the `smoother`
+ * = 1 solver option), host-only: the rule ms_step applies to a context's
+ * mesh.  rest_xyz [n][3]; the vertex graph as CSR (row_ptr [n+1], col
+ * [row_ptr[n]], entries 0..n-1, self entries allowed).  Positions are binned
+ * into cubes of twice the graph's shortest edge, offset by half an edge (a
+ * regular grid gives 2 x 2 x 2 vertices), bins ordered by (z, y, x) and
+ * each split in vertex order into groups of at most 8.  *n_agg receives the
+ * aggregate count; vert (caller-owned, cap entries; cap = 0 and vert = NULL
+ * to query) receives 8 entries per aggregate, vertex ids padded with -1,
+ * the first cap of them.  MS_E_ARG on null pointers or n < 1,
+ * MS_E_NONFINITE on a non-finite position, MS_E_MESH on a malformed graph. */
+ms_status ms_aggregates_compute(int64_t n, const double* rest_xyz, const int32_t* row_ptr, const int32_t* col,
+                                int64_t cap, int32_t* vert, int64_t* n_agg);
+
 /* Modal moment-fitting cubature (Sec. 3.8, modal moment fitting and its
  * solver; Alg. 3), host-only (no device involved).  Per partition p
  * (tets with part[t] == p, part [T] >= 0): the basis functions touching p,

@@ -197,27 +197,26 @@ __global__ void __launch_bounds__(kUpdBlock) k_cg_update_agg(int nagg, int npart
 
 }  // namespace
 
-// Aggregation from the rest positions and the current mesh pattern.
-ms_status build_aggregates(ms_ctx* c) {
-  auto& G = c->agg;
-  if (G.built) return MS_OK;
-  const int64_t n = c->n;
-  const Pattern& P = c->pat;
-  if (n <= 0 || int64_t(P.h_row_ptr.size()) != n + 1) return fail(c, MS_E_ORDER, "upload a mesh first");
-  if (P.nslots >= int64_t(1) << 31) return fail(c, MS_E_ARG, "too many block slots for the aggregate smoother");
-  const double* X = c->h_rest.data();
+// Vertex aggregates of a mesh: rest positions X [n][3] binned into cubes of
+// twice the shortest edge of the vertex graph (CSR row_ptr / col, self
+// entries allowed), the bins offset by half an edge so that a regular grid
+// falls into 2 x 2 x 2 vertices; bins in (z, y, x) order, each split in
+// vertex order into groups of at most kAggV.  vert receives kAggV entries
+// per aggregate (vertex ids, -1 padding).
+void aggregate_vertices(int64_t n, const double* X, const int32_t* row_ptr, const int32_t* col,
+                        std::vector<int32_t>& vert) {
   double hmin = INFINITY, lo[3] = {INFINITY, INFINITY, INFINITY};
   for (int64_t v = 0; v < n; ++v) {
     for (int q = 0; q < 3; ++q) lo[q] = std::min(lo[q], X[3 * v + q]);
-    for (int32_t e = P.h_row_ptr[v]; e < P.h_row_ptr[v + 1]; ++e) {
-      const int64_t j = P.h_col[e];
+    for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+      const int64_t j = col[e];
       if (j == v) continue;
       const double dx = X[3 * j] - X[3 * v], dy = X[3 * j + 1] - X[3 * v + 1], dz = X[3 * j + 2] - X[3 * v + 2];
       const double l = std::sqrt(dx * dx + dy * dy + dz * dz);
       if (l > 0.0) hmin = std::min(hmin, l);
     }
   }
-  if (!std::isfinite(hmin)) hmin = 1.0;  // no edges of positive length: one bin per vertex run
+  if (!std::isfinite(hmin)) hmin = 1.0;  // no edge of positive length
   std::vector<std::array<int64_t, 3>> key(n);
   for (int64_t v = 0; v < n; ++v)
     for (int q = 0; q < 3; ++q) key[v][q] = int64_t(std::floor((X[3 * v + q] - lo[q]) / (2.0 * hmin) + 0.25));
@@ -229,7 +228,7 @@ ms_status build_aggregates(ms_ctx* c) {
     if (key[x][0] != key[y][0]) return key[x][0] < key[y][0];
     return x < y;
   });
-  std::vector<int32_t> vert;
+  vert.clear();
   for (int64_t b = 0; b < n;) {
     int64_t e = b;
     while (e < n && key[order[e]] == key[order[b]]) ++e;
@@ -237,6 +236,19 @@ ms_status build_aggregates(ms_ctx* c) {
       for (int q = 0; q < kAggV; ++q) vert.push_back(g + q < e ? int32_t(order[g + q]) : -1);
     b = e;
   }
+}
+
+// Aggregates of the context's mesh with the block slots of the current
+// pattern, uploaded; inverse storage allocated.
+ms_status build_aggregates(ms_ctx* c) {
+  auto& G = c->agg;
+  if (G.built) return MS_OK;
+  const int64_t n = c->n;
+  const Pattern& P = c->pat;
+  if (n <= 0 || int64_t(P.h_row_ptr.size()) != n + 1) return fail(c, MS_E_ORDER, "upload a mesh first");
+  if (P.nslots >= int64_t(1) << 31) return fail(c, MS_E_ARG, "too many block slots for the aggregate smoother");
+  std::vector<int32_t> vert;
+  aggregate_vertices(n, c->h_rest.data(), P.h_row_ptr.data(), P.h_col.data(), vert);
   const int nagg = int(vert.size() / kAggV);
   std::vector<int32_t> slot(size_t(nagg) * kAggV * kAggV, -1);
   for (int a = 0; a < nagg; ++a)
@@ -298,3 +310,20 @@ void launch_cg_update_agg(ms_ctx* c, int prec, int parity) {
 }
 
 }  // namespace ms
+
+extern "C" ms_status ms_aggregates_compute(int64_t n, const double* rest_xyz, const int32_t* row_ptr,
+                                           const int32_t* col, int64_t cap, int32_t* vert, int64_t* n_agg) {
+  if (n < 1 || !rest_xyz || !row_ptr || !col || !n_agg || cap < 0 || (cap > 0 && !vert)) return MS_E_ARG;
+  for (int64_t v = 0; v < n; ++v) {
+    if (row_ptr[v + 1] < row_ptr[v]) return MS_E_MESH;
+    for (int q = 0; q < 3; ++q)
+      if (!std::isfinite(rest_xyz[3 * v + q])) return MS_E_NONFINITE;
+  }
+  for (int64_t e = 0; e < row_ptr[n]; ++e)
+    if (col[e] < 0 || col[e] >= n) return MS_E_MESH;
+  std::vector<int32_t> out;
+  ms::aggregate_vertices(n, rest_xyz, row_ptr, col, out);
+  *n_agg = int64_t(out.size()) / ms::kAggV;
+  if (cap > 0) std::copy(out.begin(), out.begin() + std::min<int64_t>(cap, int64_t(out.size())), vert);
+  return MS_OK;
+}

@@ -116,6 +116,7 @@ def lib():
             "ms_energy_difference": [vp, dp, dp, d, d, dp],
             "ms_basis_compute": [i64, dp, i64, ip, dp, i64, ip, C.POINTER(ms_basis_params), C.POINTER(C.c_void_p)],
             "ms_basis_get": [vp, C.POINTER(i32), C.POINTER(i64), dp, ip, ip, dp, ip],
+            "ms_aggregates_compute": [i64, dp, ip, ip, i64, ip, C.POINTER(i64)],
             "ms_cubature_compute": [i64, dp, i64, ip, ip, i32, ip, ip, dp, d, i32, i32, i32, C.c_uint64, i32,
                                     C.POINTER(C.c_void_p)],
             "ms_cubature_get": [vp, C.POINTER(i64), ip, dp, C.POINTER(d)],
@@ -415,6 +416,22 @@ class Context:
         A = np.empty((r, r))
         self._check(self.L.ms_get_coarse_matrix(self.h, _ptr(A)))
         return A
+
+
+def ms_aggregates_compute(rest, row_ptr, col):
+    """Host-only vertex aggregates of the aggregate smoother: int32 [nagg][8]
+    (vertex ids, -1 padding)."""
+    L = lib()
+    rest, row_ptr, col = _f64(rest), _i32(row_ptr), _i32(col)
+    n = C.c_int64()
+    code = L.ms_aggregates_compute(len(rest), _ptr(rest), _ptr(row_ptr), _ptr(col), 0, None, C.byref(n))
+    if code != MS_OK:
+        raise MSError(code, "ms_aggregates_compute")
+    out = np.empty((n.value, 8), dtype=np.int32)
+    code = L.ms_aggregates_compute(len(rest), _ptr(rest), _ptr(row_ptr), _ptr(col), out.size, _ptr(out), C.byref(n))
+    if code != MS_OK:
+        raise MSError(code, "ms_aggregates_compute")
+    return out
 
 
 def ms_basis_compute(rest, tets, E, dbc=(), params=None, **kw):
