@@ -54,7 +54,7 @@ def parse():
                     help="implicit Euler or BDF2 (first step implicit Euler) for every form in the run")
     ap.add_argument("--pc", choices=["jacobi", "two_level", "additive", "vcycle"], default="additive")
     ap.add_argument("--handles", type=int, default=None,
-                    help="basis handles (176 on the benchmarked block, else 192)")
+                    help="basis handles (144 on the benchmarked block, else 192)")
     ap.add_argument("--oversample", type=float, default=1.0, help="k-means++ seed oversampling of the basis build")
     ap.add_argument("--rigid", type=float, default=1e3,
                     help="basis weights constant on connected sets of tets with E >= RIGID x min E (0: off; "
@@ -123,7 +123,7 @@ def parse():
     if a.endgame_ratio is None:
         a.endgame_ratio = 1e-1 if block else 1e-3
     if a.handles is None:
-        a.handles = 176 if block else 192
+        a.handles = 144 if block else 192
     if a.endgame_fp64 is None:
         a.endgame_fp64 = 0 if block else 1
     if a.smoother is None:

@@ -2,7 +2,7 @@
 against the CPU oracle: the heterogeneous block at 32^3 (35,937 vertices,
 196,608 tets, 20 inclusions at 1e10 Pa in 1e5 Pa), mixed precision (FP32
 Hessian values, FP64 vectors, gradients and line search), the additive
-two-level preconditioner on a 176-handle basis with constant weights on
+two-level preconditioner on a 144-handle basis with constant weights on
 the inclusions and 2x2x2 vertex aggregates as its block part,
 Eisenstat-Walker forcing in [3e-2, 0.1], the exact
 (unprojected) Hessian from ||d|| <= 1e-1 ||x - x^t|| and movement-triggered
@@ -32,7 +32,7 @@ def test_bench_form_step_at_full_size():
     s = scenes.inclusion_block(32, seed=0, steps=3)
     c = ms.context_from_scene(dev, s)
     t0 = time.time()
-    c.ms_build_basis(n_handles=176, oversample=1.0, rigid_contrast=1e3)
+    c.ms_build_basis(n_handles=144, oversample=1.0, rigid_contrast=1e3)
     say("basis", c.ms_get_basis()["m"], "handles in", round(time.time() - t0, 1), "s")
     params = ms.solver_defaults(precision=ms.PREC_MIXED, preconditioner=ms.PC_TWO_LEVEL_ADDITIVE, forcing=1,
                                 pcg_eta_max=0.1, pcg_eta_min=3e-2, coarse_move=0.2, mixed_endgame_fp64=0, smoother=1,
