@@ -347,8 +347,8 @@ void ms_basis_free(ms_basis* b);
 
 /* Vertex aggregates of the aggregate block-Jacobi smoother (the `smoother`
  * = 1 solver option), host-only: the rule ms_step applies to a context's
- * mesh.  rest_xyz [n][3]; the vertex graph as CSR (row_ptr [n+1], col
- * [row_ptr[n]], entries 0..n-1, self entries allowed).  Positions are binned
+ * mesh.  rest_xyz [n][3]; the vertex graph as CSR (row_ptr [n+1] from 0,
+ * col [row_ptr[n]], entries 0..n-1, self entries allowed).  Positions are binned
  * into cubes of twice the graph's shortest edge, offset by half an edge (a
  * regular grid gives 2 x 2 x 2 vertices), bins ordered by (z, y, x) and
  * each split in vertex order into groups of at most 8.  *n_agg receives the

@@ -314,6 +314,7 @@ void launch_cg_update_agg(ms_ctx* c, int prec, int parity) {
 extern "C" ms_status ms_aggregates_compute(int64_t n, const double* rest_xyz, const int32_t* row_ptr,
                                            const int32_t* col, int64_t cap, int32_t* vert, int64_t* n_agg) {
   if (n < 1 || !rest_xyz || !row_ptr || !col || !n_agg || cap < 0 || (cap > 0 && !vert)) return MS_E_ARG;
+  if (row_ptr[0] != 0) return MS_E_MESH;
   for (int64_t v = 0; v < n; ++v) {
     if (row_ptr[v + 1] < row_ptr[v]) return MS_E_MESH;
     for (int q = 0; q < 3; ++q)

@@ -86,6 +86,11 @@ def test_rejects_malformed_input():
     with pytest.raises(ms.MSError) as e:
         ms.ms_aggregates_compute(rest, row_ptr, c2)
     assert e.value.code == ms.MS_E_MESH
+    r2 = row_ptr.copy()
+    r2[0] = 1
+    with pytest.raises(ms.MSError) as e:
+        ms.ms_aggregates_compute(rest, r2, col)
+    assert e.value.code == ms.MS_E_MESH
     with pytest.raises(ms.MSError) as e:
         ms.ms_aggregates_compute(np.zeros((0, 3)), np.zeros(1, np.int32), np.zeros(0, np.int32))
     assert e.value.code == ms.MS_E_ARG
