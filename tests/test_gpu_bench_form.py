@@ -36,7 +36,7 @@ def test_bench_form_step_at_full_size():
     say("basis", c.ms_get_basis()["m"], "handles in", round(time.time() - t0, 1), "s")
     params = ms.solver_defaults(precision=ms.PREC_MIXED, preconditioner=ms.PC_TWO_LEVEL_ADDITIVE, forcing=1,
                                 pcg_eta_max=0.1, pcg_eta_min=3e-2, coarse_move=0.2, mixed_endgame_fp64=0, smoother=1,
-                                endgame_ratio=1e-1)
+                                endgame_ratio=1e-1, max_newton=200)
     for k in (1, 2):
         c.ms_set_dirichlet(s["dirichlet"], s["dbc_targets"](k))
         c.ms_step(s["dt"], params)
@@ -68,7 +68,7 @@ def test_fp64_continuation_converges_at_full_size():
     dev = device()
     s = scenes.inclusion_block(32, seed=0, steps=5)
     form = dict(preconditioner=ms.PC_TWO_LEVEL_ADDITIVE, forcing=1, pcg_eta_max=0.1, pcg_eta_min=3e-2,
-                coarse_move=0.2, mixed_endgame_fp64=0, smoother=1, endgame_ratio=1e-1)
+                coarse_move=0.2, mixed_endgame_fp64=0, smoother=1, endgame_ratio=1e-1, max_newton=200)
     states, basis = {}, {}
     for prec in (ms.PREC_MIXED, ms.PREC_FP64):
         c = ms.context_from_scene(dev, s)
