@@ -82,9 +82,10 @@ def parse():
                          "default 3e-2 for the block, 1e-3 for the other workloads")
     ap.add_argument("--no-accuracy", action="store_true",
                     help="skip the per-step error check against tightly converged FP64 steps")
-    ap.add_argument("--coarse-move", type=float, default=0.2,
+    ap.add_argument("--coarse-move", type=float, default=None,
                     help="> 0: rebuild U^T H U once the iterate has moved by this fraction of the step's "
-                         "displacement since the last rebuild (replaces --coarse-every)")
+                         "displacement since the last rebuild (replaces --coarse-every; 0.8 on the benchmarked "
+                         "block, else 0.2)")
     ap.add_argument("--workload", choices=["block32", "batch64", "learned", "spmv_sweep", "paper", "cubature"],
                     default="block32",
                     help="block32: the heterogeneous block (default); batch64: 64 uneven scenes stepped together; "
@@ -131,6 +132,8 @@ def parse():
         a.endgame_fp64 = 0 if block else 1
     if a.smoother is None:
         a.smoother = 1 if block else 0
+    if a.coarse_move is None:
+        a.coarse_move = 0.8 if block else 0.2
     return a
 
 

@@ -4,9 +4,9 @@ against the CPU oracle: the heterogeneous block at 32^3 (35,937 vertices,
 Hessian values, FP64 vectors, gradients and line search), the additive
 two-level preconditioner on a 144-handle basis with constant weights on
 the inclusions and 2x2x2 vertex aggregates as its block part,
-Eisenstat-Walker forcing in [3e-2, 0.1], the exact
-(unprojected) Hessian from ||d|| <= 1e-1 ||x - x^t|| and movement-triggered
-coarse rebuilds.
+Eisenstat-Walker forcing in [3e-2, 0.1], the exact (unprojected) Hessian
+from ||d|| <= 1e-1 ||x - x^t||, coarse rebuilds after a movement of
+0.8 ||x - x^t|| and at most 200 Newton iterations.
 
 The oracle's sparse direct solve costs about a minute per Newton iteration
 at this size, so it starts from the GPU's result (the minimiser does not
@@ -35,7 +35,7 @@ def test_bench_form_step_at_full_size():
     c.ms_build_basis(n_handles=144, oversample=1.0, rigid_contrast=1e3)
     say("basis", c.ms_get_basis()["m"], "handles in", round(time.time() - t0, 1), "s")
     params = ms.solver_defaults(precision=ms.PREC_MIXED, preconditioner=ms.PC_TWO_LEVEL_ADDITIVE, forcing=1,
-                                pcg_eta_max=0.1, pcg_eta_min=3e-2, coarse_move=0.2, mixed_endgame_fp64=0, smoother=1,
+                                pcg_eta_max=0.1, pcg_eta_min=3e-2, coarse_move=0.8, mixed_endgame_fp64=0, smoother=1,
                                 endgame_ratio=1e-1, max_newton=200)
     for k in (1, 2):
         c.ms_set_dirichlet(s["dirichlet"], s["dbc_targets"](k))
@@ -68,7 +68,7 @@ def test_fp64_continuation_converges_at_full_size():
     dev = device()
     s = scenes.inclusion_block(32, seed=0, steps=5)
     form = dict(preconditioner=ms.PC_TWO_LEVEL_ADDITIVE, forcing=1, pcg_eta_max=0.1, pcg_eta_min=3e-2,
-                coarse_move=0.2, mixed_endgame_fp64=0, smoother=1, endgame_ratio=1e-1, max_newton=200)
+                coarse_move=0.8, mixed_endgame_fp64=0, smoother=1, endgame_ratio=1e-1, max_newton=200)
     states, basis = {}, {}
     for prec in (ms.PREC_MIXED, ms.PREC_FP64):
         c = ms.context_from_scene(dev, s)
